@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark: transitive-closure time-to-fixpoint and effective TOPS at N = 8192.
+
+Workload (one "step"): the int8 repeated-squaring closure R = min1(A + R R)
+run to its fixpoint on each of nine Erdos-Renyi graphs with N = 8192
+constants, edge probability p in {1/N, 4/N, 0.01} and seeds 0, 1, 2 -- ingest,
+every squaring step with its fused threshold and counter, the device-side
+convergence test and the emit of the 0/1 model.  Inputs are resident in HBM
+before the timed region starts.
+
+value = effective TOPS = sum over graphs of 2 N^3 x (products executed,
+including the one that confirms the fixpoint) / wall time of the step.
+
+Also reported, each measured once outside the timed steps: per-graph
+time-to-fixpoint, the plain FP32 iteration and the fp64 epsilon solve on the
+same inputs (with their threshold errors against the int8 model), the bf16
+and fp8 variants, same generation at N = 4096 on random forests, the
+dominant kernel's roofline figures (HIP events inside the library, on the
+launch stream) and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TC time-to-fixpoint & eff. TOPS at N=8192; batched req/s with p50/p99 latency"
+N = 8192
+PROBS = (("1/N", 1.0 / N), ("4/N", 4.0 / N), ("0.01", 0.01))
+SEEDS = (0, 1, 2)
+INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 MFMA, 5.0 POP/s
+FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true", help="skip the once-measured variants")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import dlgen
+    import paper_1608_00139_amd as dl
+
+    torch.cuda.set_device(0)
+    ctx = dl.Context(0)
+    log(f"generating {len(PROBS) * len(SEEDS)} ER graphs, N={N}")
+    graphs = []
+    for pname, p in PROBS:
+        for seed in SEEDS:
+            e = dlgen.er_edges(N, p, seed)
+            a = dlgen.to_dense(N, e)
+            graphs.append({"p": pname, "seed": seed, "edges": int(len(e)), "host": a,
+                           "dev": torch.from_numpy(a).cuda(),
+                           "sha256": dlgen.edges_sha256(N, e)})
+    outs = [torch.empty((N, N), dtype=torch.uint8, device="cuda") for _ in graphs]
+    torch.cuda.synchronize()
+
+    def step():
+        its = []
+        for g, out in zip(graphs, outs):
+            _, it = dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=out, ctx=ctx)
+            its.append(it)
+        return its
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.kernel_stats(0, reset=True)
+    ctx.set_timing(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = None
+    for _ in range(args.steps):
+        iters = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    launches, kms = ctx.kernel_stats(0, reset=True)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    products = [it - 1 for it in iters]  # step 1 is the input itself, no product
+    ops_per_step = sum(2.0 * N ** 3 * k for k in products)
+    value = ops_per_step / (ms_per_step * 1e-3) / 1e12
+    avg_kernel_ms = kms / max(launches, 1)
+    achieved = 2.0 * N ** 3 / (avg_kernel_ms * 1e-3) / 1e12
+
+    # per-graph time-to-fixpoint (median of a few runs each)
+    per_graph = []
+    for g, out in zip(graphs, outs):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            _, it = dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=out, ctx=ctx)
+            ts.append(time.perf_counter() - a0)
+        t = statistics.median(ts)
+        per_graph.append({"p": g["p"], "seed": g["seed"], "edges": g["edges"], "iters": it,
+                          "time_to_fixpoint_ms": round(t * 1e3, 3),
+                          "eff_tops": round(2.0 * N ** 3 * (it - 1) / t / 1e12, 1),
+                          "closure_density": round(float(out.sum().item()) / N ** 2, 6)})
+
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(dl, ctx, graphs, outs, np, torch)
+
+    cpu = None if args.no_cpu else cpu_baseline(graphs, iters)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "TOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic (seeded ER graphs, dense 0/1 int8 in HBM)",
+        "config": {"workload": "TC to fixpoint, int8 repeated squaring, N=8192 ER p in {1/N,4/N,0.01} x seeds {0,1,2}",
+                   "n": N, "graphs": len(graphs), "iters": iters, "products_per_step": sum(products)},
+        "frac_of_int8_peak": round(value / INT8_PEAK_TOPS, 4),
+        "roofline": {"bound": "mfma", "kernel": "k_nt_step<256,256,128,64,64,OpI8>",
+                     "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                     "launches": launches, "avg_kernel_ms": round(avg_kernel_ms, 4),
+                     "ops_per_launch": 2.0 * N ** 3},
+        "per_graph": per_graph,
+        "extras": extras,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def run_extras(dl, ctx, graphs, outs, np, torch):
+    """Variants of the hot path, each timed once on the same resident inputs."""
+    res = {}
+    seed0 = [i for i, g in enumerate(graphs) if g["seed"] == 0]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    # plain FP32 fixpoint (the "Iteration" baseline) and speed-up of int8 squaring
+    plain = []
+    for i in seed0:
+        g = graphs[i]
+        log(f"fp32 plain p={g['p']}")
+        tmp = torch.empty_like(outs[i])
+        (_, it), t = timed(lambda: dl.dl_tc(g["dev"], method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=tmp, ctx=ctx))
+        (_, it8), t8 = timed(lambda: dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=outs[i], ctx=ctx))
+        mism = int((tmp != outs[i]).sum().item())
+        plain.append({"p": g["p"], "iters": it, "time_ms": round(t * 1e3, 2),
+                      "eff_tflops": round(2.0 * N ** 3 * (it - 1) / t / 1e12, 1),
+                      "int8_square_ms": round(t8 * 1e3, 2), "speedup_int8_square": round(t / t8, 1),
+                      "model_mismatches_vs_int8": mism})
+    res["tc_plain_fp32"] = plain
+
+    # bf16 / fp8 squaring variants
+    var = []
+    for prec_name, prec in (("bf16", dl.DL_BF16), ("fp8", dl.DL_FP8)):
+        for i in seed0:
+            g = graphs[i]
+            log(f"{prec_name} square p={g['p']}")
+            tmp = torch.empty_like(outs[i])
+            dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=prec, out=tmp, ctx=ctx)
+            (_, it), t = timed(lambda: dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=prec, out=tmp, ctx=ctx))
+            var.append({"prec": prec_name, "p": g["p"], "iters": it, "time_ms": round(t * 1e3, 2),
+                        "eff_tops": round(2.0 * N ** 3 * (it - 1) / t / 1e12, 1),
+                        "model_mismatches_vs_int8": int((tmp != outs[i]).sum().item())})
+    res["tc_square_variants"] = var
+
+    # fp64 epsilon solve, eps = 0.5 / (max row sum + 1)
+    eps_rows = []
+    for i in seed0:
+        g = graphs[i]
+        eps = 0.5 / (1.0 + float(g["host"].sum(axis=1).max()))
+        log(f"fp64 eps solve p={g['p']}")
+        tmp = torch.empty_like(outs[i])
+        ctx.kernel_stats(1, reset=True)
+        ctx.set_timing(True)
+        _, t = timed(lambda: dl.dl_solve_eps(g["dev"], eps, out=tmp, ctx=ctx))
+        ctx.set_timing(False)
+        nl, tms = ctx.kernel_stats(1, reset=True)
+        eps_rows.append({"p": g["p"], "eps": eps, "time_ms": round(t * 1e3, 2),
+                         "eff_tflops": round(8.0 / 3.0 * N ** 3 / t / 1e12, 2),
+                         "threshold_errors_vs_int8_model": int((tmp != outs[i]).sum().item()),
+                         "trailing_update_launches": nl, "trailing_update_ms": round(tms, 2)})
+    res["eps_solve_fp64"] = eps_rows
+
+    # same generation, N = 4096 random forests
+    import dlgen
+
+    sg = []
+    n = 4096
+    for seed in SEEDS:
+        p = torch.from_numpy(dlgen.to_dense(n, dlgen.forest_edges(n, seed))).cuda()
+        s = torch.empty_like(p)
+        dl.dl_sg(p, prec=dl.DL_I8, out=s, ctx=ctx)
+        (_, it), t = timed(lambda: dl.dl_sg(p, prec=dl.DL_I8, out=s, ctx=ctx))
+        sg.append({"n": n, "seed": seed, "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 2),
+                   "eff_tops": round(2 * 2.0 * n ** 3 * (it - 1) / t / 1e12, 1),
+                   "model_size": int(s.sum().item())})
+    res["sg_n4096"] = sg
+    return res
+
+
+def cpu_baseline(graphs, iters):
+    """The CPU oracle (semi-naive bitset evaluation) on the host's cores.
+
+    Sample: the three seed-0 graphs of the workload (one per edge
+    probability), timed end to end in the oracle's C code.  Its rate is put
+    in the metric's unit by crediting it with the same algorithmic work the
+    GPU schedule performs on those graphs (2 N^3 per squaring product).
+    """
+    import oracle
+
+    sample = [(i, g) for i, g in enumerate(graphs) if g["seed"] == 0]
+    t_total = 0.0
+    work = 0.0
+    per = []
+    for i, g in sample:
+        log(f"cpu oracle p={g['p']}")
+        t0 = time.perf_counter()
+        _, _, it, _ = oracle.tc_seminaive(g["host"])
+        dt = time.perf_counter() - t0
+        t_total += dt
+        work += 2.0 * N ** 3 * (iters[i] - 1)
+        per.append({"p": g["p"], "seconds": round(dt, 3), "plain_rounds": it})
+    return {"value": round(work / t_total / 1e12, 3), "unit": "TOPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "semi-naive TC on the three seed-0 graphs (p = 1/N, 4/N, 0.01), N=8192",
+            "seconds": round(t_total, 3), "per_graph": per}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,153 @@
+/*
+ * dl.h -- C ABI of the MI355X (gfx950) library for linear-algebraic Datalog
+ * evaluation (T. Sato, "A Linear Algebraic Approach to Datalog Evaluation").
+ *
+ * The library computes least Herbrand models of two linear, binary-predicate
+ * programs as fixpoints of thresholded dense N x N matrix products:
+ *   - transitive closure   R = min1(R1 + R1 R)           (Sec. 3, program DB1)
+ *     and its repeated-squaring form R = min1(R1 + R R)  (Sec. 8)
+ *   - same generation      S = min1(I + R1 S R1^T)       (Sec. 7.2)
+ *   - the purely linear form of Sec. 4, Proposition 1:
+ *     X = (I - eps R1)^-1 eps R1, thresholded at > 0      (Theorem 1)
+ *
+ * Matrix conventions (all entry points):
+ *   - Every matrix is n x n, row-major, 0-based: element (i, j) at p[i*ld + j],
+ *     ld >= n.  (R)_ij = 1 iff r(e_i, e_j) holds: row = first argument
+ *     (adjacency encoding, Sec. 2).
+ *   - Relation inputs are uint8 bytes; 0 is false and any nonzero byte is
+ *     true.  Model outputs are exactly 0 or 1.
+ *   - All matrix pointers are DEVICE pointers owned by the caller.  The
+ *     library never frees or retains them past the call.  Inputs are read
+ *     only; an output must not overlap an input.
+ *   - min1(x) = 1 if x >= 1 else x (Sec. 2).  On the non-negative integer
+ *     counts these products produce it is the test x != 0.
+ *   - `iters` (host pointer) receives the number of applications of the
+ *     update starting from the empty relation R^(0) = 0, including the first
+ *     application that changes nothing.  For the plain series this is D + 1,
+ *     D the longest shortest path; for repeated squaring 2 + ceil(log2 D)
+ *     (1 when R1 is empty).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; calls that report `iters` block until it is known.
+ *
+ * Errors: every call returns a dl_status.  DL_EINVAL for bad arguments
+ * (n < 0, NULL pointer with n > 0, ld < n, overlapping input/output, eps out
+ * of range, unknown enum); DL_ENOMEM when the workspace needed exceeds the
+ * context's budget or hipMalloc fails; DL_EHIP for a HIP runtime error;
+ * DL_ENOCONV if the step cap is hit (impossible for valid inputs);
+ * DL_EUNSUPPORTED for a method/precision pair that is not built.  After an
+ * error, dl_last_error() returns a message for the calling thread.  No C++
+ * exception crosses this interface.  n == 0 is valid and returns at once
+ * with iters = 1 (the empty model).
+ *
+ * Threading: a context may be used by one thread at a time; use one
+ * context per thread (or per stream) for concurrency.
+ */
+#ifndef DL_H_
+#define DL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DL_OK = 0,
+  DL_EINVAL = 1,
+  DL_ENOMEM = 2,
+  DL_EHIP = 3,
+  DL_ENOCONV = 4,
+  DL_EUNSUPPORTED = 5
+} dl_status;
+
+/* How the closure fixpoint is iterated. */
+typedef enum {
+  DL_TC_PLAIN = 0,  /* R^(k+1) = min1(R1 + R1 R^(k))         (Sec. 3, "Iteration", Sec. 7.1) */
+  DL_TC_SQUARE = 1  /* R^(k+1) = min1(R1 + R^(k) R^(k))      (non-linear program, Sec. 8)    */
+} dl_tc_method;
+
+/* Arithmetic of the products.  Operands are exactly 0/1 in every format, so
+ * all are exact: int8 with int32 accumulation, and fp32/bf16/fp8(e4m3) with
+ * fp32 accumulation while counts stay below 2^24. */
+typedef enum { DL_I8 = 0, DL_F32 = 1, DL_BF16 = 2, DL_FP8 = 3 } dl_prec;
+
+typedef struct dl_ctx dl_ctx;
+
+/* Create a context on HIP device `device`.  workspace_budget_bytes caps the
+ * device memory the context may allocate for its internal buffers (0 = no
+ * cap).  Workspace is allocated lazily by the first call that needs it and
+ * reused by later calls. */
+int dl_create(dl_ctx** ctx, int device, size_t workspace_budget_bytes);
+int dl_destroy(dl_ctx* ctx);
+
+/* Transitive closure of R1 = A (Sec. 3, Theorem 1 gives the same model).
+ *   n      number of constants
+ *   A      device uint8 [n x lda], nonzero = r1(e_i, e_j)
+ *   R      device uint8 [n x ldr], receives the 0/1 least model of r2
+ *   method dl_tc_method, prec dl_prec
+ *   iters  host int32, see above. */
+int dl_tc(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
+          int method, int prec, int32_t* iters, void* stream);
+
+/* As dl_tc, but stops after at most max_steps applications (max_steps >= 0)
+ * and reports the per-step model sizes.  R receives the last iterate
+ * computed, R^(min(max_steps, iters)).  ones (host int64, length
+ * max_steps + 1, or NULL) receives ones[k] = number of true entries of
+ * R^(k) for k = 0 .. *steps.  *steps = number of iterates computed;
+ * *converged = 1 if the fixpoint was confirmed within max_steps. */
+int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
+                int method, int prec, int32_t max_steps, int64_t* ones, int32_t* steps,
+                int32_t* converged, void* stream);
+
+/* Same generation (Sec. 7.2): least S with S = min1(I + P S P^T), where P is
+ * the r1 relation (device uint8 [n x ldp]) and I encodes diag(x, x) for
+ * every constant.  Each step runs two products, T = min1(P S) and
+ * S' = min1(I + T P^T); thresholding the intermediate keeps the zero
+ * pattern of P S P^T.  prec: DL_I8, DL_F32, DL_BF16 or DL_FP8. */
+int dl_sg(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds,
+          int prec, int32_t* iters, void* stream);
+
+/* Step-capped variant of dl_sg; arguments as in dl_tc_steps. */
+int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds,
+                int prec, int32_t max_steps, int64_t* ones, int32_t* steps, int32_t* converged,
+                void* stream);
+
+/* Linear epsilon form (Sec. 4, Proposition 1 and Theorem 1): solves
+ * (I - eps A) X = eps A in fp64 by LU factorisation without pivoting and
+ * two triangular solves, then writes R = [X > 0].
+ *   eps  must satisfy 0 < eps <= 1 / (1 + ||A||_inf), ||A||_inf = max row
+ *        sum of the 0/1 matrix (Lemma 1); otherwise DL_EINVAL.
+ *   X    optional device double [n x ldx] receiving the real solution
+ *        (NULL to skip).
+ *   iters is set to 0: the solve is direct, no fixpoint iteration. */
+int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double eps, uint8_t* R,
+                 int64_t ldr, double* X, int64_t ldx, int32_t* iters, void* stream);
+
+/* Largest eps that Lemma 1 allows for A: 1 / (1 + max row sum).  Computed on
+ * the device; host double out. */
+int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* eps_max,
+                 void* stream);
+
+/* Kernel timing.  When enabled, the library brackets each launch of its
+ * product kernels with HIP events on the call's stream and accumulates, per
+ * kernel class, the number of launches that did work and their total
+ * duration.  Classes: 0 = boolean product step (all precisions), 1 = fp64
+ * trailing update of the epsilon solve, 2 = all other kernels. */
+int dl_set_timing(dl_ctx* ctx, int enable);
+int dl_kernel_stats(dl_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms,
+                    int reset);
+
+/* Padded size Np the library uses for n in this mode (multiple of its tile);
+ * lets callers size budgets.  kind: 0 = closure, 1 = same generation,
+ * 2 = epsilon solve. */
+int64_t dl_padded_size(int64_t n, int kind, int prec);
+
+const char* dl_status_str(int status);
+const char* dl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DL_H_ */

@@ -1,0 +1,251 @@
+"""Python binding of libdl.so, the gfx950 library for linear-algebraic Datalog
+evaluation (least models of transitive closure, same generation and the
+epsilon-scaled linear form, Sato's method).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+torch supplies device memory and the stream.  The functions keep the C names
+(``dl_tc``, ``dl_sg``, ``dl_solve_eps`` ...) and take uint8 CUDA/HIP tensors.
+
+The library must be built beforehand (``python -m paper_1608_00139_amd.build``
+or ``__graft_entry__.build()``); importing this module never compiles and
+never falls back to another implementation: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8",
+    "DLError", "Context", "lib_path", "load",
+    "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound",
+    "dl_padded_size",
+]
+
+DL_TC_PLAIN, DL_TC_SQUARE = 0, 1
+DL_I8, DL_F32, DL_BF16, DL_FP8 = 0, 1, 2, 3
+PRECISIONS = {"i8": DL_I8, "f32": DL_F32, "bf16": DL_BF16, "fp8": DL_FP8}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libdl.so")
+
+
+class DLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def load() -> ctypes.CDLL:
+    """Load libdl.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1608_00139_amd.build`")
+    lib = ctypes.CDLL(path)
+    i64, i32, vp, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "dl_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t], ctypes.c_int),
+        "dl_destroy": ([vp], ctypes.c_int),
+        "dl_tc": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, pi32, vp], ctypes.c_int),
+        "dl_tc_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, pi64, pi32, pi32, vp],
+                        ctypes.c_int),
+        "dl_sg": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, pi32, vp], ctypes.c_int),
+        "dl_sg_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, pi64, pi32, pi32, vp], ctypes.c_int),
+        "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
+        "dl_eps_bound": ([vp, i64, vp, i64, ctypes.POINTER(dbl), vp], ctypes.c_int),
+        "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "dl_kernel_stats": ([vp, ctypes.c_int, pi64, ctypes.POINTER(dbl), ctypes.c_int], ctypes.c_int),
+        "dl_padded_size": ([i64, ctypes.c_int, ctypes.c_int], i64),
+        "dl_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "dl_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        lib = load()
+        raise DLError(rc, f"{lib.dl_status_str(rc).decode()} -- {lib.dl_last_error().decode()}")
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mat(t: torch.Tensor, name: str, dtype=torch.uint8) -> tuple[int, int]:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be square")
+    if t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < t.shape[1]):
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    return t.shape[0], max(t.stride(0), t.shape[1]) if t.shape[0] > 0 else 1
+
+
+class Context:
+    """Owns a dl_ctx (workspace, counters) on one device."""
+
+    def __init__(self, device: int | None = None, workspace_budget: int = 0):
+        lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        self._h = ctypes.c_void_p()
+        _check(lib.dl_create(ctypes.byref(self._h), device, workspace_budget))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise RuntimeError("context destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            load().dl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool) -> None:
+        _check(load().dl_set_timing(self.handle, int(bool(on))))
+
+    def kernel_stats(self, kernel_class: int, reset: bool = False) -> tuple[int, float]:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(load().dl_kernel_stats(self.handle, kernel_class, ctypes.byref(n), ctypes.byref(ms), int(reset)))
+        return int(n.value), float(ms.value)
+
+
+_DEFAULT: dict[int, Context] = {}
+
+
+def _ctx(ctx: Context | None) -> Context:
+    if ctx is not None:
+        return ctx
+    dev = torch.cuda.current_device()
+    if dev not in _DEFAULT:
+        _DEFAULT[dev] = Context(dev)
+    return _DEFAULT[dev]
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def dl_tc(A: torch.Tensor, method: int = DL_TC_SQUARE, prec=DL_I8, out: torch.Tensor | None = None,
+          ctx: Context | None = None, stream=None) -> tuple[torch.Tensor, int]:
+    """Transitive closure of A (uint8 n x n on the device): (R, iters)."""
+    n, lda = _mat(A, "A")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=A.device)
+    _, ldr = _mat(R, "R")
+    it = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_tc(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()), ldr,
+                        int(method), _prec(prec), ctypes.byref(it), _stream_ptr(stream)))
+    return R, int(it.value)
+
+
+@dataclass
+class StepResult:
+    R: torch.Tensor
+    ones: list
+    steps: int
+    converged: bool
+
+
+def dl_tc_steps(A: torch.Tensor, max_steps: int, method: int = DL_TC_SQUARE, prec=DL_I8,
+                out: torch.Tensor | None = None, ctx: Context | None = None, stream=None) -> StepResult:
+    n, lda = _mat(A, "A")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=A.device)
+    _, ldr = _mat(R, "R")
+    ones = (ctypes.c_int64 * (max_steps + 1))()
+    steps = ctypes.c_int32()
+    conv = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_tc_steps(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()),
+                              ldr, int(method), _prec(prec), int(max_steps), ones, ctypes.byref(steps),
+                              ctypes.byref(conv), _stream_ptr(stream)))
+    return StepResult(R, [int(ones[k]) for k in range(steps.value + 1)], int(steps.value), bool(conv.value))
+
+
+def dl_sg(P: torch.Tensor, prec=DL_I8, out: torch.Tensor | None = None, ctx: Context | None = None,
+          stream=None) -> tuple[torch.Tensor, int]:
+    """Same-generation model of the parent relation P: (S, iters)."""
+    n, ldp = _mat(P, "P")
+    S = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=P.device)
+    _, lds = _mat(S, "S")
+    it = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_sg(c.handle, n, ctypes.c_void_p(P.data_ptr()), ldp, ctypes.c_void_p(S.data_ptr()), lds,
+                        _prec(prec), ctypes.byref(it), _stream_ptr(stream)))
+    return S, int(it.value)
+
+
+def dl_sg_steps(P: torch.Tensor, max_steps: int, prec=DL_I8, out: torch.Tensor | None = None,
+                ctx: Context | None = None, stream=None) -> StepResult:
+    n, ldp = _mat(P, "P")
+    S = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=P.device)
+    _, lds = _mat(S, "S")
+    ones = (ctypes.c_int64 * (max_steps + 1))()
+    steps = ctypes.c_int32()
+    conv = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_sg_steps(c.handle, n, ctypes.c_void_p(P.data_ptr()), ldp, ctypes.c_void_p(S.data_ptr()),
+                              lds, _prec(prec), int(max_steps), ones, ctypes.byref(steps), ctypes.byref(conv),
+                              _stream_ptr(stream)))
+    return StepResult(S, [int(ones[k]) for k in range(steps.value + 1)], int(steps.value), bool(conv.value))
+
+
+def dl_eps_bound(A: torch.Tensor, ctx: Context | None = None, stream=None) -> float:
+    n, lda = _mat(A, "A")
+    out = ctypes.c_double()
+    c = _ctx(ctx)
+    _check(load().dl_eps_bound(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.byref(out),
+                               _stream_ptr(stream)))
+    return float(out.value)
+
+
+def dl_solve_eps(A: torch.Tensor, eps: float, want_x: bool = False, out: torch.Tensor | None = None,
+                 ctx: Context | None = None, stream=None):
+    """Epsilon form: returns (R, X or None); R = [(I - eps A)^-1 eps A > 0]."""
+    n, lda = _mat(A, "A")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=A.device)
+    _, ldr = _mat(R, "R")
+    X = torch.empty((n, n), dtype=torch.float64, device=A.device) if want_x else None
+    ldx = max(n, 1)
+    it = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_solve_eps(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, float(eps),
+                               ctypes.c_void_p(R.data_ptr()), ldr,
+                               ctypes.c_void_p(X.data_ptr()) if X is not None else None, ldx,
+                               ctypes.byref(it), _stream_ptr(stream)))
+    return R, X
+
+
+def dl_padded_size(n: int, kind: int, prec=DL_I8) -> int:
+    return int(load().dl_padded_size(n, kind, _prec(prec)))

@@ -1,0 +1,642 @@
+// bool_kernels.hip -- boolean fixpoint steps on gfx950 matrix cores.
+//
+// Every step of the three fixpoints is one "NT" product with a fused
+// threshold:   out(i, j) = [ add(i, j) + sum_k X(i, k) Y(j, k)  !=  0 ].
+// Both operands are row-major with K contiguous, the layout the MFMA
+// operand registers want.  The products of the paper map onto it as:
+//   closure, plain   R' = min1(A + A R)     run transposed: S = R^T,
+//                    S' = [A^T + S A^T]     X = S, Y = A, add = A^T
+//   closure, squared R' = min1(A + R R)     X = R, Y = R^T, add = A,
+//                                           and the epilogue also writes R'^T
+//   same generation  T  = [P S]             X = P, Y = S (S is symmetric)
+//                    S' = [I + T P^T]       X = T, Y = P, add = identity
+// min1 on the non-negative integer counts is the test "!= 0" (Sec. 2, 3).
+//
+// Operands hold exactly 0 or 1 in the chosen precision (int8, fp32, bf16 or
+// fp8 e4m3), so every product is exact: int32 accumulation, or fp32
+// accumulation of counts below 2^24.
+//
+// Kernel structure: one workgroup computes a BM x BN output tile, staging
+// BK-byte slices of its X and Y row panels through LDS with double
+// buffering.  LDS holds each slice as 16-byte chunks ordered
+// [chunk][row][16 B], so the 16 lanes that read one MFMA operand chunk read
+// 256 contiguous bytes (no bank conflicts).  The epilogue stages the 0/1
+// tile through LDS, ORs the addend with 16-byte loads, stores coalesced rows
+// (and, for squaring, the transposed tile), and counts the ones of the tile
+// with a wave reduction and a single atomic per workgroup.  A launch first
+// checks the device-side convergence state and returns at once if the
+// fixpoint was already reached, so chunks of steps can be enqueued ahead.
+#include "common.h"
+
+namespace dl {
+
+// ----------------------------------------------------------------- operand policies
+// CPL = 16-byte chunks per lane per MFMA; the four lane groups (lane / 16)
+// read consecutive chunk groups, and A and B use the same K assignment, so
+// the internal K order of the instruction does not matter.
+
+struct OpI8 {
+  static constexpr int kPrec = P_I8;
+  static constexpr int CPL = 1;
+  typedef v4i Acc;
+  __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(v4i, a[0]),
+                                                 __builtin_bit_cast(v4i, b[0]), c, 0, 0, 0);
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0; }
+};
+
+struct OpF32 {
+  static constexpr int kPrec = P_F32;
+  static constexpr int CPL = 1;
+  typedef v4f Acc;
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    // one chunk = 4 consecutive k; four K=4 instructions, lane group g
+    // supplies k = 4*chunk(g) + j in instruction j
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][j]),
+                                               __builtin_bit_cast(float, b[0][j]), c, 0, 0, 0);
+    return c;
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
+};
+
+struct OpBF16 {
+  static constexpr int kPrec = P_BF16;
+  static constexpr int CPL = 1;
+  typedef v4f Acc;
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[0]),
+                                                   __builtin_bit_cast(v8bf, b[0]), c, 0, 0, 0);
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
+};
+
+struct OpFP8 {
+  static constexpr int kPrec = P_FP8;
+  static constexpr int CPL = 2;
+  typedef v4f Acc;
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    v8i av, bv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { av[j] = a[0][j]; av[4 + j] = a[1][j]; bv[j] = b[0][j]; bv[4 + j] = b[1][j]; }
+    // formats 0/0 = fp8 e4m3 for both operands; E8M0 scale 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
+};
+
+// Store 16 boolean bytes (each 0 or 1) as 16 operand elements.
+template <int PREC>
+__device__ inline void store_bool16(uint8_t* dst, u32x4 b) {
+  if constexpr (PREC == P_I8) {
+    *(u32x4*)dst = b;
+  } else if constexpr (PREC == P_FP8) {
+    *(u32x4*)dst = b * 0x38u;  // bytes are 0/1: multiply puts 0x38 (1.0 in e4m3) in each set byte
+  } else if constexpr (PREC == P_BF16) {
+    u32x4 lo, hi;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      unsigned x = b[w];
+      lo[2 * w] = ((x & 1u) ? 0x3F80u : 0u) | (((x >> 8) & 1u) ? 0x3F800000u : 0u);
+      lo[2 * w + 1] = (((x >> 16) & 1u) ? 0x3F80u : 0u) | (((x >> 24) & 1u) ? 0x3F800000u : 0u);
+      unsigned y = b[2 + w];
+      hi[2 * w] = ((y & 1u) ? 0x3F80u : 0u) | (((y >> 8) & 1u) ? 0x3F800000u : 0u);
+      hi[2 * w + 1] = (((y >> 16) & 1u) ? 0x3F80u : 0u) | (((y >> 24) & 1u) ? 0x3F800000u : 0u);
+    }
+    ((u32x4*)dst)[0] = lo;
+    ((u32x4*)dst)[1] = hi;
+  } else {  // F32
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      unsigned x = b[w];
+      u32x4 v;
+      v[0] = (x & 1u) ? 0x3F800000u : 0u;
+      v[1] = ((x >> 8) & 1u) ? 0x3F800000u : 0u;
+      v[2] = ((x >> 16) & 1u) ? 0x3F800000u : 0u;
+      v[3] = ((x >> 24) & 1u) ? 0x3F800000u : 0u;
+      ((u32x4*)dst)[w] = v;
+    }
+  }
+}
+
+// Nonzero test of one operand element, returned as 0/1.
+template <int PREC>
+__device__ inline unsigned elem_nz(const uint8_t* p, int64_t idx) {
+  if constexpr (PREC == P_F32) return ((const unsigned*)p)[idx] != 0u ? 1u : 0u;
+  else if constexpr (PREC == P_BF16) return ((const unsigned short*)p)[idx] != 0 ? 1u : 0u;
+  else return p[idx] != 0 ? 1u : 0u;
+}
+
+__device__ inline int popc16(u32x4 v) {
+  return __builtin_popcount(v[0]) + __builtin_popcount(v[1]) + __builtin_popcount(v[2]) +
+         __builtin_popcount(v[3]);
+}
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block index -> output tile.  The hardware deals workgroups round-robin
+// over the 8 XCDs (block b on XCD b % 8).  Give each XCD a contiguous run of
+// logical tiles, then walk the logical tiles in groups of GM tile rows so
+// the workgroups resident on one XCD share row and column panels in its L2.
+__device__ inline void tile_coords(int b, int nblocks, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int x = b & 7, local = b >> 3;
+  const int logical = x * q + (x < r ? x : r) + local;
+  constexpr int GM = 8;
+  const int per_group = GM * tiles_n;
+  const int group = logical / per_group;
+  const int first_m = group * GM;
+  const int gm = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in = logical - group * per_group;
+  tm = first_m + in % gm;
+  tn = in / gm;
+}
+
+// Early exit shared by every step launch: returns true if this launch has
+// nothing to do because the fixpoint was reached before step p.step.
+__device__ inline bool step_is_done(const NTParams& p) {
+  if (!p.conv) return false;
+  const int c = *(volatile const int*)p.conv;
+  if (c < p.step) return true;
+  if (p.check && p.step >= 2) {
+    const unsigned long long a = *(volatile const unsigned long long*)(p.ones + ((p.step - 1) % kRing));
+    const unsigned long long b = *(volatile const unsigned long long*)(p.ones + ((p.step - 2) % kRing));
+    if (a == b) {
+      if (threadIdx.x == 0) atomicMin(p.conv, p.step - 1);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int BM, int BN, int WM, int WN, int KB, class Op>
+struct NTKernel {
+  static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
+  static constexpr int NWAVES = WAVES_M * WAVES_N;
+  static constexpr int NT = NWAVES * 64;
+  static constexpr int KC = KB / 16;                 // chunks per row per stage
+  static constexpr int FM = WM / 16, FN = WN / 16;   // 16x16 fragments per wave
+  static constexpr int CPL = Op::CPL;
+  static constexpr int KSTEP_CHUNKS = 4 * CPL;       // chunks consumed by one MFMA k-step
+  static constexpr int KSTEPS = KC / KSTEP_CHUNKS;
+  static constexpr int STAGE_CHUNKS = (BM + BN) * KC;
+  static constexpr int LOADS = STAGE_CHUNKS / NT;
+  static constexpr int EPAD = 16;
+  static constexpr int EST = BN + EPAD;              // epilogue LDS row stride (bytes)
+  static constexpr size_t OPER_BYTES = 2ull * STAGE_CHUNKS * 16;
+  static constexpr size_t EPI_BYTES = (size_t)BM * EST;
+  static constexpr size_t LDS_BYTES = OPER_BYTES > EPI_BYTES ? OPER_BYTES : EPI_BYTES;
+  static constexpr int ES = elem_bytes(Op::kPrec);
+  static_assert(KC % KSTEP_CHUNKS == 0, "stage must hold whole MFMA k-steps");
+  static_assert(STAGE_CHUNKS % NT == 0, "loads must divide evenly");
+  static_assert((BM * BN / 16) % NT == 0, "epilogue segments must divide evenly");
+};
+
+template <int BM, int BN, int WM, int WN, int KB, class Op>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+k_nt_step(NTParams p) {
+  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int64_t ldb = p.ld * K::ES;  // row pitch in bytes
+  const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
+  const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
+  const int nk = (int)(ldb / KB);
+
+  u32x4* lds = (u32x4*)smem;
+  // chunk q of a stage: rows [0, BM) of X then rows [0, BN) of Y;
+  // q -> (row, chunk) with 16-byte chunks of one row adjacent in global memory
+  u32x4 regs[K::LOADS];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < K::LOADS; ++i) {
+      const int q = tid + i * K::NT;
+      const int row = q / K::KC, c = q % K::KC;
+      const uint8_t* src = (row < BM) ? (Xg + (int64_t)row * ldb) : (Yg + (int64_t)(row - BM) * ldb);
+      regs[i] = *(const u32x4*)(src + (int64_t)kt * KB + c * 16);
+    }
+  };
+  auto sstore = [&](int buf) {
+    u32x4* base = lds + buf * K::STAGE_CHUNKS;
+#pragma unroll
+    for (int i = 0; i < K::LOADS; ++i) {
+      const int q = tid + i * K::NT;
+      const int row = q / K::KC, c = q % K::KC;
+      // X region: [KC][BM]; Y region after it: [KC][BN]
+      const int off = (row < BM) ? (c * BM + row) : (BM * K::KC + c * BN + (row - BM));
+      base[off] = regs[i];
+    }
+  };
+
+  typename Op::Acc acc[K::FM][K::FN];
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::zero();
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+
+  const int g = lane >> 4, r16 = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    const u32x4* xs = lds + cur * K::STAGE_CHUNKS;
+    const u32x4* ys = xs + BM * K::KC;
+#pragma unroll
+    for (int ks = 0; ks < K::KSTEPS; ++ks) {
+      u32x4 af[K::FM][K::CPL], bf[K::FN][K::CPL];
+#pragma unroll
+      for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+        for (int c = 0; c < K::CPL; ++c) {
+          const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
+          af[i][c] = xs[ch * BM + wm * WM + i * 16 + r16];
+        }
+#pragma unroll
+      for (int j = 0; j < K::FN; ++j)
+#pragma unroll
+        for (int c = 0; c < K::CPL; ++c) {
+          const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
+          bf[j][c] = ys[ch * BN + wn * WN + j * 16 + r16];
+        }
+#pragma unroll
+      for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::mma(af[i], bf[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: 0/1 tile in LDS, [BM][EST] bytes
+  uint8_t* et = smem;
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < K::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * WM + i * 16 + 4 * g + v;
+        const int c = wn * WN + j * 16 + r16;
+        et[r * K::EST + c] = Op::nz(acc[i][j], v) ? 1 : 0;
+      }
+  __syncthreads();
+
+  int cnt = 0;
+  constexpr int SEG_PER_ROW = BN / 16;
+  constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
+  uint8_t* outb = (uint8_t*)p.out;
+#pragma unroll 4
+  for (int i = 0; i < SEGS; ++i) {
+    const int q = tid + i * K::NT;
+    const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
+    u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
+    const int gr = row0 + r, gc = col0 + cs * 16;
+    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+      const int b = gr - gc;
+      v[b >> 2] |= 1u << (8 * (b & 3));
+    }
+    cnt += popc16(v);
+    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::ES, v);
+    if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
+  }
+
+  if (p.outT) {
+    __syncthreads();
+    constexpr int SEG_PER_COL = BM / 16;
+    constexpr int TSEGS = BN * SEG_PER_COL / K::NT;
+    uint8_t* outt = (uint8_t*)p.outT;
+#pragma unroll 2
+    for (int i = 0; i < TSEGS; ++i) {
+      const int q = tid + i * K::NT;
+      const int c = q / SEG_PER_COL, rs = q % SEG_PER_COL;
+      u32x4 v;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint8_t* e = et + (rs * 16 + 4 * w) * K::EST + c;
+        v[w] = (unsigned)e[0] | ((unsigned)e[K::EST] << 8) | ((unsigned)e[2 * K::EST] << 16) |
+               ((unsigned)e[3 * K::EST] << 24);
+      }
+      store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::ES, v);
+    }
+  }
+
+  if (p.count) {
+    __shared__ int red[K::NWAVES];
+    cnt = wave_sum(cnt);
+    if (lane == 0) red[wave] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long t = 0;
+#pragma unroll
+      for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
+      if (t) atomicAdd(p.ones + (p.step % kRing), t);
+    }
+  }
+}
+
+// ----------------------------------------------------------------- configurations
+// cfg 0: 256x256 tile, 8 waves of 128x64 (large n)
+// cfg 1: 128x128 tile, 4 waves of 64x64  (medium n)
+// cfg 2: 64x64 tile,   4 waves of 32x32  (small n)
+
+template <class Op, int BM, int BN, int WM, int WN, int KB>
+static hipError_t launch_cfg(const NTParams& p, hipStream_t s) {
+  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
+  const int grid = p.tiles_m * p.tiles_n;
+  hipLaunchKernelGGL((k_nt_step<BM, BN, WM, WN, KB, Op>), dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p);
+  return hipGetLastError();
+}
+
+template <class Op, int BM, int BN, int WM, int WN, int KB>
+static hipError_t set_lds_attr() {
+  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
+  return hipFuncSetAttribute((const void*)k_nt_step<BM, BN, WM, WN, KB, Op>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)K::LDS_BYTES);
+}
+
+template <class Op>
+static hipError_t launch_op(int cfg, const NTParams& p, hipStream_t s) {
+  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  switch (cfg) {
+    case 0:
+      if constexpr (Op::CPL == 2) return hipErrorInvalidValue;
+      else return launch_cfg<Op, 256, 256, 128, 64, KBIG>(p, s);
+    case 1: return launch_cfg<Op, 128, 128, 64, 64, KBIG>(p, s);
+    default: return launch_cfg<Op, 64, 64, 32, 32, KBIG>(p, s);
+  }
+}
+
+template <class Op>
+static hipError_t init_op() {
+  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  hipError_t e;
+  if constexpr (Op::CPL == 1)
+    if ((e = set_lds_attr<Op, 256, 256, 128, 64, KBIG>()) != hipSuccess) return e;
+  if ((e = set_lds_attr<Op, 128, 128, 64, 64, KBIG>()) != hipSuccess) return e;
+  return set_lds_attr<Op, 64, 64, 32, 32, KBIG>();
+}
+
+template <class Op>
+static TileCfg cfg_of(int cfg) {
+  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  switch (cfg) {
+    case 0:
+      if constexpr (Op::CPL == 1) { typedef NTKernel<256, 256, 128, 64, KBIG, Op> K; return {256, 256, KBIG, K::NT, K::LDS_BYTES}; }
+      else return {0, 0, 0, 0, 0};
+    case 1: { typedef NTKernel<128, 128, 64, 64, KBIG, Op> K; return {128, 128, KBIG, K::NT, K::LDS_BYTES}; }
+    default: { typedef NTKernel<64, 64, 32, 32, KBIG, Op> K; return {64, 64, KBIG, K::NT, K::LDS_BYTES}; }
+  }
+}
+
+hipError_t bool_kernels_init() {
+  hipError_t e;
+  if ((e = init_op<OpI8>()) != hipSuccess) return e;
+  if ((e = init_op<OpF32>()) != hipSuccess) return e;
+  if ((e = init_op<OpBF16>()) != hipSuccess) return e;
+  return init_op<OpFP8>();
+}
+
+TileCfg nt_config(int prec, int cfg) {
+  switch (prec) {
+    case P_I8: return cfg_of<OpI8>(cfg);
+    case P_F32: return cfg_of<OpF32>(cfg);
+    case P_BF16: return cfg_of<OpBF16>(cfg);
+    default: return cfg_of<OpFP8>(cfg);
+  }
+}
+
+hipError_t launch_nt_step(int prec, int cfg, const NTParams& p, hipStream_t s) {
+  switch (prec) {
+    case P_I8: return launch_op<OpI8>(cfg, p, s);
+    case P_F32: return launch_op<OpF32>(cfg, p, s);
+    case P_BF16: return launch_op<OpBF16>(cfg, p, s);
+    case P_FP8: return launch_op<OpFP8>(cfg, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Padding: every dimension is a multiple of 256, which every configuration's
+// tile and K slice divide.
+int64_t padded_size_for(int prec, int64_t n) {
+  (void)prec;
+  const int64_t q = 256;
+  return n <= 0 ? 0 : ((n + q - 1) / q) * q;
+}
+
+int choose_nt_config(int prec, int64_t np) {
+  // enough workgroups to cover the 256 CUs before choosing the large tile;
+  // fp8 operands (two chunks per lane) exceed the register file at 256x256
+  if (prec != P_FP8 && (np / 256) * (np / 256) >= 256) return 0;
+  if ((np / 128) * (np / 128) >= 128) return 1;
+  return 2;
+}
+
+// ----------------------------------------------------------------- ingest / emit
+// Ingest: normalise the caller's bytes (nonzero = true) into 0/1, zero-pad to
+// Np x Np, and write the layouts the chosen fixpoint needs: int8 A and A^T
+// (epilogue addends) and A, A^T in operand precision.  Counts the ones of A.
+template <int PREC>
+__global__ void __launch_bounds__(256)
+k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, int8_t* AT8,
+         uint8_t* Aop, uint8_t* ATop, unsigned long long* ones_slot) {
+  __shared__ uint8_t tile[64][64 + 16];
+  constexpr int ES = elem_bytes(PREC);
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int r = tid >> 2, c0 = (tid & 3) * 16;
+  const int gi = bi * 64 + r;
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (gi < n) {
+    const uint8_t* src = A + (int64_t)gi * lda + bj * 64 + c0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int gj = bj * 64 + c0 + t;
+      const unsigned b = (gj < n && src[t] != 0) ? 1u : 0u;
+      v[t >> 2] |= b << (8 * (t & 3));
+    }
+  }
+  *(u32x4*)&tile[r][c0] = v;
+  const int64_t off = (int64_t)gi * Np + bj * 64 + c0;
+  if (A8) *(u32x4*)(A8 + off) = v;
+  if (Aop) store_bool16<PREC>(Aop + off * ES, v);
+  int cnt = popc16(v);
+  __syncthreads();
+  if (AT8 || ATop) {
+    u32x4 t;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      t[w] = (unsigned)tile[c0 + 4 * w][r] | ((unsigned)tile[c0 + 4 * w + 1][r] << 8) |
+             ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
+    const int64_t toff = (int64_t)(bj * 64 + r) * Np + bi * 64 + c0;
+    if (AT8) *(u32x4*)(AT8 + toff) = t;
+    if (ATop) store_bool16<PREC>(ATop + toff * ES, t);
+  }
+  if (ones_slot) {
+    __shared__ int red[4];
+    cnt = wave_sum(cnt);
+    if ((tid & 63) == 0) red[tid >> 6] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned long long s = (unsigned long long)(red[0] + red[1] + red[2] + red[3]);
+      if (s) atomicAdd(ones_slot, s);
+    }
+  }
+}
+
+hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
+                         int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
+                         hipStream_t s) {
+  dim3 grid(Np / 64, Np / 64);
+  uint8_t* a = (uint8_t*)Aop;
+  uint8_t* at = (uint8_t*)ATop;
+  switch (prec) {
+    case P_I8: hipLaunchKernelGGL(k_ingest<P_I8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    case P_F32: hipLaunchKernelGGL(k_ingest<P_F32>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    case P_BF16: hipLaunchKernelGGL(k_ingest<P_BF16>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    default: hipLaunchKernelGGL(k_ingest<P_FP8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+  }
+  return hipGetLastError();
+}
+
+// S = identity on the first n constants, zero elsewhere (diag(x, x) facts).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_identity(uint8_t* S, int Np, int n) {
+  constexpr int ES = elem_bytes(PREC);
+  const int row = blockIdx.y;
+  const int c = (blockIdx.x * 256 + threadIdx.x) * 16;
+  if (c >= Np) return;
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (row < n && row >= c && row < c + 16) {
+    const int b = row - c;
+    v[b >> 2] = 1u << (8 * (b & 3));
+  }
+  store_bool16<PREC>(S + ((int64_t)row * Np + c) * ES, v);
+}
+
+hipError_t launch_identity(int prec, void* S, int Np, int n, hipStream_t s) {
+  dim3 grid((Np / 16 + 255) / 256, Np);
+  uint8_t* p = (uint8_t*)S;
+  switch (prec) {
+    case P_I8: hipLaunchKernelGGL(k_identity<P_I8>, grid, dim3(256), 0, s, p, Np, n); break;
+    case P_F32: hipLaunchKernelGGL(k_identity<P_F32>, grid, dim3(256), 0, s, p, Np, n); break;
+    case P_BF16: hipLaunchKernelGGL(k_identity<P_BF16>, grid, dim3(256), 0, s, p, Np, n); break;
+    default: hipLaunchKernelGGL(k_identity<P_FP8>, grid, dim3(256), 0, s, p, Np, n); break;
+  }
+  return hipGetLastError();
+}
+
+// Emit: crop the padded iterate to n x n and write 0/1 bytes into the
+// caller's matrix, transposing when the fixpoint ran on R^T.
+template <int PREC>
+__global__ void __launch_bounds__(256)
+k_emit(const uint8_t* __restrict__ S, int Np, int transpose, int n, uint8_t* R, int64_t ldr) {
+  __shared__ uint8_t tile[64][64 + 4];
+  const int bi = blockIdx.y, bj = blockIdx.x;  // output tile (rows bi, cols bj)
+  const int tid = threadIdx.x;
+  if (!transpose) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int r = e >> 6, c = e & 63;
+      const int gi = bi * 64 + r, gj = bj * 64 + c;
+      if (gi < n && gj < n) R[(int64_t)gi * ldr + gj] = (uint8_t)elem_nz<PREC>(S, (int64_t)gi * Np + gj);
+    }
+  } else {
+    // read the source tile (rows bj, cols bi) coalesced, write transposed
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int r = e >> 6, c = e & 63;
+      tile[r][c] = (uint8_t)elem_nz<PREC>(S, (int64_t)(bj * 64 + r) * Np + bi * 64 + c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = tid + t * 256;
+      const int r = e >> 6, c = e & 63;
+      const int gi = bi * 64 + r, gj = bj * 64 + c;
+      if (gi < n && gj < n) R[(int64_t)gi * ldr + gj] = tile[c][r];
+    }
+  }
+}
+
+hipError_t launch_emit(int prec, const void* S, int Np, int transpose, int n, uint8_t* R,
+                       int64_t ldr, hipStream_t s) {
+  const int nt = (n + 63) / 64;
+  dim3 grid(nt, nt);
+  const uint8_t* p = (const uint8_t*)S;
+  switch (prec) {
+    case P_I8: hipLaunchKernelGGL(k_emit<P_I8>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+    case P_F32: hipLaunchKernelGGL(k_emit<P_F32>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+    case P_BF16: hipLaunchKernelGGL(k_emit<P_BF16>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+    default: hipLaunchKernelGGL(k_emit<P_FP8>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+  }
+  return hipGetLastError();
+}
+
+// Zero the ring slots of steps [s0, s0 + count) before they accumulate, and
+// optionally reset the convergence state.  A kernel, not a memset, so the
+// sequence stays valid under stream capture.
+__global__ void k_ring_clear(unsigned long long* ones, int* conv, int s0, int count, int reset_conv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) ones[(s0 + i) % kRing] = 0ull;
+  if (i == 0 && reset_conv) *conv = kNotConverged;
+}
+
+hipError_t launch_ring_clear(unsigned long long* ones, int* conv, int s0, int count, int reset_conv,
+                             hipStream_t s) {
+  const int threads = 256;
+  const int blocks = (count + threads - 1) / threads > 0 ? (count + threads - 1) / threads : 1;
+  hipLaunchKernelGGL(k_ring_clear, dim3(blocks), dim3(threads), 0, s, ones, conv, s0, count, reset_conv);
+  return hipGetLastError();
+}
+
+__global__ void k_ring_set(unsigned long long* ones, int slot, unsigned long long value) {
+  if (threadIdx.x == 0) ones[slot % kRing] = value;
+}
+
+hipError_t launch_ring_set(unsigned long long* ones, int slot, unsigned long long value, hipStream_t s) {
+  hipLaunchKernelGGL(k_ring_set, dim3(1), dim3(64), 0, s, ones, slot, value);
+  return hipGetLastError();
+}
+
+// Largest row sum of the 0/1 relation (||A||_inf, Sec. 2): one workgroup per row.
+__global__ void __launch_bounds__(256) k_row_max(const uint8_t* A, int64_t lda, int n, int* out_max) {
+  const int row = blockIdx.x;
+  int s = 0;
+  for (int j = threadIdx.x; j < n; j += 256) s += A[(int64_t)row * lda + j] != 0;
+  __shared__ int red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out_max, red[0] + red[1] + red[2] + red[3]);
+}
+
+hipError_t launch_row_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_max, dim3(n), dim3(256), 0, s, A, lda, n, out_max);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,73 @@
+// common.h -- types and helpers shared by the library's HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dl {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Precision codes, identical to dl_prec in include/dl.h.
+enum Prec { P_I8 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3 };
+
+// Slots of the per-step model-size ring kept on the device.  Step s of a
+// fixpoint accumulates the number of true entries of its iterate into
+// ones[s % kRing]; kRing exceeds the largest chunk of steps launched between
+// two host read-backs.
+constexpr int kRing = 4096;
+constexpr int kNotConverged = 0x7fffffff;
+
+// Bytes per operand element for each precision.
+__host__ __device__ constexpr int elem_bytes(int prec) {
+  return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1);
+}
+
+// Parameters of one boolean product step  out = [add + X * Y^T != 0].
+struct NTParams {
+  const void* X;        // [Np x Np] operand, row-major, K contiguous
+  const void* Y;        // [Np x Np] operand; row j of Y is column j of the right factor
+  int64_t ld;           // leading dimension of X, Y, out, outT in elements (= Np)
+  int Np;               // padded size: M = N = K = Np
+  const int8_t* add;    // optional 0/1 addend [Np x Np] (row-major, ld = Np)
+  int add_identity;     // if set, OR in (i, i) for i < n_valid
+  int n_valid;          // number of real constants
+  void* out;            // [Np x Np] next iterate in operand precision
+  void* outT;           // optional transposed copy of out
+  unsigned long long* ones;  // model-size ring (read for the repeat test)
+  int count;            // 1: add this iterate's number of ones to ones[step % kRing]
+  int* conv;            // convergence step (null: no early exit)
+  int step;             // index s of the iterate this launch produces
+  int check;            // 1: detect a repeat from ones[s-1] == ones[s-2]
+  int tiles_m, tiles_n; // grid in tiles
+};
+
+// Launch helpers implemented in bool_kernels.hip.
+struct TileCfg {
+  int bm, bn, kb, threads;
+  size_t lds_bytes;
+};
+
+hipError_t launch_nt_step(int prec, int cfg_id, const NTParams& p, hipStream_t s);
+TileCfg nt_config(int prec, int cfg_id);
+int choose_nt_config(int prec, int64_t n);
+int64_t padded_size_for(int prec, int64_t n);
+
+hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
+                         int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
+                         hipStream_t s);
+hipError_t launch_identity(int prec, void* S, int Np, int n, hipStream_t s);
+hipError_t launch_emit(int prec, const void* S, int Np, int transpose, int n, uint8_t* R,
+                       int64_t ldr, hipStream_t s);
+hipError_t launch_ring_clear(unsigned long long* ones, int* conv, int s0, int count, int reset_conv,
+                             hipStream_t s);
+hipError_t launch_ring_set(unsigned long long* ones, int slot, unsigned long long value, hipStream_t s);
+hipError_t launch_row_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s);
+hipError_t bool_kernels_init();
+
+}  // namespace dl

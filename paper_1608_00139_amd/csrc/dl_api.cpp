@@ -1,0 +1,499 @@
+// dl_api.cpp -- the C ABI of include/dl.h: argument checks, workspace, and the
+// fixpoint driver that enqueues step launches and reads back model sizes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dl.h"
+#include "common.h"
+#include "eps_solve.h"
+
+using namespace dl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return DL_EHIP;
+}
+
+#define DL_HIP(expr)                                      \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
+  } while (0)
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct dl_ctx {
+  int device = 0;
+  size_t budget = 0;
+  void* ws = nullptr;  // main workspace
+  size_t ws_size = 0;
+  unsigned long long* ring = nullptr;  // device ring of model sizes (kRing slots)
+  int* conv = nullptr;                 // device convergence step
+  int* dscratch = nullptr;             // small device scratch (row max, ...)
+  unsigned long long* h_ring = nullptr;  // pinned host mirror of the ring
+  int* h_conv = nullptr;                 // pinned: conv step, scratch ints
+  bool timing = false;
+  int64_t launches[3] = {0, 0, 0};
+  double ms[3] = {0, 0, 0};
+  std::vector<EventPair> events;
+  dl::EpsWorkspace eps;  // workspace of the epsilon solve
+};
+
+namespace {
+
+int ensure_ws(dl_ctx* c, size_t need) {
+  if (need <= c->ws_size) return DL_OK;
+  if (c->budget && need > c->budget)
+    return fail(DL_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the budget of " +
+                               std::to_string(c->budget));
+  if (c->ws) {
+    hipError_t e = hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_size = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+  }
+  hipError_t e = hipMalloc(&c->ws, need);
+  if (e != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(DL_ENOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+  }
+  c->ws_size = need;
+  return DL_OK;
+}
+
+bool overlaps(const void* a, size_t alen, const void* b, size_t blen) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + blen && y < x + alen;
+}
+
+size_t mat_span(int64_t n, int64_t ld) { return n <= 0 ? 0 : (size_t)((n - 1) * ld + n); }
+
+int check_common(dl_ctx* ctx, int64_t n, const void* in, int64_t ldin, const void* out, int64_t ldout) {
+  if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(DL_EINVAL, "n < 0");
+  if (n > (1 << 16)) return fail(DL_EINVAL, "n > 65536 is not supported");
+  if (n == 0) return DL_OK;
+  if (!in || !out) return fail(DL_EINVAL, "NULL matrix pointer");
+  if (ldin < n || ldout < n) return fail(DL_EINVAL, "leading dimension smaller than n");
+  if (overlaps(in, mat_span(n, ldin), out, mat_span(n, ldout)))
+    return fail(DL_EINVAL, "output overlaps the input");
+  return DL_OK;
+}
+
+int set_device(dl_ctx* c) {
+  DL_HIP(hipSetDevice(c->device));
+  return DL_OK;
+}
+
+// Timed launch bracket (events only when timing is on).
+struct Timer {
+  dl_ctx* c;
+  hipStream_t s;
+  std::vector<std::pair<int, int>> marks;  // (class, event index)
+  size_t used = 0;
+  int begin(int cls) {
+    if (!c->timing) return -1;
+    if (used >= c->events.size()) {
+      EventPair ep;
+      if (hipEventCreate(&ep.a) != hipSuccess || hipEventCreate(&ep.b) != hipSuccess) return -1;
+      c->events.push_back(ep);
+    }
+    (void)hipEventRecord(c->events[used].a, s);
+    marks.push_back({cls, (int)used});
+    return (int)used++;
+  }
+  void end(int idx) {
+    if (idx >= 0) (void)hipEventRecord(c->events[idx].b, s);
+  }
+  // Accumulate the first `keep` marks of each class (launches that did work);
+  // call after the stream has been synchronised.
+  void collect(int cls, int64_t keep) {
+    int64_t taken = 0;
+    for (auto& m : marks) {
+      if (m.first != cls) continue;
+      if (taken >= keep) break;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, c->events[m.second].a, c->events[m.second].b) == hipSuccess) {
+        c->ms[cls] += t;
+        c->launches[cls] += 1;
+      }
+      ++taken;
+    }
+  }
+};
+
+enum Mode { M_PLAIN = 0, M_SQUARE = 1, M_SG = 2 };
+
+// Runs a fixpoint: ingest, step chunks with device-side early exit, emit.
+int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R,
+                 int64_t ldr, int prec, int32_t max_steps, int64_t* ones_out, int32_t* steps_out,
+                 int32_t* converged_out, hipStream_t s) {
+  if (prec < P_I8 || prec > P_FP8) return fail(DL_EINVAL, "unknown precision");
+  if (max_steps < 0) return fail(DL_EINVAL, "max_steps < 0");
+  int rc = set_device(c);
+  if (rc) return rc;
+  if (n == 0) {
+    if (ones_out) ones_out[0] = 0;
+    if (ones_out && max_steps >= 1) ones_out[1] = 0;
+    if (steps_out) *steps_out = max_steps >= 1 ? 1 : 0;
+    if (converged_out) *converged_out = max_steps >= 1 ? 1 : 0;
+    return DL_OK;
+  }
+  const int64_t Np = padded_size_for(prec, n);
+  const int cfg = choose_nt_config(prec, Np);
+  const size_t es = (size_t)elem_bytes(prec);
+  const size_t mat8 = (size_t)Np * Np;
+  const size_t matT = mat8 * es;
+  // layout: [add int8][op0][op1][op2][op3]
+  size_t need = mat8 + 4 * matT + 256;
+  if ((rc = ensure_ws(c, need))) return rc;
+  uint8_t* base = (uint8_t*)c->ws;
+  int8_t* ADD = (int8_t*)base;
+  uint8_t* op[4];
+  for (int i = 0; i < 4; ++i) op[i] = base + mat8 + i * matT;
+
+  Timer tm{c, s, {}, 0};
+  DL_HIP(launch_ring_clear(c->ring, c->conv, 0, 2, 1, s));
+  void *Yop = nullptr, *S[2] = {nullptr, nullptr}, *ST[2] = {nullptr, nullptr}, *Tmp = nullptr;
+  if (mode == M_PLAIN) {
+    // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
+    Yop = op[0];
+    S[0] = op[1];
+    S[1] = op[2];
+    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, nullptr, ADD, Yop, S[1], c->ring + 1, s));
+  } else if (mode == M_SQUARE) {
+    // R^(1) = A with its transpose; addend A
+    S[0] = op[0];
+    ST[0] = op[1];
+    S[1] = op[2];
+    ST[1] = op[3];
+    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, ADD, nullptr, S[1], ST[1], c->ring + 1, s));
+  } else {
+    // P in operand precision; S^(1) = I; intermediate T
+    Yop = op[0];
+    S[0] = op[1];
+    S[1] = op[2];
+    Tmp = op[3];
+    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, nullptr, nullptr, Yop, nullptr, nullptr, s));
+    DL_HIP(launch_identity(prec, S[1], (int)Np, (int)n, s));
+    DL_HIP(launch_ring_set(c->ring, 1, (unsigned long long)n, s));
+  }
+
+  const TileCfg tc = nt_config(prec, cfg);
+  NTParams p{};
+  p.ld = Np;
+  p.Np = (int)Np;
+  p.n_valid = (int)n;
+  p.ones = c->ring;
+  p.conv = c->conv;
+  p.tiles_m = (int)(Np / tc.bm);
+  p.tiles_n = (int)(Np / tc.bn);
+
+  std::vector<int64_t> ones_hist(2, 0);
+  int64_t iters = -1;  // set when the repeat is seen
+  int64_t computed = max_steps >= 1 ? 1 : 0;
+  // chunk sizes: squaring needs about 2 + log2(D) steps, so one chunk of the
+  // worst case; the plain and same-generation series grow their chunk
+  int chunk = mode == M_SQUARE ? 18 : 4;
+  int64_t s0 = 2;
+  int steps_launched = 0;
+
+  // Copy the ring and the convergence state to the host after a chunk.  The
+  // ring holds the last kRing steps, more than one chunk, so every step of
+  // the chunk just run is still present.
+  auto readback = [&](int64_t upto) -> int {
+    DL_HIP(hipMemcpyAsync(c->h_ring, c->ring, kRing * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipMemcpyAsync(c->h_conv, c->conv, sizeof(int), hipMemcpyDeviceToHost, s));
+    DL_HIP(hipStreamSynchronize(s));
+    const int cv = c->h_conv[0];
+    int64_t last = upto;
+    if (cv != kNotConverged) last = std::min<int64_t>(last, cv);
+    const int64_t first = (int64_t)ones_hist.size() - 1;  // slot 1 may be unread yet
+    if ((int64_t)ones_hist.size() < last + 1) ones_hist.resize(last + 1, 0);
+    for (int64_t k = std::max<int64_t>(1, first); k <= last; ++k) ones_hist[k] = (int64_t)c->h_ring[k % kRing];
+    if (cv != kNotConverged) {
+      iters = cv;
+    } else if (upto >= 1 && ones_hist[upto] == ones_hist[upto - 1]) {
+      iters = upto;
+    }
+    computed = (iters >= 0) ? iters : upto;
+    return DL_OK;
+  };
+
+  if (max_steps >= 1) {
+    // step 1 was produced by ingest; a single read-back settles max_steps == 1
+    if (max_steps == 1) {
+      if ((rc = readback(1))) return rc;
+    }
+    while (iters < 0 && s0 <= max_steps) {
+      const int cnt = (int)std::min<int64_t>(chunk, (int64_t)max_steps - s0 + 1);
+      DL_HIP(launch_ring_clear(c->ring, c->conv, (int)s0, cnt, 0, s));
+      for (int64_t t = s0; t < s0 + cnt; ++t) {
+        const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
+        p.step = (int)t;
+        if (mode == M_PLAIN) {
+          p.X = S[prev]; p.Y = Yop; p.add = ADD; p.add_identity = 0;
+          p.out = S[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
+          int ev = tm.begin(0);
+          DL_HIP(launch_nt_step(prec, cfg, p, s));
+          tm.end(ev);
+        } else if (mode == M_SQUARE) {
+          p.X = S[prev]; p.Y = ST[prev]; p.add = ADD; p.add_identity = 0;
+          p.out = S[cur]; p.outT = ST[cur]; p.count = 1; p.check = 1;
+          int ev = tm.begin(0);
+          DL_HIP(launch_nt_step(prec, cfg, p, s));
+          tm.end(ev);
+        } else {
+          p.X = Yop; p.Y = S[prev]; p.add = nullptr; p.add_identity = 0;
+          p.out = Tmp; p.outT = nullptr; p.count = 0; p.check = 1;
+          int ev = tm.begin(0);
+          DL_HIP(launch_nt_step(prec, cfg, p, s));
+          tm.end(ev);
+          p.X = Tmp; p.Y = Yop; p.add = nullptr; p.add_identity = 1;
+          p.out = S[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
+          ev = tm.begin(0);
+          DL_HIP(launch_nt_step(prec, cfg, p, s));
+          tm.end(ev);
+        }
+        ++steps_launched;
+      }
+      if ((rc = readback(s0 + cnt - 1))) return rc;
+      s0 += cnt;
+      chunk = std::min(chunk * 2, 256);
+    }
+  }
+
+  // the last iterate computed is R^(computed), in buffer computed % 2
+  const int64_t last = computed;
+  if (last == 0) {
+    DL_HIP(hipMemset2DAsync(R, (size_t)ldr, 0, (size_t)n, (size_t)n, s));
+  } else {
+    const void* src = S[last & 1];
+    DL_HIP(launch_emit(prec, src, (int)Np, mode == M_PLAIN ? 1 : 0, (int)n, R, ldr, s));
+  }
+  DL_HIP(hipStreamSynchronize(s));
+  if (c->timing) {
+    // launches that did work: every product of steps 2 .. computed
+    const int per = (mode == M_SG) ? 2 : 1;
+    tm.collect(0, (last >= 2 ? (last - 1) : 0) * per);
+  }
+  if (ones_out) {
+    for (int64_t k = 0; k <= last; ++k) ones_out[k] = k < (int64_t)ones_hist.size() ? ones_hist[k] : 0;
+    if (last == 0) ones_out[0] = 0;
+  }
+  if (steps_out) *steps_out = (int32_t)last;
+  if (converged_out) *converged_out = iters >= 0 ? 1 : 0;
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dl_create(dl_ctx** out, int device, size_t budget) {
+  if (!out) return fail(DL_EINVAL, "ctx out-pointer is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(DL_EINVAL, "no such device");
+  dl_ctx* c = new (std::nothrow) dl_ctx();
+  if (!c) return fail(DL_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->budget = budget;
+  auto cleanup = [&](int st) {
+    dl_destroy(c);
+    return st;
+  };
+  if ((e = hipSetDevice(device)) != hipSuccess) return cleanup(hip_fail(e, "hipSetDevice"));
+  if ((e = bool_kernels_init()) != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
+  if ((e = hipMalloc(&c->ring, kRing * sizeof(unsigned long long))) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc(ring)"));
+  if ((e = hipMalloc(&c->conv, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(conv)"));
+  c->dscratch = c->conv + 16;
+  if ((e = hipHostMalloc(&c->h_ring, kRing * sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc(ring)"));
+  if ((e = hipHostMalloc(&c->h_conv, 64 * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostMalloc(conv)"));
+  if ((e = hipMemset(c->ring, 0, kRing * sizeof(unsigned long long))) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemset(ring)"));
+  if ((e = hipMemset(c->conv, 0, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMemset(conv)"));
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
+  *out = c;
+  return DL_OK;
+}
+
+int dl_destroy(dl_ctx* c) {
+  if (!c) return DL_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->ring) (void)hipFree(c->ring);
+  if (c->conv) (void)hipFree(c->conv);
+  if (c->h_ring) (void)hipHostFree(c->h_ring);
+  if (c->h_conv) (void)hipHostFree(c->h_conv);
+  for (auto& ep : c->events) {
+    (void)hipEventDestroy(ep.a);
+    (void)hipEventDestroy(ep.b);
+  }
+  dl::eps_free(&c->eps);
+  delete c;
+  return DL_OK;
+}
+
+int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
+                int method, int prec, int32_t max_steps, int64_t* ones, int32_t* steps,
+                int32_t* converged, void* stream) {
+  int rc = check_common(ctx, n, A, lda, R, ldr);
+  if (rc) return rc;
+  if (method != DL_TC_PLAIN && method != DL_TC_SQUARE) return fail(DL_EINVAL, "unknown method");
+  return run_fixpoint(ctx, method == DL_TC_PLAIN ? M_PLAIN : M_SQUARE, n, A, lda, R, ldr, prec, max_steps,
+                      ones, steps, converged, (hipStream_t)stream);
+}
+
+int dl_tc(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr, int method,
+          int prec, int32_t* iters, void* stream) {
+  // plain: iters <= D + 1 <= n + 1; squaring: iters <= 2 + ceil(log2 n)
+  int64_t cap = method == DL_TC_SQUARE ? 3 + 64 : n + 2;
+  int32_t steps = 0, conv = 0;
+  int rc = dl_tc_steps(ctx, n, A, lda, R, ldr, method, prec, (int32_t)std::min<int64_t>(cap, INT_MAX), nullptr,
+                       &steps, &conv, stream);
+  if (rc) return rc;
+  if (!conv) return fail(DL_ENOCONV, "step cap reached before the fixpoint");
+  if (iters) *iters = steps;
+  return DL_OK;
+}
+
+int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds, int prec,
+                int32_t max_steps, int64_t* ones, int32_t* steps, int32_t* converged, void* stream) {
+  int rc = check_common(ctx, n, P, ldp, S, lds);
+  if (rc) return rc;
+  return run_fixpoint(ctx, M_SG, n, P, ldp, S, lds, prec, max_steps, ones, steps, converged,
+                      (hipStream_t)stream);
+}
+
+int dl_sg(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds, int prec,
+          int32_t* iters, void* stream) {
+  // a new pair needs a pair of equal-length walks to a common constant: at
+  // most n^2 rounds after the diagonal
+  const int64_t cap = std::min<int64_t>(n * n + 2, INT_MAX);
+  int32_t steps = 0, conv = 0;
+  int rc = dl_sg_steps(ctx, n, P, ldp, S, lds, prec, (int32_t)cap, nullptr, &steps, &conv, stream);
+  if (rc) return rc;
+  if (!conv) return fail(DL_ENOCONV, "step cap reached before the fixpoint");
+  if (iters) *iters = steps;
+  return DL_OK;
+}
+
+int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* eps_max, void* stream) {
+  if (!ctx || !eps_max) return fail(DL_EINVAL, "NULL argument");
+  if (n < 0 || (n > 0 && (!A || lda < n))) return fail(DL_EINVAL, "bad matrix");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  if (n == 0) {
+    *eps_max = 1.0;
+    return DL_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  DL_HIP(hipMemsetAsync(ctx->dscratch, 0, sizeof(int), s));
+  DL_HIP(launch_row_max(A, lda, (int)n, ctx->dscratch, s));
+  DL_HIP(hipMemcpyAsync(ctx->h_conv + 1, ctx->dscratch, sizeof(int), hipMemcpyDeviceToHost, s));
+  DL_HIP(hipStreamSynchronize(s));
+  *eps_max = 1.0 / (1.0 + (double)ctx->h_conv[1]);
+  return DL_OK;
+}
+
+int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double eps, uint8_t* R, int64_t ldr,
+                 double* X, int64_t ldx, int32_t* iters, void* stream) {
+  int rc = check_common(ctx, n, A, lda, R, ldr);
+  if (rc) return rc;
+  if (X && n > 0) {
+    if (ldx < n) return fail(DL_EINVAL, "ldx < n");
+    if (overlaps(X, mat_span(n, ldx) * sizeof(double), A, mat_span(n, lda)) ||
+        overlaps(X, mat_span(n, ldx) * sizeof(double), R, mat_span(n, ldr)))
+      return fail(DL_EINVAL, "X overlaps another matrix");
+  }
+  if (!(eps > 0.0)) return fail(DL_EINVAL, "eps must be positive");
+  if (iters) *iters = 0;
+  if (n == 0) return DL_OK;
+  double bound = 0.0;
+  if ((rc = dl_eps_bound(ctx, n, A, lda, &bound, stream))) return rc;
+  if (eps > bound) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "eps = %.17g exceeds 1/(1+||A||_inf) = %.17g (Lemma 1)", eps, bound);
+    return fail(DL_EINVAL, buf);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::string err;
+  const int64_t launches_before = ctx->launches[1];
+  (void)launches_before;
+  double tmsum = 0.0;
+  int64_t tcount = 0;
+  hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, A, lda, eps, R, ldr, X, ldx, s, ctx->timing,
+                               &tmsum, &tcount, &err);
+  if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
+  if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
+  ctx->ms[1] += tmsum;
+  ctx->launches[1] += tcount;
+  return DL_OK;
+}
+
+int dl_set_timing(dl_ctx* ctx, int enable) {
+  if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  ctx->timing = enable != 0;
+  return DL_OK;
+}
+
+int dl_kernel_stats(dl_ctx* ctx, int cls, int64_t* launches, double* total_ms, int reset) {
+  if (!ctx || cls < 0 || cls > 2) return fail(DL_EINVAL, "bad argument");
+  if (launches) *launches = ctx->launches[cls];
+  if (total_ms) *total_ms = ctx->ms[cls];
+  if (reset) {
+    ctx->launches[cls] = 0;
+    ctx->ms[cls] = 0.0;
+  }
+  return DL_OK;
+}
+
+int64_t dl_padded_size(int64_t n, int kind, int prec) {
+  if (kind == 2) return dl::eps_padded_size(n);
+  return padded_size_for(prec, n);
+}
+
+const char* dl_status_str(int status) {
+  switch (status) {
+    case DL_OK: return "DL_OK";
+    case DL_EINVAL: return "DL_EINVAL: invalid argument";
+    case DL_ENOMEM: return "DL_ENOMEM: out of memory or over budget";
+    case DL_EHIP: return "DL_EHIP: HIP runtime error";
+    case DL_ENOCONV: return "DL_ENOCONV: step cap reached";
+    case DL_EUNSUPPORTED: return "DL_EUNSUPPORTED: unsupported method/precision";
+    default: return "unknown status";
+  }
+}
+
+const char* dl_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""Transitive closure on the GPU through the C ABI, bit-exact against the oracle.
+
+Every case compares the whole 0/1 model, the iteration count and the
+per-step model sizes with the CPU oracle on the same seeded input.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import dlgen
+import oracle
+from tests.golden.load import load_sections
+from tests.gpu_util import announce, dev, gpu, host
+
+pytestmark = gpu
+
+PRECS = ["i8", "f32", "bf16", "fp8"]
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import paper_1608_00139_amd as m
+
+    m.load()
+    return m
+
+
+def _check_closure(dl, a, method, prec, tag=""):
+    n = a.shape[0]
+    announce("tc", tag, n, method, prec)
+    r, iters = dl.dl_tc(dev(a), method=method, prec=prec)
+    ref, ones, it_ref, _ = oracle.tc_seminaive(a)
+    got = host(r)
+    assert got.dtype == np.uint8 and got.shape == (n, n)
+    mism = int((got != ref).sum())
+    assert mism == 0, f"{tag} n={n} method={method} prec={prec}: {mism} entries differ"
+    if method == dl.DL_TC_PLAIN:
+        assert iters == it_ref
+    else:
+        _, hist = oracle.bfs(a, want_matrix=False)
+        assert iters == oracle.square_schedule_from_hist(hist)[0]
+    return got, iters
+
+
+def test_worked_example_all_methods(dl):
+    g = load_sections("worked_example.txt")
+    a = g["R1"].astype(np.uint8)
+    for method in (dl.DL_TC_PLAIN, dl.DL_TC_SQUARE):
+        for prec in PRECS:
+            announce("worked example", method, prec)
+            r, iters = dl.dl_tc(dev(a), method=method, prec=prec)
+            assert np.array_equal(host(r), g["R2_printed"].astype(np.uint8))
+            assert iters == 4
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 64, 65, 100, 255, 256, 257, 300, 513, 1000])
+@pytest.mark.parametrize("method", [0, 1])
+def test_random_sizes_int8(dl, n, method):
+    for seed, p in ((0, 1.5 / n), (1, 4.0 / n), (2, 0.05)):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, min(p, 1.0), seed))
+        _check_closure(dl, a, method, "i8", f"er seed={seed} p={p:.4f}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("method", [0, 1])
+def test_precisions(dl, prec, method):
+    for n, seed in ((200, 3), (777, 4)):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, seed, self_loops=True))
+        _check_closure(dl, a, method, prec, f"prec seed={seed}")
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_per_step_parity(dl, method):
+    """Iterate k of the GPU series equals the oracle's iterate k, with model sizes."""
+    n = 300
+    a = dlgen.to_dense(n, dlgen.er_edges(n, 1.3 / n, 5))
+    if method == dl.DL_TC_PLAIN:
+        _, ones_ref, iters_ref, _ = oracle.tc_seminaive(a)
+    else:
+        _, ones_ref, iters_ref, _ = oracle.tc_square_literal(a)
+    for k in range(0, iters_ref + 2):
+        announce("steps", method, k)
+        res = dl.dl_tc_steps(dev(a), k, method=method, prec="i8")
+        if method == dl.DL_TC_PLAIN:
+            rk = oracle.tc_seminaive(a, maxsteps=k)[0]
+        else:
+            rk = oracle.tc_square_literal(a, maxsteps=k)[0]
+        assert np.array_equal(host(res.R), rk), k
+        assert res.steps == min(k, iters_ref)
+        assert res.converged == (k >= iters_ref)
+        assert res.ones == list(ones_ref[: res.steps + 1])
+
+
+def test_special_graphs(dl):
+    cases = {
+        "empty": np.zeros((50, 50), np.uint8),
+        "complete": 1 - np.eye(40, dtype=np.uint8),
+        "cycle": np.roll(np.eye(97, dtype=np.uint8), 1, axis=1),
+        "path": np.eye(130, k=1, dtype=np.uint8),
+        "selfloops": np.eye(20, dtype=np.uint8),
+        "full": np.ones((33, 33), np.uint8),
+    }
+    for name, a in cases.items():
+        for method in (0, 1):
+            for prec in ("i8", "f32"):
+                _check_closure(dl, a, method, prec, name)
+
+
+def test_input_encoding_and_strides(dl):
+    """Any nonzero byte is true; a strided view (ld > n) is read and written correctly."""
+    import torch
+
+    n = 120
+    a = dlgen.to_dense(n, dlgen.er_edges(n, 3.0 / n, 9))
+    noisy = a * np.random.default_rng(0).integers(1, 256, size=a.shape).astype(np.uint8)
+    big = np.zeros((n, n + 37), np.uint8)
+    big[:, :n] = noisy
+    tbig = dev(big)
+    view = tbig[:, :n]
+    out_big = torch.full((n, n + 11), 7, dtype=torch.uint8, device="cuda")
+    out = out_big[:, :n]
+    announce("strides")
+    dl.dl_tc(view, method=1, prec="i8", out=out)
+    ref = oracle.tc_seminaive(a)[0]
+    assert np.array_equal(host(out), ref)
+    assert np.all(host(out_big)[:, n:] == 7)  # padding columns untouched
+
+
+def test_zero_size_and_errors(dl):
+    import torch
+
+    announce("zero size")
+    r, iters = dl.dl_tc(torch.zeros((0, 0), dtype=torch.uint8, device="cuda"))
+    assert iters == 1 and r.shape == (0, 0)
+    a = dev(np.eye(8, k=1, dtype=np.uint8))
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc(a, method=5)
+    assert ei.value.status == 1
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc(a, prec=9)
+    assert ei.value.status == 1
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc(a, out=a)  # output aliases the input
+    assert ei.value.status == 1
+
+
+def test_config_plain_fp32_n512(dl):
+    """Plain FP32 iteration, n = 512, ER p = 2/n, seeds 0..2."""
+    n = 512
+    for seed in range(3):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, seed))
+        _check_closure(dl, a, dl.DL_TC_PLAIN, "f32", f"cfg512 seed={seed}")
+
+
+@pytest.mark.parametrize("pname,p", [("1/N", 1.0 / 8192), ("4/N", 4.0 / 8192), ("0.01", 0.01)])
+def test_config_n8192_int8_square(dl, pname, p):
+    """Int8 repeated squaring at n = 8192 on ER graphs, three seeds each."""
+    n = 8192
+    for seed in range(3):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, p, seed))
+        _check_closure(dl, a, dl.DL_TC_SQUARE, "i8", f"cfg8192 p={pname} seed={seed}")
+
+
+def test_config_n8192_fp32_plain(dl):
+    """The plain FP32 baseline at n = 8192 gives the same model (one seed per p)."""
+    n = 8192
+    for p in (4.0 / n, 0.01):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, p, 0))
+        _check_closure(dl, a, dl.DL_TC_PLAIN, "f32", f"cfg8192 fp32 p={p}")
+
+
+def test_tile_configs_sizes(dl):
+    """Sizes that select each tile configuration, with ragged tails."""
+    for n in (1500, 2100, 4001):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, 2.5 / n, n))
+        for prec in ("i8", "bf16"):
+            _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
