@@ -55,10 +55,13 @@ struct OpF32 {
   __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
     // one chunk = 4 consecutive k; four K=4 instructions, lane group g
     // supplies k = 4*chunk(g) + j in instruction j
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(float, a[0][j]),
-                                               __builtin_bit_cast(float, b[0][j]), c, 0, 0, 0);
+    // bit-cast whole vectors: a scalar bit-cast of one element of an
+    // unsigned ext-vector is miscompiled by this clang (it yields element 0)
+    const v4f x = __builtin_bit_cast(v4f, a[0]), y = __builtin_bit_cast(v4f, b[0]);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, y.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, y.w, c, 0, 0, 0);
     return c;
   }
   __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
