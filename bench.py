@@ -50,7 +50,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true", help="skip the once-measured variants")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--trace-summary", metavar="DB",
+                    help="summarise a rocprofv3 --kernel-trace results database and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        return trace_summary(args.trace_summary)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -145,7 +149,7 @@ def main() -> int:
         "config": {"workload": "TC to fixpoint, int8 repeated squaring, N=8192 ER p in {1/N,4/N,0.01} x seeds {0,1,2}",
                    "n": N, "graphs": len(graphs), "iters": iters, "products_per_step": sum(products)},
         "frac_of_int8_peak": round(value / INT8_PEAK_TOPS, 4),
-        "roofline": {"bound": "mfma", "kernel": "k_nt_step<256,256,128,64,64,OpI8>",
+        "roofline": {"bound": "mfma", "kernel": "k_nt_dma<256,256,64,64,128,OpI8,2>",
                      "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
                      "launches": launches, "avg_kernel_ms": round(avg_kernel_ms, 4),
@@ -187,7 +191,7 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
 
     # bf16 / fp8 squaring variants
     var = []
-    for prec_name, prec in (("bf16", dl.DL_BF16), ("fp8", dl.DL_FP8)):
+    for prec_name, prec in (("fp4", dl.DL_FP4), ("fp8", dl.DL_FP8), ("bf16", dl.DL_BF16)):
         for i in seed0:
             g = graphs[i]
             log(f"{prec_name} square p={g['p']}")
@@ -259,6 +263,33 @@ def cpu_baseline(graphs, iters):
     return {"value": round(work / t_total / 1e12, 3), "unit": "TOPS", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": "semi-naive TC on the three seed-0 graphs (p = 1/N, 4/N, 0.01), N=8192",
             "seconds": round(t_total, 3), "per_graph": per}
+
+
+def trace_summary(db_path: str) -> int:
+    """Per-kernel statistics from a rocprofv3 kernel-trace database.
+
+    Besides rocprofv3's own per-kernel average, the step kernels are also
+    averaged over the launches that did work: a step launched after the
+    fixpoint was reached returns at once (a few microseconds), and those
+    launches are separated by a duration cut at 10% of the kernel's longest
+    launch.
+    """
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration from kernels").fetchall()
+    by = {}
+    for name, dur in rows:
+        by.setdefault(name, []).append(float(dur))
+    total = sum(sum(v) for v in by.values())
+    print(f"# kernel trace summary of {db_path}")
+    print(f"# {'calls':>7} {'total_ms':>10} {'avg_us':>10} {'pct':>6} {'work_calls':>10} {'work_avg_us':>11}  kernel")
+    for name, v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        cut = 0.1 * max(v)
+        work = [d for d in v if d >= cut]
+        print(f"  {len(v):7d} {sum(v) / 1e6:10.3f} {sum(v) / len(v) / 1e3:10.3f} {100 * sum(v) / total:6.2f} "
+              f"{len(work):10d} {sum(work) / len(work) / 1e3:11.3f}  {name[:110]}")
+    return 0
 
 
 if __name__ == "__main__":

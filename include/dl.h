@@ -68,9 +68,10 @@ typedef enum {
 } dl_tc_method;
 
 /* Arithmetic of the products.  Operands are exactly 0/1 in every format, so
- * all are exact: int8 with int32 accumulation, and fp32/bf16/fp8(e4m3) with
- * fp32 accumulation while counts stay below 2^24. */
-typedef enum { DL_I8 = 0, DL_F32 = 1, DL_BF16 = 2, DL_FP8 = 3 } dl_prec;
+ * all are exact: int8 with int32 accumulation, and fp32/bf16/fp8(e4m3)/
+ * fp4(e2m1, two elements per byte) with fp32 accumulation while counts stay
+ * below 2^24 (n <= 65536 keeps every count below that). */
+typedef enum { DL_I8 = 0, DL_F32 = 1, DL_BF16 = 2, DL_FP8 = 3, DL_FP4 = 4 } dl_prec;
 
 typedef struct dl_ctx dl_ctx;
 
@@ -104,7 +105,7 @@ int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* 
  * the r1 relation (device uint8 [n x ldp]) and I encodes diag(x, x) for
  * every constant.  Each step runs two products, T = min1(P S) and
  * S' = min1(I + T P^T); thresholding the intermediate keeps the zero
- * pattern of P S P^T.  prec: DL_I8, DL_F32, DL_BF16 or DL_FP8. */
+ * pattern of P S P^T.  prec: any dl_prec. */
 int dl_sg(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds,
           int prec, int32_t* iters, void* stream);
 
@@ -114,8 +115,11 @@ int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* 
                 void* stream);
 
 /* Linear epsilon form (Sec. 4, Proposition 1 and Theorem 1): solves
- * (I - eps A) X = eps A in fp64 by LU factorisation without pivoting and
- * two triangular solves, then writes R = [X > 0].
+ * (I - eps A) X = eps A in fp64 by block Gaussian elimination without
+ * pivoting (each diagonal block inverted, panels and trailing updates as
+ * fp64 matrix products) and block back substitution, then writes
+ * R = [X > 0].  Device workspace: (n rounded up to 128)^2 * 16 bytes plus
+ * a panel.
  *   eps  must satisfy 0 < eps <= 1 / (1 + ||A||_inf), ||A||_inf = max row
  *        sum of the 0/1 matrix (Lemma 1); otherwise DL_EINVAL.
  *   X    optional device double [n x ldx] receiving the real solution

@@ -19,15 +19,15 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8",
+    "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
     "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound",
     "dl_padded_size",
 ]
 
 DL_TC_PLAIN, DL_TC_SQUARE = 0, 1
-DL_I8, DL_F32, DL_BF16, DL_FP8 = 0, 1, 2, 3
-PRECISIONS = {"i8": DL_I8, "f32": DL_F32, "bf16": DL_BF16, "fp8": DL_FP8}
+DL_I8, DL_F32, DL_BF16, DL_FP8, DL_FP4 = 0, 1, 2, 3, 4
+PRECISIONS = {"i8": DL_I8, "f32": DL_F32, "bf16": DL_BF16, "fp8": DL_FP8, "fp4": DL_FP4}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None

@@ -31,13 +31,23 @@
 namespace dl {
 
 // ----------------------------------------------------------------- operand policies
-// CPL = 16-byte chunks per lane per MFMA; the four lane groups (lane / 16)
-// read consecutive chunk groups, and A and B use the same K assignment, so
-// the internal K order of the instruction does not matter.
+// FR = rows (and columns) of one MFMA fragment; the 64 lanes form 64 / FR
+// groups along K, lane l supplying row l % FR of its group's K range.
+// CPL = 16-byte chunks per lane per MFMA.  A and B use the same K
+// assignment, so the instruction's internal K order does not matter.
+// coord() gives the output row/column of accumulator item i of a lane
+// (layouts checked on the device).
+
+// 16x16 output tile: item i of lane l is row 4 (l / 16) + i, column l % 16
+__device__ inline void coord16(int lane, int i, int& r, int& c) {
+  r = 4 * (lane >> 4) + i;
+  c = lane & 15;
+}
 
 struct OpI8 {
   static constexpr int kPrec = P_I8;
-  static constexpr int CPL = 1;
+  static constexpr int FR = 16, CPL = 1, NI = 4;
+  __device__ static void coord(int lane, int i, int& r, int& c) { coord16(lane, i, r, c); }
   typedef v4i Acc;
   __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
   __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
@@ -47,9 +57,28 @@ struct OpI8 {
   __device__ static bool nz(const Acc& c, int i) { return c[i] != 0; }
 };
 
+// v_mfma_i32_32x32x32_i8: item i of lane l is row 8 (i / 4) + 4 (l / 32) + i % 4,
+// column l % 32
+struct OpI8x32 {
+  static constexpr int kPrec = P_I8;
+  static constexpr int FR = 32, CPL = 1, NI = 16;
+  __device__ static void coord(int lane, int i, int& r, int& c) {
+    r = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+    c = lane & 31;
+  }
+  typedef v16i Acc;
+  __device__ static Acc zero() { return Acc{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(v4i, a[0]),
+                                                 __builtin_bit_cast(v4i, b[0]), c, 0, 0, 0);
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0; }
+};
+
 struct OpF32 {
   static constexpr int kPrec = P_F32;
-  static constexpr int CPL = 1;
+  static constexpr int FR = 16, CPL = 1, NI = 4;
+  __device__ static void coord(int lane, int i, int& r, int& c) { coord16(lane, i, r, c); }
   typedef v4f Acc;
   __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
   __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
@@ -69,7 +98,8 @@ struct OpF32 {
 
 struct OpBF16 {
   static constexpr int kPrec = P_BF16;
-  static constexpr int CPL = 1;
+  static constexpr int FR = 16, CPL = 1, NI = 4;
+  __device__ static void coord(int lane, int i, int& r, int& c) { coord16(lane, i, r, c); }
   typedef v4f Acc;
   __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
   __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
@@ -81,7 +111,8 @@ struct OpBF16 {
 
 struct OpFP8 {
   static constexpr int kPrec = P_FP8;
-  static constexpr int CPL = 2;
+  static constexpr int FR = 16, CPL = 2, NI = 4;
+  __device__ static void coord(int lane, int i, int& r, int& c) { coord16(lane, i, r, c); }
   typedef v4f Acc;
   __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
   __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
@@ -94,11 +125,41 @@ struct OpFP8 {
   __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
 };
 
+// fp4 e2m1 operands: 32 elements (16 bytes) per lane, K = 128 per instruction;
+// 1.0 is the code 0x2.  The instruction reads the low four operand dwords.
+struct OpFP4 {
+  static constexpr int kPrec = P_FP4;
+  static constexpr int FR = 16, CPL = 1, NI = 4;
+  __device__ static void coord(int lane, int i, int& r, int& c) { coord16(lane, i, r, c); }
+  typedef v4f Acc;
+  __device__ static Acc zero() { return Acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static Acc mma(const u32x4* a, const u32x4* b, Acc c) {
+    v8i av = {0, 0, 0, 0, 0, 0, 0, 0}, bv = {0, 0, 0, 0, 0, 0, 0, 0};
+    const v4i x = __builtin_bit_cast(v4i, a[0]), y = __builtin_bit_cast(v4i, b[0]);
+    av.lo = x;
+    bv.lo = y;
+    // formats 4/4 = fp4 e2m1 for both operands; E8M0 scale 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 4, 4, 0, 127, 0, 127);
+  }
+  __device__ static bool nz(const Acc& c, int i) { return c[i] != 0.f; }
+};
+
 // Store 16 boolean bytes (each 0 or 1) as 16 operand elements.
 template <int PREC>
 __device__ inline void store_bool16(uint8_t* dst, u32x4 b) {
   if constexpr (PREC == P_I8) {
     *(u32x4*)dst = b;
+  } else if constexpr (PREC == P_FP4) {
+    // two elements per byte: element 2t -> low nibble, 2t + 1 -> high nibble
+    unsigned w2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const unsigned x = b[2 * h], y = b[2 * h + 1];
+      const unsigned lo = ((x & 1u) << 1) | (((x >> 8) & 1u) << 5) | (((x >> 16) & 1u) << 9) | (((x >> 24) & 1u) << 13);
+      const unsigned hi = ((y & 1u) << 1) | (((y >> 8) & 1u) << 5) | (((y >> 16) & 1u) << 9) | (((y >> 24) & 1u) << 13);
+      w2[h] = lo | (hi << 16);
+    }
+    *(uint2*)dst = make_uint2(w2[0], w2[1]);
   } else if constexpr (PREC == P_FP8) {
     *(u32x4*)dst = b * 0x38u;  // bytes are 0/1: multiply puts 0x38 (1.0 in e4m3) in each set byte
   } else if constexpr (PREC == P_BF16) {
@@ -132,6 +193,7 @@ __device__ inline void store_bool16(uint8_t* dst, u32x4 b) {
 template <int PREC>
 __device__ inline unsigned elem_nz(const uint8_t* p, int64_t idx) {
   if constexpr (PREC == P_F32) return ((const unsigned*)p)[idx] != 0u ? 1u : 0u;
+  else if constexpr (PREC == P_FP4) return ((p[idx >> 1] >> (4 * (idx & 1))) & 15u) != 0 ? 1u : 0u;
   else if constexpr (PREC == P_BF16) return ((const unsigned short*)p)[idx] != 0 ? 1u : 0u;
   else return p[idx] != 0 ? 1u : 0u;
 }
@@ -182,15 +244,27 @@ __device__ inline bool step_is_done(const NTParams& p) {
   return false;
 }
 
-template <int BM, int BN, int WM, int WN, int KB, class Op>
+// LDS row swizzle: the 16-byte chunk c of row r of a staged slice is stored
+// at unit  c * rows + (r ^ swz(c)).  Lanes that store one global row (its KC
+// chunks) then land in different banks, and the lanes that read one MFMA
+// operand (consecutive rows of one chunk) still read a permutation of one
+// aligned 8-row block.  swz < 8 keeps every row inside its aligned block.
+template <int SWZ>
+__device__ __host__ constexpr int swz(int c) {
+  return SWZ ? ((c * SWZ) & 7) : 0;
+}
+
+template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF = 1>
 struct NTKernel {
   static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
   static constexpr int NWAVES = WAVES_M * WAVES_N;
   static constexpr int NT = NWAVES * 64;
   static constexpr int KC = KB / 16;                 // chunks per row per stage
-  static constexpr int FM = WM / 16, FN = WN / 16;   // 16x16 fragments per wave
+  static constexpr int FR = Op::FR;
+  static constexpr int GROUPS = 64 / FR;             // lane groups along K
+  static constexpr int FM = WM / FR, FN = WN / FR;   // fragments per wave
   static constexpr int CPL = Op::CPL;
-  static constexpr int KSTEP_CHUNKS = 4 * CPL;       // chunks consumed by one MFMA k-step
+  static constexpr int KSTEP_CHUNKS = GROUPS * CPL;  // chunks consumed by one MFMA k-step
   static constexpr int KSTEPS = KC / KSTEP_CHUNKS;
   static constexpr int STAGE_CHUNKS = (BM + BN) * KC;
   static constexpr int LOADS = STAGE_CHUNKS / NT;
@@ -199,16 +273,17 @@ struct NTKernel {
   static constexpr size_t OPER_BYTES = 2ull * STAGE_CHUNKS * 16;
   static constexpr size_t EPI_BYTES = (size_t)BM * EST;
   static constexpr size_t LDS_BYTES = OPER_BYTES > EPI_BYTES ? OPER_BYTES : EPI_BYTES;
-  static constexpr int ES = elem_bytes(Op::kPrec);
+  static constexpr int NIB = elem_nibbles(Op::kPrec);  // 4-bit units per element
   static_assert(KC % KSTEP_CHUNKS == 0, "stage must hold whole MFMA k-steps");
   static_assert(STAGE_CHUNKS % NT == 0, "loads must divide evenly");
   static_assert((BM * BN / 16) % NT == 0, "epilogue segments must divide evenly");
+  static_assert(WM % FR == 0 && WN % FR == 0, "wave tile must hold whole fragments");
 };
 
-template <int BM, int BN, int WM, int WN, int KB, class Op>
+template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF = 1>
 __global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
 k_nt_step(NTParams p) {
-  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
+  typedef NTKernel<BM, BN, WM, WN, KB, Op, SWZ, PREF> K;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   if (step_is_done(p)) return;
 
@@ -219,16 +294,15 @@ k_nt_step(NTParams p) {
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
   const int row0 = tm * BM, col0 = tn * BN;
-  const int64_t ldb = p.ld * K::ES;  // row pitch in bytes
+  const int64_t ldb = p.ld * K::NIB / 2;  // row pitch in bytes
   const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
   const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
   const int nk = (int)(ldb / KB);
 
   u32x4* lds = (u32x4*)smem;
-  // chunk q of a stage: rows [0, BM) of X then rows [0, BN) of Y;
-  // q -> (row, chunk) with 16-byte chunks of one row adjacent in global memory
-  u32x4 regs[K::LOADS];
-  auto gload = [&](int kt) {
+  // chunk q of a stage: rows [0, BM) of X then rows [0, BN) of Y; the KC
+  // chunks of one row are adjacent in global memory and in q
+  auto gload = [&](u32x4 (&regs)[K::LOADS], int kt) {
 #pragma unroll
     for (int i = 0; i < K::LOADS; ++i) {
       const int q = tid + i * K::NT;
@@ -237,14 +311,15 @@ k_nt_step(NTParams p) {
       regs[i] = *(const u32x4*)(src + (int64_t)kt * KB + c * 16);
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](const u32x4 (&regs)[K::LOADS], int buf) {
     u32x4* base = lds + buf * K::STAGE_CHUNKS;
 #pragma unroll
     for (int i = 0; i < K::LOADS; ++i) {
       const int q = tid + i * K::NT;
       const int row = q / K::KC, c = q % K::KC;
       // X region: [KC][BM]; Y region after it: [KC][BN]
-      const int off = (row < BM) ? (c * BM + row) : (BM * K::KC + c * BN + (row - BM));
+      const int off = (row < BM) ? (c * BM + (row ^ swz<SWZ>(c)))
+                                 : (BM * K::KC + c * BN + ((row - BM) ^ swz<SWZ>(c)));
       base[off] = regs[i];
     }
   };
@@ -255,15 +330,9 @@ k_nt_step(NTParams p) {
 #pragma unroll
     for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::zero();
 
-  gload(0);
-  sstore(0);
-  __syncthreads();
-
-  const int g = lane >> 4, r16 = lane & 15;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-    const u32x4* xs = lds + cur * K::STAGE_CHUNKS;
+  const int g = lane / K::FR, rf = lane % K::FR;
+  auto compute = [&](int buf) {
+    const u32x4* xs = lds + buf * K::STAGE_CHUNKS;
     const u32x4* ys = xs + BM * K::KC;
 #pragma unroll
     for (int ks = 0; ks < K::KSTEPS; ++ks) {
@@ -273,22 +342,55 @@ k_nt_step(NTParams p) {
 #pragma unroll
         for (int c = 0; c < K::CPL; ++c) {
           const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
-          af[i][c] = xs[ch * BM + wm * WM + i * 16 + r16];
+          af[i][c] = xs[ch * BM + ((wm * WM + i * K::FR + rf) ^ swz<SWZ>(ch))];
         }
 #pragma unroll
       for (int j = 0; j < K::FN; ++j)
 #pragma unroll
         for (int c = 0; c < K::CPL; ++c) {
           const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
-          bf[j][c] = ys[ch * BN + wn * WN + j * 16 + r16];
+          bf[j][c] = ys[ch * BN + ((wn * WN + j * K::FR + rf) ^ swz<SWZ>(ch))];
         }
 #pragma unroll
       for (int i = 0; i < K::FM; ++i)
 #pragma unroll
         for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::mma(af[i], bf[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+
+  if constexpr (PREF == 1) {
+    // one slice in flight: load k+1 into registers while computing k
+    u32x4 ra[K::LOADS];
+    gload(ra, 0);
+    sstore(ra, 0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk) gload(ra, kt + 1);
+      compute(kt & 1);
+      if (kt + 1 < nk) sstore(ra, (kt + 1) & 1);
+      __syncthreads();
+    }
+  } else {
+    // two slices in flight: the loads of slice k+1 had a whole compute phase
+    // to land before they are stored to LDS at the end of iteration k
+    u32x4 ra[K::LOADS], rb[K::LOADS];
+    gload(ra, 0);
+    if (nk > 1) gload(rb, 1);
+    sstore(ra, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      // even iteration: rb holds slice kt+1, ra is free
+      if (kt + 2 < nk) gload(ra, kt + 2);
+      compute(0);
+      if (kt + 1 < nk) sstore(rb, 1);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      // odd iteration: ra holds slice kt+2, rb is free
+      if (kt + 3 < nk) gload(rb, kt + 3);
+      compute(1);
+      if (kt + 2 < nk) sstore(ra, 0);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue: 0/1 tile in LDS, [BM][EST] bytes
@@ -298,10 +400,10 @@ k_nt_step(NTParams p) {
 #pragma unroll
     for (int j = 0; j < K::FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wm * WM + i * 16 + 4 * g + v;
-        const int c = wn * WN + j * 16 + r16;
-        et[r * K::EST + c] = Op::nz(acc[i][j], v) ? 1 : 0;
+      for (int v = 0; v < Op::NI; ++v) {
+        int r, c;
+        Op::coord(lane, v, r, c);
+        et[(wm * WM + i * K::FR + r) * K::EST + wn * WN + j * K::FR + c] = Op::nz(acc[i][j], v) ? 1 : 0;
       }
   __syncthreads();
 
@@ -321,7 +423,7 @@ k_nt_step(NTParams p) {
       v[b >> 2] |= 1u << (8 * (b & 3));
     }
     cnt += popc16(v);
-    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::ES, v);
+    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
     if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
   }
 
@@ -332,8 +434,10 @@ k_nt_step(NTParams p) {
     uint8_t* outt = (uint8_t*)p.outT;
 #pragma unroll 2
     for (int i = 0; i < TSEGS; ++i) {
+      // consecutive lanes take consecutive columns of the same 16 rows, so
+      // each byte read of a wave touches one 64-byte run of one LDS row
       const int q = tid + i * K::NT;
-      const int c = q / SEG_PER_COL, rs = q % SEG_PER_COL;
+      const int c = q % BN, rs = q / BN;
       u32x4 v;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -341,7 +445,7 @@ k_nt_step(NTParams p) {
         v[w] = (unsigned)e[0] | ((unsigned)e[K::EST] << 8) | ((unsigned)e[2 * K::EST] << 16) |
                ((unsigned)e[3 * K::EST] << 24);
       }
-      store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::ES, v);
+      store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::NIB / 2, v);
     }
   }
 
@@ -359,57 +463,296 @@ k_nt_step(NTParams p) {
   }
 }
 
+// ----------------------------------------------------------------- direct-to-LDS variant
+// Same product and epilogue as k_nt_step, but the K slices are fetched with
+// global_load_lds_dwordx4 (global memory straight into LDS, no staging
+// registers) into a ring of NSTAGE slices, so NSTAGE - 1 slices are in
+// flight while one is multiplied.  Slice layout: KB-byte rows, the 16-byte
+// chunk c of row r stored at position c ^ rsw(r).  One DMA instruction of a
+// wave writes 1 KB of consecutive rows in lane order, so lane l fetches row
+// r0 + l / KC, chunk (l % KC) ^ rsw(row): each row is still read by KC
+// adjacent lanes.  rsw is chosen so that the 16 lanes reading one MFMA
+// operand (16 consecutive rows, one chunk) hit distinct banks for both 32-
+// and 64-bank LDS (checked exhaustively on the host).
+template <int KC>
+__device__ __host__ constexpr int rsw(int r) {
+  return KC == 4 ? (((r >> 1) ^ (r >> 3)) & 3) : ((r ^ (r >> 1)) & 7);
+}
+
+template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
+struct DmaKernel {
+  static constexpr int KC = KB / 16;
+  static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN;
+  static constexpr int NWAVES = WAVES_M * WAVES_N;
+  static constexpr int NT = NWAVES * 64;
+  static constexpr int FR = Op::FR;
+  static constexpr int GROUPS = 64 / FR;
+  static constexpr int FM = WM / FR, FN = WN / FR;
+  static constexpr int CPL = Op::CPL;
+  static constexpr int KSTEP_CHUNKS = GROUPS * CPL;
+  static constexpr int KSTEPS = KC / KSTEP_CHUNKS;
+  static constexpr int STAGE_BYTES = (BM + BN) * KB;
+  static constexpr int ROWS_PER_DMA = 1024 / KB;                 // rows one 1 KB instruction covers
+  static constexpr int DMA_PER_WAVE = (BM + BN) / ROWS_PER_DMA / NWAVES;
+  static constexpr int EPAD = 16;
+  static constexpr int EST = BN + EPAD;
+  static constexpr size_t OPER_BYTES = (size_t)NSTAGE * STAGE_BYTES;
+  static constexpr size_t EPI_BYTES = (size_t)BM * EST;
+  static constexpr size_t LDS_BYTES = OPER_BYTES > EPI_BYTES ? OPER_BYTES : EPI_BYTES;
+  static constexpr int NIB = elem_nibbles(Op::kPrec);  // 4-bit units per element
+  static_assert(KC == 4 || KC == 8, "64- or 128-byte slices");
+  static_assert(KC % KSTEP_CHUNKS == 0, "slice must hold whole MFMA k-steps");
+  static_assert(((BM + BN) / ROWS_PER_DMA) % NWAVES == 0, "DMA instructions must divide evenly");
+  static_assert((NSTAGE - 2) * DMA_PER_WAVE < 64, "vmcnt range");
+  static_assert((BM * BN / 16) % NT == 0, "epilogue segments must divide evenly");
+};
+
+// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__attribute__((amdgpu_waves_per_eu(1, ((BM / WM) * (BN / WN) + 3) / 4 > 2 ? ((BM / WM) * (BN / WN) + 3) / 4 : 2)))
+k_nt_dma(NTParams p) {
+  typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int64_t ldb = p.ld * K::NIB / 2;
+  const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
+  const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
+  const int nk = (int)(ldb / KB);
+
+  // per-lane source address of each of this wave's DMA instructions
+  const uint8_t* src[K::DMA_PER_WAVE];
+#pragma unroll
+  for (int j = 0; j < K::DMA_PER_WAVE; ++j) {
+    const int r = (wave + j * K::NWAVES) * K::ROWS_PER_DMA + lane / K::KC;  // X rows then Y rows
+    const int c = (lane % K::KC) ^ rsw<K::KC>(r);
+    src[j] = ((r < BM) ? (Xg + (int64_t)r * ldb) : (Yg + (int64_t)(r - BM) * ldb)) + c * 16;
+  }
+  auto issue = [&](int kt) {
+    uint8_t* stage = smem + (kt % NSTAGE) * K::STAGE_BYTES;
+#pragma unroll
+    for (int j = 0; j < K::DMA_PER_WAVE; ++j) {
+      uint8_t* dst = stage + (wave + j * K::NWAVES) * 1024;  // wave-uniform
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[j] + (int64_t)kt * KB),
+                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+  };
+
+  typename Op::Acc acc[K::FM][K::FN];
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::zero();
+
+  const int g = lane / K::FR, rf = lane % K::FR;
+  typedef u32x4 FragA[K::FM][K::CPL];
+  typedef u32x4 FragB[K::FN][K::CPL];
+  auto load_frags = [&](const uint8_t* xs, const uint8_t* ys, int ks, FragA& af, FragB& bf) {
+#pragma unroll
+    for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+      for (int c = 0; c < K::CPL; ++c) {
+        const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
+        const int r = wm * WM + i * K::FR + rf;
+        af[i][c] = *(const u32x4*)(xs + r * KB + 16 * (ch ^ rsw<K::KC>(r)));
+      }
+#pragma unroll
+    for (int j = 0; j < K::FN; ++j)
+#pragma unroll
+      for (int c = 0; c < K::CPL; ++c) {
+        const int ch = ks * K::KSTEP_CHUNKS + g * K::CPL + c;
+        const int r = wn * WN + j * K::FR + rf;
+        bf[j][c] = *(const u32x4*)(ys + r * KB + 16 * (ch ^ rsw<K::KC>(r)));
+      }
+  };
+  // the fragments of k-step ks + 1 are requested before the products of ks
+  auto compute = [&](int buf) {
+    const uint8_t* xs = smem + buf * K::STAGE_BYTES;
+    const uint8_t* ys = xs + BM * KB;
+    FragA af[2];
+    FragB bf[2];
+    load_frags(xs, ys, 0, af[0], bf[0]);
+#pragma unroll
+    for (int ks = 0; ks < K::KSTEPS; ++ks) {
+      if (ks + 1 < K::KSTEPS) load_frags(xs, ys, ks + 1, af[(ks + 1) & 1], bf[(ks + 1) & 1]);
+#pragma unroll
+      for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::mma(af[ks & 1][i], bf[ks & 1][j], acc[i][j]);
+    }
+  };
+
+  // prologue: NSTAGE - 1 slices in flight
+#pragma unroll
+  for (int s0 = 0; s0 < NSTAGE - 1; ++s0)
+    if (s0 < nk) issue(s0);
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's DMA for slice kt has landed once at most the later
+    // slices' instructions are outstanding; the barrier extends that to
+    // every wave, and also retires all reads of the slot refilled below
+    if (kt + NSTAGE - 2 < nk) wait_vmcnt<(NSTAGE - 2) * K::DMA_PER_WAVE>();
+    else wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+    compute(kt % NSTAGE);
+  }
+  wait_vmcnt<0>();
+  __syncthreads();
+
+  // ---- epilogue (identical to k_nt_step)
+  uint8_t* et = smem;
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < K::FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Op::NI; ++v) {
+        int r, c;
+        Op::coord(lane, v, r, c);
+        et[(wm * WM + i * K::FR + r) * K::EST + wn * WN + j * K::FR + c] = Op::nz(acc[i][j], v) ? 1 : 0;
+      }
+  __syncthreads();
+
+  int cnt = 0;
+  constexpr int SEG_PER_ROW = BN / 16;
+  constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
+  uint8_t* outb = (uint8_t*)p.out;
+#pragma unroll 4
+  for (int i = 0; i < SEGS; ++i) {
+    const int q = tid + i * K::NT;
+    const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
+    u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
+    const int gr = row0 + r, gc = col0 + cs * 16;
+    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+      const int b = gr - gc;
+      v[b >> 2] |= 1u << (8 * (b & 3));
+    }
+    cnt += popc16(v);
+    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
+    if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
+  }
+  if (p.outT) {
+    __syncthreads();
+    constexpr int SEG_PER_COL = BM / 16;
+    constexpr int TSEGS = BN * SEG_PER_COL / K::NT;
+    uint8_t* outt = (uint8_t*)p.outT;
+#pragma unroll 2
+    for (int i = 0; i < TSEGS; ++i) {
+      const int q = tid + i * K::NT;
+      const int c = q % BN, rs = q / BN;
+      u32x4 v;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint8_t* e = et + (rs * 16 + 4 * w) * K::EST + c;
+        v[w] = (unsigned)e[0] | ((unsigned)e[K::EST] << 8) | ((unsigned)e[2 * K::EST] << 16) |
+               ((unsigned)e[3 * K::EST] << 24);
+      }
+      store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::NIB / 2, v);
+    }
+  }
+  if (p.count) {
+    __shared__ int red[K::NWAVES];
+    cnt = wave_sum(cnt);
+    if (lane == 0) red[wave] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long t = 0;
+#pragma unroll
+      for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
+      if (t) atomicAdd(p.ones + (p.step % kRing), t);
+    }
+  }
+}
+
+template <class Op, int BM, int BN, int WM, int WN, int KB, int NSTAGE>
+static hipError_t launch_dma(const NTParams& p, hipStream_t s) {
+  typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
+  const int grid = p.tiles_m * p.tiles_n;
+  hipLaunchKernelGGL((k_nt_dma<BM, BN, WM, WN, KB, Op, NSTAGE>), dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p);
+  return hipGetLastError();
+}
+
+template <class Op, int BM, int BN, int WM, int WN, int KB, int NSTAGE>
+static hipError_t set_lds_attr_dma() {
+  typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
+  return hipFuncSetAttribute((const void*)k_nt_dma<BM, BN, WM, WN, KB, Op, NSTAGE>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)K::LDS_BYTES);
+}
+
 // ----------------------------------------------------------------- configurations
 // cfg 0: 256x256 tile, 8 waves of 128x64 (large n)
 // cfg 1: 128x128 tile, 4 waves of 64x64  (medium n)
 // cfg 2: 64x64 tile,   4 waves of 32x32  (small n)
 
-template <class Op, int BM, int BN, int WM, int WN, int KB>
+template <class Op, int BM, int BN, int WM, int WN, int KB, int SWZ = (KB == 64 ? 2 : 1), int PREF = 1>
 static hipError_t launch_cfg(const NTParams& p, hipStream_t s) {
-  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
+  typedef NTKernel<BM, BN, WM, WN, KB, Op, SWZ, PREF> K;
   const int grid = p.tiles_m * p.tiles_n;
-  hipLaunchKernelGGL((k_nt_step<BM, BN, WM, WN, KB, Op>), dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p);
+  hipLaunchKernelGGL((k_nt_step<BM, BN, WM, WN, KB, Op, SWZ, PREF>), dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p);
   return hipGetLastError();
 }
 
-template <class Op, int BM, int BN, int WM, int WN, int KB>
+template <class Op, int BM, int BN, int WM, int WN, int KB, int SWZ = (KB == 64 ? 2 : 1), int PREF = 1>
 static hipError_t set_lds_attr() {
-  typedef NTKernel<BM, BN, WM, WN, KB, Op> K;
-  return hipFuncSetAttribute((const void*)k_nt_step<BM, BN, WM, WN, KB, Op>,
+  typedef NTKernel<BM, BN, WM, WN, KB, Op, SWZ, PREF> K;
+  return hipFuncSetAttribute((const void*)k_nt_step<BM, BN, WM, WN, KB, Op, SWZ, PREF>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)K::LDS_BYTES);
 }
 
+// Large tiles: 256x256 per workgroup, 16 waves of 64x64, 128-byte K slices
+// fetched straight into a 2-slice LDS ring (fp32: 64-byte slices, 4-slice
+// ring), picked by sweeping tile shapes, slice depths and ring sizes at
+// n = 8192.  Smaller problems use register-staged 128x128 or 64x64 tiles so
+// that enough workgroups exist to fill the 256 compute units.
+template <class Op>
+struct BigCfg {
+  static constexpr int KB = (Op::kPrec == P_F32) ? 64 : 128;
+  static constexpr int NS = (Op::kPrec == P_F32) ? 4 : 2;
+  typedef DmaKernel<256, 256, 64, 64, KB, Op, NS> K;
+};
+
 template <class Op>
 static hipError_t launch_op(int cfg, const NTParams& p, hipStream_t s) {
-  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   switch (cfg) {
-    case 0:
-      if constexpr (Op::CPL == 2) return hipErrorInvalidValue;
-      else return launch_cfg<Op, 256, 256, 128, 64, KBIG>(p, s);
-    case 1: return launch_cfg<Op, 128, 128, 64, 64, KBIG>(p, s);
-    default: return launch_cfg<Op, 64, 64, 32, 32, KBIG>(p, s);
+    case 0: return launch_dma<Op, 256, 256, 64, 64, BigCfg<Op>::KB, BigCfg<Op>::NS>(p, s);
+    case 1: return launch_cfg<Op, 128, 128, 64, 64, KSMALL>(p, s);
+    default: return launch_cfg<Op, 64, 64, 32, 32, KSMALL>(p, s);
   }
 }
 
 template <class Op>
 static hipError_t init_op() {
-  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   hipError_t e;
-  if constexpr (Op::CPL == 1)
-    if ((e = set_lds_attr<Op, 256, 256, 128, 64, KBIG>()) != hipSuccess) return e;
-  if ((e = set_lds_attr<Op, 128, 128, 64, 64, KBIG>()) != hipSuccess) return e;
-  return set_lds_attr<Op, 64, 64, 32, 32, KBIG>();
+  if ((e = set_lds_attr_dma<Op, 256, 256, 64, 64, BigCfg<Op>::KB, BigCfg<Op>::NS>()) != hipSuccess) return e;
+  if ((e = set_lds_attr<Op, 128, 128, 64, 64, KSMALL>()) != hipSuccess) return e;
+  return set_lds_attr<Op, 64, 64, 32, 32, KSMALL>();
 }
 
 template <class Op>
 static TileCfg cfg_of(int cfg) {
-  constexpr int KBIG = (Op::CPL == 2) ? 128 : 64;
+  constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   switch (cfg) {
-    case 0:
-      if constexpr (Op::CPL == 1) { typedef NTKernel<256, 256, 128, 64, KBIG, Op> K; return {256, 256, KBIG, K::NT, K::LDS_BYTES}; }
-      else return {0, 0, 0, 0, 0};
-    case 1: { typedef NTKernel<128, 128, 64, 64, KBIG, Op> K; return {128, 128, KBIG, K::NT, K::LDS_BYTES}; }
-    default: { typedef NTKernel<64, 64, 32, 32, KBIG, Op> K; return {64, 64, KBIG, K::NT, K::LDS_BYTES}; }
+    case 0: { typedef typename BigCfg<Op>::K K; return {256, 256, BigCfg<Op>::KB, K::NT, K::LDS_BYTES}; }
+    case 1: { typedef NTKernel<128, 128, 64, 64, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {128, 128, KSMALL, K::NT, K::LDS_BYTES}; }
+    default: { typedef NTKernel<64, 64, 32, 32, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {64, 64, KSMALL, K::NT, K::LDS_BYTES}; }
   }
 }
 
@@ -418,7 +761,8 @@ hipError_t bool_kernels_init() {
   if ((e = init_op<OpI8>()) != hipSuccess) return e;
   if ((e = init_op<OpF32>()) != hipSuccess) return e;
   if ((e = init_op<OpBF16>()) != hipSuccess) return e;
-  return init_op<OpFP8>();
+  if ((e = init_op<OpFP8>()) != hipSuccess) return e;
+  return init_op<OpFP4>();
 }
 
 TileCfg nt_config(int prec, int cfg) {
@@ -426,7 +770,8 @@ TileCfg nt_config(int prec, int cfg) {
     case P_I8: return cfg_of<OpI8>(cfg);
     case P_F32: return cfg_of<OpF32>(cfg);
     case P_BF16: return cfg_of<OpBF16>(cfg);
-    default: return cfg_of<OpFP8>(cfg);
+    case P_FP8: return cfg_of<OpFP8>(cfg);
+    default: return cfg_of<OpFP4>(cfg);
   }
 }
 
@@ -436,6 +781,7 @@ hipError_t launch_nt_step(int prec, int cfg, const NTParams& p, hipStream_t s) {
     case P_F32: return launch_op<OpF32>(cfg, p, s);
     case P_BF16: return launch_op<OpBF16>(cfg, p, s);
     case P_FP8: return launch_op<OpFP8>(cfg, p, s);
+    case P_FP4: return launch_op<OpFP4>(cfg, p, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -449,9 +795,9 @@ int64_t padded_size_for(int prec, int64_t n) {
 }
 
 int choose_nt_config(int prec, int64_t np) {
-  // enough workgroups to cover the 256 CUs before choosing the large tile;
-  // fp8 operands (two chunks per lane) exceed the register file at 256x256
-  if (prec != P_FP8 && (np / 256) * (np / 256) >= 256) return 0;
+  (void)prec;
+  // enough workgroups to cover the 256 CUs before choosing the large tile
+  if ((np / 256) * (np / 256) >= 256) return 0;
   if ((np / 128) * (np / 128) >= 128) return 1;
   return 2;
 }
@@ -465,7 +811,6 @@ __global__ void __launch_bounds__(256)
 k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, int8_t* AT8,
          uint8_t* Aop, uint8_t* ATop, unsigned long long* ones_slot) {
   __shared__ uint8_t tile[64][64 + 16];
-  constexpr int ES = elem_bytes(PREC);
   const int bi = blockIdx.y, bj = blockIdx.x;
   const int tid = threadIdx.x;
   const int r = tid >> 2, c0 = (tid & 3) * 16;
@@ -483,7 +828,7 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
   *(u32x4*)&tile[r][c0] = v;
   const int64_t off = (int64_t)gi * Np + bj * 64 + c0;
   if (A8) *(u32x4*)(A8 + off) = v;
-  if (Aop) store_bool16<PREC>(Aop + off * ES, v);
+  if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v);
   int cnt = popc16(v);
   __syncthreads();
   if (AT8 || ATop) {
@@ -494,7 +839,7 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
              ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
     const int64_t toff = (int64_t)(bj * 64 + r) * Np + bi * 64 + c0;
     if (AT8) *(u32x4*)(AT8 + toff) = t;
-    if (ATop) store_bool16<PREC>(ATop + toff * ES, t);
+    if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
   }
   if (ones_slot) {
     __shared__ int red[4];
@@ -518,7 +863,8 @@ hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np,
     case P_I8: hipLaunchKernelGGL(k_ingest<P_I8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
     case P_F32: hipLaunchKernelGGL(k_ingest<P_F32>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
     case P_BF16: hipLaunchKernelGGL(k_ingest<P_BF16>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
-    default: hipLaunchKernelGGL(k_ingest<P_FP8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    case P_FP8: hipLaunchKernelGGL(k_ingest<P_FP8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    default: hipLaunchKernelGGL(k_ingest<P_FP4>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
   }
   return hipGetLastError();
 }
@@ -526,7 +872,6 @@ hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np,
 // S = identity on the first n constants, zero elsewhere (diag(x, x) facts).
 template <int PREC>
 __global__ void __launch_bounds__(256) k_identity(uint8_t* S, int Np, int n) {
-  constexpr int ES = elem_bytes(PREC);
   const int row = blockIdx.y;
   const int c = (blockIdx.x * 256 + threadIdx.x) * 16;
   if (c >= Np) return;
@@ -535,7 +880,7 @@ __global__ void __launch_bounds__(256) k_identity(uint8_t* S, int Np, int n) {
     const int b = row - c;
     v[b >> 2] = 1u << (8 * (b & 3));
   }
-  store_bool16<PREC>(S + ((int64_t)row * Np + c) * ES, v);
+  store_bool16<PREC>(S + elem_offset(PREC, (int64_t)row * Np + c), v);
 }
 
 hipError_t launch_identity(int prec, void* S, int Np, int n, hipStream_t s) {
@@ -545,7 +890,8 @@ hipError_t launch_identity(int prec, void* S, int Np, int n, hipStream_t s) {
     case P_I8: hipLaunchKernelGGL(k_identity<P_I8>, grid, dim3(256), 0, s, p, Np, n); break;
     case P_F32: hipLaunchKernelGGL(k_identity<P_F32>, grid, dim3(256), 0, s, p, Np, n); break;
     case P_BF16: hipLaunchKernelGGL(k_identity<P_BF16>, grid, dim3(256), 0, s, p, Np, n); break;
-    default: hipLaunchKernelGGL(k_identity<P_FP8>, grid, dim3(256), 0, s, p, Np, n); break;
+    case P_FP8: hipLaunchKernelGGL(k_identity<P_FP8>, grid, dim3(256), 0, s, p, Np, n); break;
+    default: hipLaunchKernelGGL(k_identity<P_FP4>, grid, dim3(256), 0, s, p, Np, n); break;
   }
   return hipGetLastError();
 }
@@ -594,7 +940,8 @@ hipError_t launch_emit(int prec, const void* S, int Np, int transpose, int n, ui
     case P_I8: hipLaunchKernelGGL(k_emit<P_I8>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
     case P_F32: hipLaunchKernelGGL(k_emit<P_F32>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
     case P_BF16: hipLaunchKernelGGL(k_emit<P_BF16>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
-    default: hipLaunchKernelGGL(k_emit<P_FP8>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+    case P_FP8: hipLaunchKernelGGL(k_emit<P_FP8>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
+    default: hipLaunchKernelGGL(k_emit<P_FP4>, grid, dim3(256), 0, s, p, Np, transpose, n, R, ldr); break;
   }
   return hipGetLastError();
 }

@@ -8,13 +8,14 @@ namespace dl {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // Precision codes, identical to dl_prec in include/dl.h.
-enum Prec { P_I8 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3 };
+enum Prec { P_I8 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3, P_FP4 = 4 };
 
 // Slots of the per-step model-size ring kept on the device.  Step s of a
 // fixpoint accumulates the number of true entries of its iterate into
@@ -23,10 +24,14 @@ enum Prec { P_I8 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3 };
 constexpr int kRing = 4096;
 constexpr int kNotConverged = 0x7fffffff;
 
-// Bytes per operand element for each precision.
-__host__ __device__ constexpr int elem_bytes(int prec) {
-  return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1);
+// 4-bit units (nibbles) per operand element: fp4 packs two elements per
+// byte, element 2t in the low nibble of byte t.
+__host__ __device__ constexpr int elem_nibbles(int prec) {
+  return prec == P_F32 ? 8 : (prec == P_BF16 ? 4 : (prec == P_FP4 ? 1 : 2));
 }
+// Byte offset of element index e, and bytes of an Np x Np operand.
+__host__ __device__ constexpr int64_t elem_offset(int prec, int64_t e) { return e * elem_nibbles(prec) / 2; }
+__host__ __device__ constexpr int64_t mat_bytes(int prec, int64_t np) { return np * np * elem_nibbles(prec) / 2; }
 
 // Parameters of one boolean product step  out = [add + X * Y^T != 0].
 struct NTParams {

@@ -150,7 +150,7 @@ enum Mode { M_PLAIN = 0, M_SQUARE = 1, M_SG = 2 };
 int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R,
                  int64_t ldr, int prec, int32_t max_steps, int64_t* ones_out, int32_t* steps_out,
                  int32_t* converged_out, hipStream_t s) {
-  if (prec < P_I8 || prec > P_FP8) return fail(DL_EINVAL, "unknown precision");
+  if (prec < P_I8 || prec > P_FP4) return fail(DL_EINVAL, "unknown precision");
   if (max_steps < 0) return fail(DL_EINVAL, "max_steps < 0");
   int rc = set_device(c);
   if (rc) return rc;
@@ -163,9 +163,8 @@ int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, 
   }
   const int64_t Np = padded_size_for(prec, n);
   const int cfg = choose_nt_config(prec, Np);
-  const size_t es = (size_t)elem_bytes(prec);
   const size_t mat8 = (size_t)Np * Np;
-  const size_t matT = mat8 * es;
+  const size_t matT = (size_t)mat_bytes(prec, Np);
   // layout: [add int8][op0][op1][op2][op3]
   size_t need = mat8 + 4 * matT + 256;
   if ((rc = ensure_ws(c, need))) return rc;

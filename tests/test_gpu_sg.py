@@ -47,7 +47,7 @@ def test_reversed_orientation_is_identity(dl):
     assert np.array_equal(host(s), np.eye(n, dtype=np.uint8)) and iters == 2
 
 
-@pytest.mark.parametrize("prec", ["i8", "f32", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["i8", "f32", "bf16", "fp8", "fp4"])
 def test_precisions_random_relations(dl, prec):
     for n, seed, pe in ((80, 1, 0.03), (333, 2, 0.004)):
         p = dlgen.to_dense(n, dlgen.er_edges(n, pe, seed, self_loops=True))
@@ -73,3 +73,5 @@ def test_config_forest_n4096(dl):
         p = dlgen.to_dense(n, dlgen.forest_edges(n, seed))
         got = _check(dl, p, "i8", f"cfg4096 seed={seed}")
         assert np.array_equal(got, got.T)
+    p = dlgen.to_dense(n, dlgen.forest_edges(n, 0))
+    _check(dl, p, "fp4", "cfg4096 fp4")

@@ -15,7 +15,7 @@ from tests.gpu_util import announce, dev, gpu, host
 
 pytestmark = gpu
 
-PRECS = ["i8", "f32", "bf16", "fp8"]
+PRECS = ["i8", "f32", "bf16", "fp8", "fp4"]
 
 
 @pytest.fixture(scope="module")
@@ -162,6 +162,14 @@ def test_config_n8192_int8_square(dl, pname, p):
         _check_closure(dl, a, dl.DL_TC_SQUARE, "i8", f"cfg8192 p={pname} seed={seed}")
 
 
+@pytest.mark.parametrize("prec", ["fp4", "fp8", "bf16"])
+def test_config_n8192_square_variants(dl, prec):
+    """The low-precision squaring variants give the same model at n = 8192."""
+    n = 8192
+    a = dlgen.to_dense(n, dlgen.er_edges(n, 4.0 / n, 1))
+    _check_closure(dl, a, dl.DL_TC_SQUARE, prec, f"cfg8192 {prec}")
+
+
 def test_config_n8192_fp32_plain(dl):
     """The plain FP32 baseline at n = 8192 gives the same model (one seed per p)."""
     n = 8192
@@ -174,5 +182,5 @@ def test_tile_configs_sizes(dl):
     """Sizes that select each tile configuration, with ragged tails."""
     for n in (1500, 2100, 4001):
         a = dlgen.to_dense(n, dlgen.er_edges(n, 2.5 / n, n))
-        for prec in ("i8", "bf16"):
+        for prec in ("i8", "bf16", "fp4"):
             _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
