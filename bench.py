@@ -50,11 +50,21 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true", help="skip the once-measured variants")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests in the Poisson serving stream (0 skips serving)")
     ap.add_argument("--trace-summary", metavar="DB",
                     help="summarise a rocprofv3 --kernel-trace results database and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run three plain 1 GiB device copies (traffic-counter calibration) and exit")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
+                    help="per-launch HBM traffic of the step kernel from rocprofv3 --pmc CSVs and exit")
     args = ap.parse_args()
     if args.trace_summary:
         return trace_summary(args.trace_summary)
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -131,6 +141,11 @@ def main() -> int:
     if not args.no_extras:
         extras = run_extras(dl, ctx, graphs, outs, np, torch)
 
+    serving = None
+    if not args.no_extras and args.serve_requests > 0:
+        graphs_dev_release(graphs)
+        serving = run_serving(dl, torch, args.serve_requests)
+
     cpu = None if args.no_cpu else cpu_baseline(graphs, iters)
 
     line = {
@@ -151,11 +166,12 @@ def main() -> int:
         "frac_of_int8_peak": round(value / INT8_PEAK_TOPS, 4),
         "roofline": {"bound": "mfma", "kernel": "k_nt_dma<256,256,64,64,128,OpI8,2>",
                      "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(),
                      "launches": launches, "avg_kernel_ms": round(avg_kernel_ms, 4),
                      "ops_per_launch": 2.0 * N ** 3},
         "per_graph": per_graph,
         "extras": extras,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -238,31 +254,179 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
     return res
 
 
-def cpu_baseline(graphs, iters):
+def graphs_dev_release(graphs):
+    """Drop the device copies of the N = 8192 inputs (host copies stay)."""
+    for g in graphs:
+        g["dev"] = None
+    import torch
+
+    torch.cuda.empty_cache()
+    return []
+
+
+def run_serving(dl, torch, count: int, seed: int = 0):
+    """Serving stream: 70% closure / 30% same generation, n log-uniform in
+    [64, 2048], ER p = 3/n or random forests.  A closed-loop burst of
+    min(count, 2000) requests (all arriving at t = 0) measures the saturated
+    throughput; then `count` requests arrive as a Poisson process at 0.8x that
+    rate and are served with continuous batching.  Latency = completion -
+    arrival.  Relations are generated as edge lists on the host before the
+    run and densified on the device when a request is admitted."""
+    import numpy as np
+
+    import dlgen
+    from paper_1608_00139_amd.serve import run_stream
+
+    pool = 8 << 30
+
+    def prepare(reqs):
+        flat, offs = [], [0]
+        for r in reqs:
+            e = dlgen.request_edges(r)
+            flat.append(e[:, 0].astype(np.int64) * r.n + e[:, 1])
+            offs.append(offs[-1] + len(e))
+        idx = torch.from_numpy(np.concatenate(flat) if flat else np.zeros(0, np.int64)).cuda()
+        offs = np.array(offs)
+        bufs = {}
+
+        def make_input(r):
+            buf = bufs.get(r.n)
+            if buf is None:
+                buf = bufs[r.n] = torch.zeros(r.n * r.n, dtype=torch.uint8, device="cuda")
+            buf.zero_()
+            buf[idx[offs[r.rid]:offs[r.rid + 1]]] = 1
+            return buf.view(r.n, r.n)
+        return make_input
+
+    burst_n = min(count, 2000)
+    burst = dlgen.serving_stream(burst_n, seed, rate=0.0)
+    log(f"serving: closed-loop burst of {burst_n}")
+    mk = prepare(burst)
+    warm = dlgen.serving_stream(64, seed + 1, rate=0.0)
+    run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512)
+    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512)
+    sat = sb.summary()
+    rate = 0.8 * sat["req_per_s"]
+    stream = dlgen.serving_stream(count, seed, rate=rate)
+    log(f"serving: Poisson stream of {count} at {rate:.0f} req/s")
+    mk = prepare(stream)
+    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512)
+    ops = 0.0
+    for c in st.completions:
+        per_step = 2.0 if c.kind == 1 else 1.0
+        ops += per_step * 2.0 * ((c.n + 63) // 64 * 64) ** 3 * (c.iters - 1)
+    out = st.summary()
+    out.update({"offered_rate": round(rate, 1), "saturation": sat,
+                "eff_tops_padded": round(ops / st.wall / 1e12, 2),
+                "workload": f"{count} requests, 70% TC (ER p=3/n) / 30% SG (forest), n log-uniform [64, 2048], "
+                            f"Poisson arrivals at 0.8x the closed-loop saturation rate, int8 grouped steps"})
+    return out
+
+
+def cpu_baseline(graphs, iters, min_seconds: float = 10.0):
     """The CPU oracle (semi-naive bitset evaluation) on the host's cores.
 
-    Sample: the three seed-0 graphs of the workload (one per edge
-    probability), timed end to end in the oracle's C code.  Its rate is put
-    in the metric's unit by crediting it with the same algorithmic work the
-    GPU schedule performs on those graphs (2 N^3 per squaring product).
+    Sample: passes over the nine workload graphs, each pass timing the
+    oracle's C fixpoint on every graph, repeated until at least
+    `min_seconds` of CPU work; the single-thread oracle is timed on the
+    first graph of each probability as well.  The rate is put in the
+    metric's unit by crediting the oracle with the same algorithmic work
+    the GPU schedule performs on those graphs (2 N^3 per squaring product).
     """
     import oracle
 
-    sample = [(i, g) for i, g in enumerate(graphs) if g["seed"] == 0]
     t_total = 0.0
     work = 0.0
-    per = []
-    for i, g in sample:
-        log(f"cpu oracle p={g['p']}")
-        t0 = time.perf_counter()
-        _, _, it, _ = oracle.tc_seminaive(g["host"])
-        dt = time.perf_counter() - t0
-        t_total += dt
-        work += 2.0 * N ** 3 * (iters[i] - 1)
-        per.append({"p": g["p"], "seconds": round(dt, 3), "plain_rounds": it})
+    passes = 0
+    while t_total < min_seconds and passes < 50:
+        for i, g in enumerate(graphs):
+            t0 = time.perf_counter()
+            oracle.tc_seminaive(g["host"])
+            t_total += time.perf_counter() - t0
+            work += 2.0 * N ** 3 * (iters[i] - 1)
+        passes += 1
+        log(f"cpu oracle pass {passes}: {t_total:.1f} s")
     return {"value": round(work / t_total / 1e12, 3), "unit": "TOPS", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": "semi-naive TC on the three seed-0 graphs (p = 1/N, 4/N, 0.01), N=8192",
-            "seconds": round(t_total, 3), "per_graph": per}
+            "kind": "oracle",
+            "sample": f"{passes} passes of the semi-naive C oracle over all nine N=8192 graphs of the workload",
+            "seconds": round(t_total, 3), "graph_fixpoints": passes * len(graphs)}
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_1608_00139_amd", "csrc", "bool_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_nt_dma_i8_n8192_traffic.txt")
+
+
+def source_hash() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, or None if the kernel source changed since it was taken."""
+    try:
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_PROFILE) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_calibration() -> int:
+    """Three plain device copies of 1 GiB: read 1 GiB and write 1 GiB each."""
+    import torch
+
+    a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy calibration: 3 x (1 GiB read + 1 GiB write)")
+    return 0
+
+
+def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
+    """Per-launch HBM traffic of the int8 step kernel (k_nt_dma ... OpI8).
+
+    FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch; each is scaled
+    by the ratio of the true bytes of a plain 1 GiB copy to what the same
+    counter reads for that copy.  Launches that returned early (fixpoint
+    already reached) are excluded by a cut at 10% of the largest value.
+    """
+    import csv
+
+    def per_kernel(path, pred):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if pred(r["Kernel_Name"])]
+        cut = 0.1 * max(vals)
+        return [v for v in vals if v >= cut]
+
+    is_step = lambda k: "k_nt_dma" in k and "OpI8" in k
+    is_copy = lambda k: "copy" in k.lower() or "elementwise" in k
+    f = per_kernel(fetch_csv, is_step)
+    w = per_kernel(write_csv, is_step)
+    cf = per_kernel(cal_fetch_csv, is_copy)
+    cw = per_kernel(cal_write_csv, is_copy)
+    gib_kib = float(1 << 20)
+    ffac = gib_kib / (sum(cf) / len(cf))
+    wfac = gib_kib / (sum(cw) / len(cw))
+    fetch = sum(f) / len(f) * ffac * 1024
+    write = sum(w) / len(w) * wfac * 1024
+    algo = 3 * N * N + 2 * N * N
+    print("# HBM traffic per launch of the int8 step kernel at N=8192 (rocprofv3 --pmc)")
+    print(f"kernel: k_nt_dma<256,256,64,64,128,OpI8,2>")
+    print(f"kernel_source_sha256: {source_hash()}")
+    print(f"launches_counted: fetch={len(f)} write={len(w)}")
+    print(f"calibration_fetch_factor: {ffac:.4f}")
+    print(f"calibration_write_factor: {wfac:.4f}")
+    print(f"fetch_bytes_per_launch: {fetch:.0f}")
+    print(f"write_bytes_per_launch: {write:.0f}")
+    print(f"traffic_bytes_per_launch: {fetch + write:.0f}")
+    print(f"algorithmic_bytes_per_launch: {algo}  (X, Y, addend read; out, out^T written; int8)")
+    print(f"traffic_over_algorithmic: {(fetch + write) / algo:.3f}")
+    return 0
 
 
 def trace_summary(db_path: str) -> int:

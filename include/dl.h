@@ -58,7 +58,8 @@ typedef enum {
   DL_ENOMEM = 2,
   DL_EHIP = 3,
   DL_ENOCONV = 4,
-  DL_EUNSUPPORTED = 5
+  DL_EUNSUPPORTED = 5,
+  DL_EAGAIN = 6 /* batch: no free request slot or pool memory; fetch finished requests and retry */
 } dl_status;
 
 /* How the closure fixpoint is iterated. */
@@ -146,6 +147,52 @@ int dl_kernel_stats(dl_ctx* ctx, int kernel_class, int64_t* launches, double* to
  * lets callers size budgets.  kind: 0 = closure, 1 = same generation,
  * 2 = epsilon solve. */
 int64_t dl_padded_size(int64_t n, int kind, int prec);
+
+/* ---------------------------------------------------------------- batching
+ * Many independent fixpoints over uneven n, resident in one device pool and
+ * advanced together: every dl_batch_step is one grouped launch that moves
+ * each unfinished request forward by one product (a closure request by one
+ * repeated-squaring step R' = min1(A + R R), Sec. 8; a same-generation
+ * request by one of the two products T = min1(P S), S' = min1(I + T P^T),
+ * Sec. 7.2), followed by one read-back of the per-request model sizes.
+ * Requests may be submitted between any two steps (continuous batching).
+ * Arithmetic is int8 with int32 accumulation; results are identical to
+ * dl_tc(DL_TC_SQUARE) / dl_sg on the same relation.  All calls on one batch
+ * must use the same stream and one thread at a time. */
+typedef struct dl_batch dl_batch;
+
+/* pool_bytes of device memory hold the admitted requests (a request of n
+ * constants takes 5 Np^2 bytes for closure, 4 Np^2 for same generation,
+ * Np = n rounded up to 64); max_active (<= 4096) bounds the requests
+ * admitted and not yet fetched. */
+int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** batch);
+int dl_batch_destroy(dl_batch* batch);
+
+/* Admit a request: kind 0 = transitive closure, 1 = same generation; A is a
+ * device uint8 [n x lda] relation (1 <= n <= 16384), copied into the pool
+ * (the caller may reuse A after the stream reaches this point).  tag is an
+ * opaque caller value returned by dl_batch_poll.  *slot receives the
+ * request's slot.  DL_EAGAIN when no slot or pool memory is free. */
+int dl_batch_submit(dl_batch* batch, int kind, int64_t n, const uint8_t* A, int64_t lda, int64_t tag,
+                    int32_t* slot, void* stream);
+
+/* One round (blocks until its model sizes are read back).  *active receives
+ * the number of requests still running, *finished the number that finished
+ * in this round. */
+int dl_batch_step(dl_batch* batch, int32_t* active, int32_t* finished, void* stream);
+
+/* Up to cap finished requests since the last poll: their tags, slots and
+ * iteration counts (the dl_tc / dl_sg convention). */
+int dl_batch_poll(dl_batch* batch, int64_t* tags, int32_t* slots, int32_t* iters, int32_t cap,
+                  int32_t* count);
+
+/* Write the 0/1 model of a finished request into R (device uint8 [n x ldr];
+ * NULL to discard), report its number of true entries in *ones (may be
+ * NULL), and free the slot and its pool memory. */
+int dl_batch_fetch(dl_batch* batch, int32_t slot, uint8_t* R, int64_t ldr, int64_t* ones, void* stream);
+
+/* Occupancy: running requests, used slots, free pool bytes. */
+int dl_batch_info(dl_batch* batch, int32_t* active, int32_t* used_slots, size_t* pool_free_bytes);
 
 const char* dl_status_str(int status);
 const char* dl_last_error(void);

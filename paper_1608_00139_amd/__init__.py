@@ -22,8 +22,10 @@ __all__ = [
     "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
     "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound",
-    "dl_padded_size",
+    "dl_padded_size", "Batch", "DL_EAGAIN",
 ]
+
+DL_EAGAIN = 6
 
 DL_TC_PLAIN, DL_TC_SQUARE = 0, 1
 DL_I8, DL_F32, DL_BF16, DL_FP8, DL_FP4 = 0, 1, 2, 3, 4
@@ -68,6 +70,13 @@ def load() -> ctypes.CDLL:
         "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "dl_kernel_stats": ([vp, ctypes.c_int, pi64, ctypes.POINTER(dbl), ctypes.c_int], ctypes.c_int),
         "dl_padded_size": ([i64, ctypes.c_int, ctypes.c_int], i64),
+        "dl_batch_create": ([vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "dl_batch_destroy": ([vp], ctypes.c_int),
+        "dl_batch_submit": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
+        "dl_batch_step": ([vp, pi32, pi32, vp], ctypes.c_int),
+        "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
+        "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
+        "dl_batch_info": ([vp, pi32, pi32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "dl_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "dl_last_error": ([], ctypes.c_char_p),
     }
@@ -249,3 +258,74 @@ def dl_solve_eps(A: torch.Tensor, eps: float, want_x: bool = False, out: torch.T
 
 def dl_padded_size(n: int, kind: int, prec=DL_I8) -> int:
     return int(load().dl_padded_size(n, kind, _prec(prec)))
+
+
+class Batch:
+    """Continuous-batching handle (dl_batch_*): requests resident in one pool,
+    advanced together one product per dl_batch_step."""
+
+    TC, SG = 0, 1
+
+    def __init__(self, pool_bytes: int, max_active: int = 256, ctx: Context | None = None, stream=None):
+        lib = load()
+        self.ctx = _ctx(ctx)
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        _check(lib.dl_batch_create(self.ctx.handle, self.ctx.device, int(pool_bytes), int(max_active),
+                                   ctypes.byref(self._h)))
+        self._cap = int(max_active)
+        self._tags = (ctypes.c_int64 * self._cap)()
+        self._slots = (ctypes.c_int32 * self._cap)()
+        self._iters = (ctypes.c_int32 * self._cap)()
+
+    def close(self) -> None:
+        if self._h:
+            load().dl_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dl_batch_submit(self, kind: int, A: torch.Tensor, tag: int) -> int | None:
+        """Admit a request; returns its slot, or None when the pool is full."""
+        n, lda = _mat(A, "A")
+        slot = ctypes.c_int32()
+        rc = load().dl_batch_submit(self._h, int(kind), n, ctypes.c_void_p(A.data_ptr()), lda, int(tag),
+                                    ctypes.byref(slot), _stream_ptr(self.stream))
+        if rc == DL_EAGAIN:
+            return None
+        _check(rc)
+        return int(slot.value)
+
+    def dl_batch_step(self) -> tuple[int, int]:
+        active = ctypes.c_int32()
+        fin = ctypes.c_int32()
+        _check(load().dl_batch_step(self._h, ctypes.byref(active), ctypes.byref(fin), _stream_ptr(self.stream)))
+        return int(active.value), int(fin.value)
+
+    def dl_batch_poll(self) -> list[tuple[int, int, int]]:
+        count = ctypes.c_int32()
+        _check(load().dl_batch_poll(self._h, self._tags, self._slots, self._iters, self._cap, ctypes.byref(count)))
+        return [(int(self._tags[i]), int(self._slots[i]), int(self._iters[i])) for i in range(count.value)]
+
+    def dl_batch_fetch(self, slot: int, out: torch.Tensor | None = None) -> int:
+        """Write the model of a finished request into `out` (or discard it);
+        returns its number of true entries and frees the slot."""
+        ones = ctypes.c_int64()
+        if out is None:
+            _check(load().dl_batch_fetch(self._h, int(slot), None, 0, ctypes.byref(ones), _stream_ptr(self.stream)))
+        else:
+            _, ldr = _mat(out, "R")
+            _check(load().dl_batch_fetch(self._h, int(slot), ctypes.c_void_p(out.data_ptr()), ldr,
+                                         ctypes.byref(ones), _stream_ptr(self.stream)))
+        return int(ones.value)
+
+    def dl_batch_info(self) -> tuple[int, int, int]:
+        a = ctypes.c_int32()
+        u = ctypes.c_int32()
+        f = ctypes.c_size_t()
+        _check(load().dl_batch_info(self._h, ctypes.byref(a), ctypes.byref(u), ctypes.byref(f)))
+        return int(a.value), int(u.value), int(f.value)

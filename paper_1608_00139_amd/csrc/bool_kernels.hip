@@ -280,20 +280,17 @@ struct NTKernel {
   static_assert(WM % FR == 0 && WN % FR == 0, "wave tile must hold whole fragments");
 };
 
-template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF = 1>
-__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
-k_nt_step(NTParams p) {
+// One BM x BN output tile at (row0, col0) of out = [add + X Y^T != 0];
+// its number of ones is added to *cnt_dst when cnt_dst is not null.  The
+// whole workgroup must call it (it synchronises through LDS).
+template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF>
+__device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
+                                        unsigned long long* cnt_dst, uint8_t* smem) {
   typedef NTKernel<BM, BN, WM, WN, KB, Op, SWZ, PREF> K;
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  if (step_is_done(p)) return;
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
-  const int row0 = tm * BM, col0 = tn * BN;
   const int64_t ldb = p.ld * K::NIB / 2;  // row pitch in bytes
   const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
   const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
@@ -449,7 +446,7 @@ k_nt_step(NTParams p) {
     }
   }
 
-  if (p.count) {
+  if (cnt_dst) {
     __shared__ int red[K::NWAVES];
     cnt = wave_sum(cnt);
     if (lane == 0) red[wave] = cnt;
@@ -458,10 +455,67 @@ k_nt_step(NTParams p) {
       unsigned long long t = 0;
 #pragma unroll
       for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
-      if (t) atomicAdd(p.ones + (p.step % kRing), t);
+      if (t) atomicAdd(cnt_dst, t);
     }
   }
 }
+
+template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF = 1>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+k_nt_step(NTParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
+  nt_tile<BM, BN, WM, WN, KB, Op, SWZ, PREF>(p, tm * BM, tn * BN, p.count ? p.ones + (p.step % kRing) : nullptr,
+                                             smem);
+}
+
+// ----------------------------------------------------------------- grouped step (serving)
+// One launch advances many independent fixpoints by one product each.  The
+// work list is the concatenation of every request's 64 x 64 output tiles;
+// desc[a].tile_start is the running tile count.  A persistent grid walks the
+// list with a stride of gridDim.x, so every workgroup ends after at most
+// ceil(total / gridDim.x) tiles.
+constexpr int kGroupTile = 64;
+
+__global__ void __launch_bounds__(256)
+k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  for (int item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+    int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].tile_start <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const GroupDesc& g = desc[lo];
+    const int local = item - g.tile_start;
+    const int tiles_n = g.Np / kGroupTile;
+    const int tm = local / tiles_n, tn = local % tiles_n;
+    NTParams p{};
+    p.X = g.X;
+    p.Y = g.Y;
+    p.ld = g.Np;
+    p.Np = g.Np;
+    p.add = g.add;
+    p.add_identity = g.add_identity;
+    p.n_valid = g.n_valid;
+    p.out = g.out;
+    p.outT = g.outT;
+    __syncthreads();  // the previous tile's epilogue is done with LDS
+    nt_tile<kGroupTile, kGroupTile, 32, 32, 64, OpI8, 2, 1>(p, tm * kGroupTile, tn * kGroupTile, g.cnt, smem);
+  }
+}
+
+hipError_t launch_group_step(const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
+  if (nreq <= 0 || total_tiles <= 0) return hipSuccess;
+  typedef NTKernel<kGroupTile, kGroupTile, 32, 32, 64, OpI8, 2, 1> K;
+  hipLaunchKernelGGL(k_group_step, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+  return hipGetLastError();
+}
+
+int group_tile() { return kGroupTile; }
 
 // ----------------------------------------------------------------- direct-to-LDS variant
 // Same product and epilogue as k_nt_step, but the K slices are fetched with
@@ -815,14 +869,23 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
   const int tid = threadIdx.x;
   const int r = tid >> 2, c0 = (tid & 3) * 16;
   const int gi = bi * 64 + r;
+  const int gj0 = bj * 64 + c0;
   u32x4 v = {0u, 0u, 0u, 0u};
   if (gi < n) {
-    const uint8_t* src = A + (int64_t)gi * lda + bj * 64 + c0;
+    const uint8_t* src = A + (int64_t)gi * lda + gj0;
+    if (gj0 + 16 <= n && (((uintptr_t)src) & 15) == 0) {
+      // whole 16-byte segment: fold each byte's bits into its bit 0
+      u32x4 x = *(const u32x4*)src;
+      x |= x >> 4;
+      x |= x >> 2;
+      x |= x >> 1;
+      v = x & 0x01010101u;
+    } else {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int gj = bj * 64 + c0 + t;
-      const unsigned b = (gj < n && src[t] != 0) ? 1u : 0u;
-      v[t >> 2] |= b << (8 * (t & 3));
+      for (int t = 0; t < 16; ++t) {
+        const unsigned b = (gj0 + t < n && src[t] != 0) ? 1u : 0u;
+        v[t >> 2] |= b << (8 * (t & 3));
+      }
     }
   }
   *(u32x4*)&tile[r][c0] = v;
@@ -905,12 +968,22 @@ k_emit(const uint8_t* __restrict__ S, int Np, int transpose, int n, uint8_t* R, 
   const int bi = blockIdx.y, bj = blockIdx.x;  // output tile (rows bi, cols bj)
   const int tid = threadIdx.x;
   if (!transpose) {
+    // thread -> (row, 16-element segment) of the 64 x 64 output tile
+    const int r = tid >> 2, c0 = (tid & 3) * 16;
+    const int gi = bi * 64 + r, gj0 = bj * 64 + c0;
+    if (gi < n) {
+      uint8_t* dst = R + (int64_t)gi * ldr + gj0;
+      if ((PREC == P_I8 || PREC == P_FP8) && gj0 + 16 <= n && (((uintptr_t)dst) & 15) == 0) {
+        u32x4 x = *(const u32x4*)(S + (int64_t)gi * Np + gj0);
+        x |= x >> 4;
+        x |= x >> 2;
+        x |= x >> 1;
+        *(u32x4*)dst = x & 0x01010101u;
+      } else {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int e = tid + t * 256;
-      const int r = e >> 6, c = e & 63;
-      const int gi = bi * 64 + r, gj = bj * 64 + c;
-      if (gi < n && gj < n) R[(int64_t)gi * ldr + gj] = (uint8_t)elem_nz<PREC>(S, (int64_t)gi * Np + gj);
+        for (int t = 0; t < 16; ++t)
+          if (gj0 + t < n) dst[t] = (uint8_t)elem_nz<PREC>(S, (int64_t)gi * Np + gj0 + t);
+      }
     }
   } else {
     // read the source tile (rows bj, cols bi) coalesced, write transposed

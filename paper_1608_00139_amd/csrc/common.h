@@ -52,6 +52,21 @@ struct NTParams {
   int tiles_m, tiles_n; // grid in tiles
 };
 
+// One request's product in a grouped (serving) launch: 64 x 64 output
+// tiles of an Np x Np int8 product, Np a multiple of 64.
+struct GroupDesc {
+  const void* X;
+  const void* Y;
+  const int8_t* add;
+  void* out;
+  void* outT;
+  unsigned long long* cnt;  // ones of this product's output (null: do not count)
+  int Np;
+  int n_valid;
+  int add_identity;
+  int tile_start;  // first work-list index of this request
+};
+
 // Launch helpers implemented in bool_kernels.hip.
 struct TileCfg {
   int bm, bn, kb, threads;
@@ -74,5 +89,7 @@ hipError_t launch_ring_clear(unsigned long long* ones, int* conv, int s0, int co
 hipError_t launch_ring_set(unsigned long long* ones, int slot, unsigned long long value, hipStream_t s);
 hipError_t launch_row_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s);
 hipError_t bool_kernels_init();
+hipError_t launch_group_step(const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
+int group_tile();
 
 }  // namespace dl

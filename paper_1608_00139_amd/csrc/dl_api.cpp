@@ -42,6 +42,10 @@ struct EventPair {
 
 }  // namespace
 
+namespace dl {
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace dl
+
 struct dl_ctx {
   int device = 0;
   size_t budget = 0;
@@ -489,6 +493,7 @@ const char* dl_status_str(int status) {
     case DL_EHIP: return "DL_EHIP: HIP runtime error";
     case DL_ENOCONV: return "DL_ENOCONV: step cap reached";
     case DL_EUNSUPPORTED: return "DL_EUNSUPPORTED: unsupported method/precision";
+    case DL_EAGAIN: return "DL_EAGAIN: no free batch slot or pool memory";
     default: return "unknown status";
   }
 }

@@ -1,0 +1,369 @@
+// serve.cpp -- batched fixpoints for serving: many independent closure
+// (repeated squaring) and same-generation requests, resident in one device
+// pool, advanced together by one grouped launch per round.
+//
+// A request is admitted with dl_batch_submit (its relation is normalised into
+// pool buffers, padded to a multiple of 64).  Each dl_batch_step is one round:
+// every unfinished request advances by one product -- a closure request by one
+// squaring step R' = [A + R R], a same-generation request by one of the two
+// products of its step (T = [P S], then S' = [I + T P^T]) -- all in a single
+// persistent launch over the concatenated 64 x 64 tile lists.  The round ends
+// with one read-back of the per-request model sizes; a request whose model
+// size repeats is finished (its iteration count follows the same convention
+// as dl_tc/dl_sg) and can be fetched, which frees its slot and pool memory.
+// Requests can be submitted between any two rounds, so batching is
+// continuous at the granularity of one product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dl.h"
+#include "common.h"
+
+using namespace dl;
+
+extern "C" const char* dl_last_error(void);
+namespace dl {
+void set_last_error(const std::string& m);
+}
+
+namespace {
+
+int bfail(int st, const std::string& m) {
+  dl::set_last_error(m);
+  return st;
+}
+
+#define BHIP(expr)                                                          \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) return bfail(DL_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Req {
+  bool used = false, done = false;
+  int kind = 0;  // 0 closure, 1 same generation
+  int64_t n = 0, Np = 0;
+  int64_t tag = 0;
+  size_t off = 0, bytes = 0;  // pool region
+  uint8_t *add = nullptr, *b[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t computed = 0;     // highest iterate written on the device
+  int phase = 0;            // same generation: 0 = next launch is T = [P S], 1 = S' = [I + T P^T]
+  std::vector<int64_t> ones;  // model sizes known on the host, ones[k] for k <= known
+  int64_t iters = 0;
+  int cnt_index = -1;       // index into the round counter array of the last counted product
+  bool admit_count = false; // ones[1] pending from the ingest counter
+};
+
+}  // namespace
+
+struct dl_batch {
+  dl_ctx* ctx = nullptr;
+  int device = 0;
+  uint8_t* pool = nullptr;
+  size_t pool_bytes = 0;
+  std::map<size_t, size_t> free_list;  // offset -> size
+  std::vector<Req> req;
+  GroupDesc* d_desc = nullptr;  // device descriptors
+  GroupDesc* h_desc = nullptr;  // pinned host descriptors
+  unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max]
+  unsigned long long* h_cnt = nullptr;
+  int max_active = 0;
+  int grid = 1024;
+  std::vector<int> finished;  // slots finished and not yet polled
+};
+
+namespace {
+
+bool pool_alloc(dl_batch* b, size_t bytes, size_t* off) {
+  for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      b->free_list.erase(it);
+      if (rest) b->free_list[roff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(dl_batch* b, size_t off, size_t bytes) {
+  auto it = b->free_list.emplace(off, bytes).first;
+  auto next = std::next(it);
+  if (next != b->free_list.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    b->free_list.erase(next);
+  }
+  if (it != b->free_list.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      b->free_list.erase(it);
+    }
+  }
+}
+
+int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+size_t request_bytes(int kind, int64_t Np) {
+  const size_t m = (size_t)Np * Np;
+  return kind == 0 ? 5 * m : 4 * m;  // closure: A + R, R^T (two each); SG: P, S (two), T
+}
+
+// Detect the first repeat in the known model sizes.
+void settle(Req& r) {
+  for (int64_t k = 1; k < (int64_t)r.ones.size(); ++k)
+    if (r.ones[k] == r.ones[k - 1]) {
+      r.done = true;
+      r.iters = k;
+      return;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** out) {
+  if (!out || pool_bytes == 0 || max_active <= 0) return bfail(DL_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  (void)ctx;
+  dl_batch* b = new (std::nothrow) dl_batch();
+  if (!b) return bfail(DL_ENOMEM, "host allocation failed");
+  b->ctx = ctx;
+  b->device = device;
+  b->max_active = max_active;
+  b->req.resize(max_active);
+  auto fail_destroy = [&](int st) {
+    dl_batch_destroy(b);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipSetDevice(device)) != hipSuccess) return fail_destroy(bfail(DL_EHIP, "hipSetDevice"));
+  if ((e = bool_kernels_init()) != hipSuccess) return fail_destroy(bfail(DL_EHIP, "kernel attributes"));
+  if ((e = hipMalloc(&b->pool, pool_bytes)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail_destroy(bfail(DL_ENOMEM, "pool allocation failed"));
+  }
+  b->pool_bytes = pool_bytes;
+  b->free_list[0] = pool_bytes;
+  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * max_active)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * max_active, hipHostMallocDefault)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
+  if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
+  if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "pinned counter allocation failed"));
+  if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
+    return fail_destroy(bfail(DL_EHIP, "counter clear"));
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+  b->grid = cus * 4;
+  *out = b;
+  return DL_OK;
+}
+
+int dl_batch_destroy(dl_batch* b) {
+  if (!b) return DL_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  if (b->pool) (void)hipFree(b->pool);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->h_desc) (void)hipHostFree(b->h_desc);
+  if (b->d_cnt) (void)hipFree(b->d_cnt);
+  if (b->h_cnt) (void)hipHostFree(b->h_cnt);
+  delete b;
+  return DL_OK;
+}
+
+int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t lda, int64_t tag, int32_t* slot_out,
+                    void* stream) {
+  if (!b || !slot_out) return bfail(DL_EINVAL, "NULL argument");
+  if (kind != 0 && kind != 1) return bfail(DL_EINVAL, "kind must be 0 (closure) or 1 (same generation)");
+  if (n <= 0 || n > 16384 || !A || lda < n) return bfail(DL_EINVAL, "bad relation (1 <= n <= 16384, lda >= n)");
+  hipStream_t s = (hipStream_t)stream;
+  int slot = -1;
+  for (int i = 0; i < b->max_active; ++i)
+    if (!b->req[i].used) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return bfail(DL_EAGAIN, "no free request slot");
+  const int64_t Np = pad64(n);
+  const size_t bytes = request_bytes(kind, Np);
+  size_t off = 0;
+  if (!pool_alloc(b, bytes, &off)) return bfail(DL_EAGAIN, "pool memory exhausted");
+  BHIP(hipSetDevice(b->device));
+  Req& r = b->req[slot];
+  r = Req();
+  r.used = true;
+  r.kind = kind;
+  r.n = n;
+  r.Np = Np;
+  r.tag = tag;
+  r.off = off;
+  r.bytes = bytes;
+  uint8_t* base = b->pool + off;
+  const size_t m = (size_t)Np * Np;
+  r.ones.push_back(0);
+  unsigned long long* adm = b->d_cnt + b->max_active + slot;
+  if (kind == 0) {
+    r.add = base;
+    for (int i = 0; i < 4; ++i) r.b[i] = base + m * (1 + i);  // R0, R0T, R1, R1T
+    BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
+    BHIP(launch_ingest(P_I8, A, lda, (int)n, (int)Np, (int8_t*)r.add, nullptr, r.b[2], r.b[3], adm, s));
+    r.computed = 1;
+    r.admit_count = true;
+  } else {
+    for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // P, S0, S1, T
+    BHIP(launch_ingest(P_I8, A, lda, (int)n, (int)Np, nullptr, nullptr, r.b[0], nullptr, nullptr, s));
+    BHIP(launch_identity(P_I8, r.b[2], (int)Np, (int)n, s));
+    r.computed = 1;
+    r.ones.push_back(n);  // S^(1) = I: one fact diag(x, x) per constant
+  }
+  *slot_out = slot;
+  return DL_OK;
+}
+
+int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void* stream) {
+  if (!b) return bfail(DL_EINVAL, "NULL batch");
+  hipStream_t s = (hipStream_t)stream;
+  BHIP(hipSetDevice(b->device));
+  // build this round's work list
+  int na = 0, tiles = 0;
+  const int T = group_tile();
+  std::vector<int> slots;
+  for (int i = 0; i < b->max_active; ++i) {
+    Req& r = b->req[i];
+    if (!r.used || r.done) continue;
+    GroupDesc& g = b->h_desc[na];
+    std::memset(&g, 0, sizeof g);
+    g.Np = (int)r.Np;
+    g.n_valid = (int)r.n;
+    g.tile_start = tiles;
+    g.cnt = nullptr;
+    r.cnt_index = -1;
+    if (r.kind == 0) {
+      const int64_t t = r.computed + 1;  // iterate produced by this round
+      const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
+      g.X = r.b[2 * prev];
+      g.Y = r.b[2 * prev + 1];
+      g.add = (const int8_t*)r.add;
+      g.out = r.b[2 * cur];
+      g.outT = r.b[2 * cur + 1];
+      g.cnt = b->d_cnt + na;
+      r.cnt_index = na;
+    } else if (r.phase == 0) {
+      const int64_t t = r.computed + 1;
+      const int prev = (int)((t - 1) & 1);
+      g.X = r.b[0];
+      g.Y = r.b[1 + prev];
+      g.out = r.b[3];
+    } else {
+      const int64_t t = r.computed + 1;
+      const int cur = (int)(t & 1);
+      g.X = r.b[3];
+      g.Y = r.b[0];
+      g.add_identity = 1;
+      g.out = r.b[1 + cur];
+      g.cnt = b->d_cnt + na;
+      r.cnt_index = na;
+    }
+    tiles += (int)((r.Np / T) * (r.Np / T));
+    slots.push_back(i);
+    ++na;
+  }
+  if (na > 0) {
+    BHIP(launch_ring_clear(b->d_cnt, nullptr, 0, na, 0, s));
+    BHIP(hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(GroupDesc) * na, hipMemcpyHostToDevice, s));
+    BHIP(launch_group_step(b->d_desc, na, tiles, std::min(b->grid, tiles), s));
+  }
+  BHIP(hipMemcpyAsync(b->h_cnt, b->d_cnt, sizeof(unsigned long long) * 2 * b->max_active, hipMemcpyDeviceToHost, s));
+  BHIP(hipStreamSynchronize(s));
+  int finished = 0;
+  for (int a = 0; a < na; ++a) {
+    Req& r = b->req[slots[a]];
+    if (r.admit_count) {
+      r.ones.push_back((int64_t)b->h_cnt[b->max_active + slots[a]]);  // ones[1] = |A|
+      r.admit_count = false;
+    }
+    if (r.kind == 0) {
+      r.computed += 1;
+      r.ones.push_back((int64_t)b->h_cnt[r.cnt_index]);
+    } else if (r.phase == 0) {
+      r.phase = 1;
+    } else {
+      r.computed += 1;
+      r.phase = 0;
+      r.ones.push_back((int64_t)b->h_cnt[r.cnt_index]);
+    }
+    settle(r);
+    if (r.done) {
+      b->finished.push_back(slots[a]);
+      ++finished;
+    }
+  }
+  if (active_out) *active_out = na - finished;
+  if (finished_out) *finished_out = finished;
+  return DL_OK;
+}
+
+int dl_batch_poll(dl_batch* b, int64_t* tags, int32_t* slots, int32_t* iters, int32_t cap, int32_t* count) {
+  if (!b || !count || cap < 0) return bfail(DL_EINVAL, "bad poll arguments");
+  int c = 0;
+  while (c < cap && !b->finished.empty()) {
+    const int sl = b->finished.front();
+    b->finished.erase(b->finished.begin());
+    if (tags) tags[c] = b->req[sl].tag;
+    if (slots) slots[c] = sl;
+    if (iters) iters[c] = (int32_t)b->req[sl].iters;
+    ++c;
+  }
+  *count = c;
+  return DL_OK;
+}
+
+int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* ones_out, void* stream) {
+  if (!b || slot < 0 || slot >= b->max_active || !b->req[slot].used) return bfail(DL_EINVAL, "bad slot");
+  Req& r = b->req[slot];
+  if (!r.done) return bfail(DL_EINVAL, "request not finished");
+  if (R && ldr < r.n) return bfail(DL_EINVAL, "ldr < n");
+  hipStream_t s = (hipStream_t)stream;
+  BHIP(hipSetDevice(b->device));
+  if (R) {
+    // the fixpoint iterate r.iters lives in buffer r.iters % 2 of its kind
+    const uint8_t* src = r.kind == 0 ? r.b[2 * (int)(r.iters & 1)] : r.b[1 + (int)(r.iters & 1)];
+    BHIP(launch_emit(P_I8, src, (int)r.Np, 0, (int)r.n, R, ldr, s));
+    BHIP(hipStreamSynchronize(s));
+  }
+  if (ones_out) *ones_out = r.ones[r.iters];
+  pool_free(b, r.off, r.bytes);
+  r = Req();
+  return DL_OK;
+}
+
+int dl_batch_info(dl_batch* b, int32_t* active, int32_t* used_slots, size_t* pool_free_bytes) {
+  if (!b) return bfail(DL_EINVAL, "NULL batch");
+  int act = 0, used = 0;
+  for (auto& r : b->req) {
+    used += r.used;
+    act += r.used && !r.done;
+  }
+  size_t fr = 0;
+  for (auto& kv : b->free_list) fr += kv.second;
+  if (active) *active = act;
+  if (used_slots) *used_slots = used;
+  if (pool_free_bytes) *pool_free_bytes = fr;
+  return DL_OK;
+}
+
+}  // extern "C"

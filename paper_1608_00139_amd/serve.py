@@ -1,0 +1,108 @@
+"""Request loop over the batching C ABI: arrivals, admission by pool memory,
+one grouped step per round, retirement, latency accounting.
+
+Every product runs in the library's grouped kernel (dl_batch_step); this
+module only decides which requests are in the batch.  A request that arrives
+while others are on the GPU is admitted as soon as a slot and pool memory are
+free, and starts moving with the very next round.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import torch
+
+from . import Batch
+
+
+@dataclass
+class Completion:
+    tag: int
+    kind: int
+    n: int
+    iters: int
+    ones: int
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclass
+class StreamStats:
+    completions: list = field(default_factory=list)
+    rounds: int = 0
+    wall: float = 0.0
+    max_active: int = 0
+    eagain: int = 0
+
+    def summary(self) -> dict:
+        lat = sorted(c.latency for c in self.completions)
+        n = len(lat)
+
+        def pct(q):
+            return lat[min(n - 1, int(round(q * (n - 1))))] if n else None
+
+        return {"requests": n, "wall_s": round(self.wall, 4),
+                "req_per_s": round(n / self.wall, 1) if self.wall > 0 else None,
+                "p50_ms": round(pct(0.50) * 1e3, 3) if n else None,
+                "p99_ms": round(pct(0.99) * 1e3, 3) if n else None,
+                "mean_ms": round(sum(lat) / n * 1e3, 3) if n else None,
+                "rounds": self.rounds, "max_active": self.max_active, "admission_waits": self.eagain}
+
+
+def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool = False,
+               batch: Batch | None = None) -> tuple[StreamStats, dict]:
+    """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
+
+    make_input(req) returns the request's relation as a uint8 device tensor.
+    Returns the statistics and, if keep_results, {rid: (model tensor, iters)}.
+    """
+    b = batch or Batch(pool_bytes, max_active)
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    waiting: deque = deque()
+    inflight = {}  # slot -> (req, admitted time)
+    results = {}
+    stats = StreamStats()
+    t0 = time.perf_counter()
+    now = 0.0
+    while pending or waiting or inflight:
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.popleft())
+        while waiting:
+            req = waiting[0]
+            kind = Batch.TC if req.kind == "tc" else Batch.SG
+            slot = b.dl_batch_submit(kind, make_input(req), req.rid)
+            if slot is None:
+                if not inflight:
+                    raise RuntimeError(f"request {req.rid} (n={req.n}) does not fit an empty pool")
+                stats.eagain += 1
+                break
+            waiting.popleft()
+            inflight[slot] = (req, time.perf_counter() - t0)
+        if not inflight:
+            if pending:  # idle until the next arrival
+                while time.perf_counter() - t0 < pending[0].arrival:
+                    pass
+            continue
+        stats.max_active = max(stats.max_active, len(inflight))
+        b.dl_batch_step()
+        stats.rounds += 1
+        for tag, slot, iters in b.dl_batch_poll():
+            req, adm = inflight.pop(slot)
+            out = torch.empty((req.n, req.n), dtype=torch.uint8, device="cuda") if keep_results else None
+            ones = b.dl_batch_fetch(slot, out)
+            fin = time.perf_counter() - t0
+            stats.completions.append(Completion(tag, 0 if req.kind == "tc" else 1, req.n, iters, ones,
+                                                req.arrival, adm, fin))
+            if keep_results:
+                results[req.rid] = (out, iters)
+    torch.cuda.synchronize()
+    stats.wall = time.perf_counter() - t0
+    return stats, results
