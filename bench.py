@@ -54,6 +54,8 @@ def main() -> int:
                     help="requests in the Poisson serving stream (0 skips serving)")
     ap.add_argument("--trace-summary", metavar="DB",
                     help="summarise a rocprofv3 --kernel-trace results database and exit")
+    ap.add_argument("--eps-only", action="store_true",
+                    help="run only the fp64 epsilon solve on the p = 4/N, seed 0 graph (for kernel traces) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain 1 GiB device copies (traffic-counter calibration) and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
@@ -65,6 +67,8 @@ def main() -> int:
         return pmc_summary(*args.pmc_summary)
     if args.copy_calibration:
         return copy_calibration()
+    if args.eps_only:
+        return eps_only()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -233,12 +237,49 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
         nl, tms = ctx.kernel_stats(1, reset=True)
         eps_rows.append({"p": g["p"], "eps": eps, "time_ms": round(t * 1e3, 2),
                          "eff_tflops": round(8.0 / 3.0 * N ** 3 / t / 1e12, 2),
+                         "executed_tflops": round(3.0 * N ** 3 / t / 1e12, 2),
                          "threshold_errors_vs_int8_model": int((tmp != outs[i]).sum().item()),
-                         "trailing_update_launches": nl, "trailing_update_ms": round(tms, 2)})
+                         "update_launches": nl, "update_ms": round(tms, 2),
+                         "update_tflops": round(3.0 * N * N * (N - 128) / (tms * 1e-3) / 1e12, 2)
+                         if tms > 0 else None})
     res["eps_solve_fp64"] = eps_rows
 
-    # same generation, N = 4096 random forests
+    # plain FP32 iteration at N = 512, ER p = 2/N (time-to-fixpoint; launch bound)
     import dlgen
+
+    small = []
+    for seed in SEEDS:
+        a = torch.from_numpy(dlgen.to_dense(512, dlgen.er_edges(512, 2.0 / 512, seed))).cuda()
+        o = torch.empty_like(a)
+        dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
+        ts = []
+        for _ in range(5):
+            (_, it), t = timed(lambda: dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx))
+            ts.append(t)
+        t = statistics.median(ts)
+        small.append({"n": 512, "seed": seed, "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 3),
+                      "eff_tflops": round(2.0 * 512 ** 3 * (it - 1) / t / 1e12, 2)})
+    res["tc_plain_fp32_n512"] = small
+
+    # power-law digraph, N = 32768 (1 GiB int8 operands), repeated squaring
+    n = 32768
+    log("chung-lu n=32768")
+    e = dlgen.chung_lu_edges(n, 0)
+    a = torch.from_numpy(dlgen.to_dense(n, e)).cuda()
+    o = torch.empty_like(a)
+    cl = []
+    for prec_name, prec in (("i8", dl.DL_I8), ("fp4", dl.DL_FP4)):
+        dl.dl_tc(a, method=dl.DL_TC_SQUARE, prec=prec, out=o, ctx=ctx)
+        (_, it), t = timed(lambda: dl.dl_tc(a, method=dl.DL_TC_SQUARE, prec=prec, out=o, ctx=ctx))
+        cl.append({"n": n, "prec": prec_name, "edges": int(len(e)), "mean_out_degree": round(len(e) / n, 3),
+                   "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 2),
+                   "eff_tops": round(2.0 * n ** 3 * (it - 1) / t / 1e12, 1),
+                   "closure_density": round(float(o.sum(dtype=torch.int64).item()) / n ** 2, 6)})
+    res["tc_chung_lu_n32768"] = cl
+    del a, o
+    torch.cuda.empty_cache()
+
+    # same generation, N = 4096 random forests
 
     sg = []
     n = 4096
@@ -373,6 +414,26 @@ def measured_traffic():
     if fields.get("kernel_source_sha256", "").strip() != source_hash():
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def eps_only(reps: int = 3) -> int:
+    """fp64 epsilon solve on one N = 8192 graph (ER p = 4/N, seed 0), timed."""
+    import torch
+
+    import dlgen
+    import paper_1608_00139_amd as dl
+
+    a = dlgen.to_dense(N, dlgen.er_edges(N, 4.0 / N, 0))
+    ad = torch.from_numpy(a).cuda()
+    eps = 0.5 / (1.0 + float(a.sum(axis=1).max()))
+    out = torch.empty_like(ad)
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dl.dl_solve_eps(ad, eps, out=out)
+        torch.cuda.synchronize()
+        print(f"eps solve {r}: {(time.perf_counter() - t0) * 1e3:.2f} ms", flush=True)
+    return 0
 
 
 def copy_calibration() -> int:

@@ -1,24 +1,24 @@
 // eps_solve.hip -- the epsilon form of Sec. 4 (Proposition 1, Theorem 1):
 // X = (I - eps A)^-1 eps A in fp64, then R = [X > 0].
 //
-// Method: block Gaussian elimination without pivoting on the augmented matrix
-// W = [ I - eps A | eps A ]  (Np x 2Np, row-major), block size NB = 128, with
-// every diagonal block normalised to the identity:
+// Method: block Gauss-Jordan elimination without pivoting on the augmented
+// matrix W = [ I - eps A | eps A ]  (Np x 2Np, row-major), block size
+// NB = 128:
 //   for each block row k (rows K0 .. K0+NB):
-//     Dinv  = W_kk^-1                      (Gauss-Jordan, one workgroup)
-//     T     = Dinv * W[k, K0+NB : 2Np]     (fp64 MFMA product)
-//     W[below, K0+NB : 2Np] -= W[below, k] * T   (trailing update, fp64 MFMA)
-//     W[k, K0+NB : 2Np] = T
-// leaving a block upper-triangular system with identity diagonal blocks,
-// then back substitution, bottom block row first:
-//     W[0 : K0, Np : 2Np] -= W[0 : K0, k] * W[k, Np : 2Np]
-// after which the right half of W holds X.
+//     Dinv = W_kk^-1                                  (Gauss-Jordan, one workgroup)
+//     W[k, K0+NB :] = Dinv * W[k, K0+NB :]             (fp64 MFMA product, in place)
+//     W[i, K0+NB :] -= W[i, K0 : K0+NB] * W[k, K0+NB :]  for every block row i != k
+// Columns left of K0+NB are never touched again (they would hold the
+// identity and zeros), so after the last block the right half of W is X.
+// 3 Np^3 flops, almost all in one full-height product per block step.
 //
 // Why no pivoting: M = I - eps A has unit diagonal and off-diagonal entries
 // <= 0 with eps * (row sum of A) < 1 (Lemma 1's eps bound), so M is a
 // strictly diagonally dominant M-matrix; its Schur complements stay
 // M-matrices, their inverses are entrywise >= 0, and every update above adds
-// terms of one sign to the off-diagonal and right-hand-side entries.  Exact
+// terms of one sign to the off-diagonal and right-hand-side entries (rows
+// above the diagonal block hold entries <= 0 in the columns being
+// eliminated, just like the rows below).  Exact
 // zeros therefore stay exactly zero and positive entries never cancel:
 // thresholding at > 0 is exact except where a true value underflows fp64
 // (it is at least eps^L for a shortest path of length L, by the footnote to
@@ -37,17 +37,24 @@ namespace dl {
 constexpr int NB = 128;  // block size of the elimination
 
 // ----------------------------------------------------------------- fp64 MFMA GEMM
-// D = beta * C + alpha * A * B,  A: M x K, B: K x N, C/D: M x N, row-major.
-// M, N multiples of 128, K multiple of 16.  D may alias C (same element
-// read then written by the same lane); A and B must not overlap D.
+// D = C - A * B  (sub = 1)  or  D = A * B  (sub = 0);  A: M x K, B: K x N,
+// C/D: M x N, row-major.  128 x 128 output tiles, 4 waves of 64 x 64,
+// K slices of 16 double-buffered in LDS.  With sub = 1 the accumulators start
+// from C and A is negated on its way into LDS (exact), so C is read once at
+// the start of the tile and D written once at the end.  Row tiles at or after
+// skip_tile are shifted down by one, which leaves out the row tile skip_tile
+// (the diagonal block row of an elimination step; -1 = none).  D may alias C
+// (every element is read and written by the same lane); D may also alias B
+// when M = K = 128 and sub = 0 (each workgroup reads its whole B column panel
+// before writing it).  A must not overlap D.
 struct GemmArgs {
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
   const double* C; int64_t ldc;
   double* D; int64_t ldd;
-  int M, N, K;
-  double alpha;
-  int beta;  // 0 or 1
+  int M, N, K;      // M counts the rows computed (without the skipped tile)
+  int sub;
+  int skip_tile;
 };
 
 // Output coordinate of accumulator element `item` of lane `lane` for
@@ -57,31 +64,46 @@ __device__ inline void f64_acc_coord(int lane, int item, int& r, int& c) {
   c = lane & 15;
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool CINIT = true>
 __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2;   // 2 x 2 waves
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int PAD = 2;
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int tiles_n = g.N / BN;
+  const int tiles_m = g.M / BM;
   // column-major walk over tiles keeps one B column panel hot across rows
-  const int tm = blockIdx.x % (g.M / BM), tn = blockIdx.x / (g.M / BM);
-  (void)tiles_n;
+  int tm = blockIdx.x % tiles_m;
+  const int tn = blockIdx.x / tiles_m;
+  if (g.skip_tile >= 0 && tm >= g.skip_tile) ++tm;
   const int m0 = tm * BM, n0 = tn * BN;
 
   v4d acc[FM][FN];
+  if (CINIT && g.sub) {
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int r, c;
+          f64_acc_coord(lane, v, r, c);
+          acc[i][j][v] = g.C[(int64_t)(m0 + wm * WM + i * 16 + r) * g.ldc + n0 + wn * WN + j * 16 + c];
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
 
   constexpr int ACH = BM * BK / 2;   // 16-byte chunks of the A tile
   constexpr int BCH = BK * BN / 2;
   constexpr int AL = ACH / 256, BL = BCH / 256;
   static_assert(ACH % 256 == 0 && BCH % 256 == 0, "tile loads must divide evenly");
+  const double sgn = (CINIT && g.sub) ? -1.0 : 1.0;
   double2 ra[AL], rb[BL];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -97,42 +119,45 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
       rb[i] = *(const double2*)(g.B + (int64_t)(k0 + k) * g.ldb + n0 + nn);
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int q = tid + i * 256;
       const int row = q / (BK / 2), kk = (q % (BK / 2)) * 2;
-      As[kk][row] = ra[i].x;
-      As[kk + 1][row] = ra[i].y;
+      As[buf][kk][row] = sgn * ra[i].x;
+      As[buf][kk + 1][row] = sgn * ra[i].y;
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int q = tid + i * 256;
       const int k = q / (BN / 2), nn = (q % (BN / 2)) * 2;
-      *(double2*)&Bs[k][nn] = rb[i];
+      *(double2*)&Bs[buf][k][nn] = rb[i];
     }
   };
 
   const int g4 = lane >> 4, r16 = lane & 15;
+  const int nk = g.K / BK;
   gload(0);
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    __syncthreads();  // previous stage fully consumed
-    sstore();
-    __syncthreads();
-    if (k0 + BK < g.K) gload(k0 + BK);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[kk + g4][wm * WM + i * 16 + r16];
+      for (int i = 0; i < FM; ++i) af[i] = As[cur][kk + g4][wm * WM + i * 16 + r16];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[kk + g4][wn * WN + j * 16 + r16];
+      for (int j = 0; j < FN; ++j) bf[j] = Bs[cur][kk + g4][wn * WN + j * 16 + r16];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
   }
 
 #pragma unroll
@@ -143,10 +168,10 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
       for (int v = 0; v < 4; ++v) {
         int r, c;
         f64_acc_coord(lane, v, r, c);
-        const int gr = m0 + wm * WM + i * 16 + r, gc = n0 + wn * WN + j * 16 + c;
-        double x = g.alpha * acc[i][j][v];
-        if (g.beta) x += g.C[(int64_t)gr * g.ldc + gc];
-        g.D[(int64_t)gr * g.ldd + gc] = x;
+        const int64_t row = m0 + wm * WM + i * 16 + r, col = n0 + wn * WN + j * 16 + c;
+        double x = acc[i][j][v];
+        if (!CINIT && g.sub) x = g.C[row * g.ldc + col] - x;
+        g.D[row * g.ldd + col] = x;
       }
 }
 
@@ -160,48 +185,64 @@ static hipError_t dgemm(const GemmArgs& g, hipStream_t s) {
 
 // ----------------------------------------------------------------- diagonal block inverse
 // In-place Gauss-Jordan inversion of the NB x NB block at W (ld), written to
-// Dinv (ld NB).  1024 threads; thread t owns row t / 8 and the 16 columns
-// (t % 8) + 8 m.  Step p broadcasts row p and column p through LDS (double
-// buffered, one barrier per step):
+// Dinv (ld NB).  1024 threads; thread t owns row t / 8 and the 16 contiguous
+// columns 16 (t % 8) + m.  Step p broadcasts row p and column p through LDS
+// (double buffered, one barrier per step) and every thread then updates its
+// 16 entries without branches:
 //   row p:     a[p][j] /= a[p][p]  (j != p),   a[p][p] = 1 / a[p][p]
-//   other i:   a[i][j] -= a[i][p] a[p][j] / a[p][p]  (j != p),
+//   other i:   a[i][j] -= (a[i][p] / a[p][p]) a[p][j]  (j != p),
 //              a[i][p]  = -a[i][p] / a[p][p]
 __global__ void __launch_bounds__(1024) k_block_inverse(const double* W, int64_t ld, double* Dinv) {
-  __shared__ double rowbuf[2][NB];
+  __shared__ __attribute__((aligned(16))) double rowbuf[2][NB];
   __shared__ double colbuf[2][NB];
+  __shared__ double invbuf[2];
   const int t = threadIdx.x;
-  const int i = t >> 3, j0 = t & 7;
+  const int i = t >> 3, j0 = (t & 7) * 16;
   double a[16];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) a[m] = W[(int64_t)i * ld + j0 + 8 * m];
+  for (int m = 0; m < 16; m += 2) {
+    const double2 v = *(const double2*)(W + (int64_t)i * ld + j0 + m);
+    a[m] = v.x;
+    a[m + 1] = v.y;
+  }
   for (int p = 0; p < NB; ++p) {
     const int b = p & 1;
+    const bool owns_col = (p >> 4) == (t & 7);  // this thread holds column p of its row
     if (i == p) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) rowbuf[b][j0 + 8 * m] = a[m];
+      for (int m = 0; m < 16; m += 2) *(double2*)&rowbuf[b][j0 + m] = make_double2(a[m], a[m + 1]);
     }
-    if (j0 == (p & 7)) {
+    if (owns_col) {
+      double v = a[0];
 #pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (m == (p >> 3)) colbuf[b][i] = a[m];
+      for (int m = 1; m < 16; ++m) v = (m == (p & 15)) ? a[m] : v;
+      colbuf[b][i] = v;
+      if (i == p) invbuf[b] = 1.0 / v;  // one division per step
     }
     __syncthreads();
-    const double inv = 1.0 / rowbuf[b][p];
-    const double f = colbuf[b][i];
+    const double inv = invbuf[b];
+    if (i != p) {
+      // general rows: one fused multiply-add per entry
+      const double f = colbuf[b][i] * inv;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int j = j0 + 8 * m;
-      if (i == p) {
-        a[m] = (j == p) ? inv : a[m] * inv;
-      } else if (j == p) {
-        a[m] = -f * inv;
-      } else {
-        a[m] -= f * (rowbuf[b][j] * inv);
+      for (int m = 0; m < 16; m += 2) {
+        const double2 r = *(const double2*)&rowbuf[b][j0 + m];
+        a[m] = __builtin_fma(-f, r.x, a[m]);
+        a[m + 1] = __builtin_fma(-f, r.y, a[m + 1]);
       }
+      if (owns_col) {  // column p receives -a[i][p] / a[p][p]
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          if (m == (p & 15)) a[m] = -f;
+      }
+    } else {
+      // pivot row: scale by 1 / a[p][p]; the pivot itself becomes 1 / a[p][p]
+#pragma unroll
+      for (int m = 0; m < 16; ++m) a[m] = (j0 + m == p) ? inv : a[m] * inv;
     }
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m) Dinv[i * NB + j0 + 8 * m] = a[m];
+  for (int m = 0; m < 16; m += 2) *(double2*)&Dinv[i * NB + j0 + m] = make_double2(a[m], a[m + 1]);
 }
 
 // ----------------------------------------------------------------- setup / copy / emit
@@ -216,14 +257,6 @@ k_eps_init(const uint8_t* A, int64_t lda, int n, int Np, double eps, double* W) 
     W[i * ld + j] = (i == j ? 1.0 : 0.0) - eps * a;
     W[i * ld + Np + j] = eps * a;
   }
-}
-
-__global__ void __launch_bounds__(256)
-k_copy_rows(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols) {
-  const int r = blockIdx.y;
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < cols; c += gridDim.x * 256)
-    dst[(int64_t)r * ldd + c] = src[(int64_t)r * lds + c];
-  (void)rows;
 }
 
 __global__ void __launch_bounds__(256)
@@ -255,8 +288,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   const int64_t ldw = 2 * Np;
   const size_t wbytes = (size_t)Np * ldw * sizeof(double);
   const size_t dbytes = (size_t)NB * NB * sizeof(double);
-  const size_t tbytes = (size_t)NB * ldw * sizeof(double);
-  const size_t need = wbytes + dbytes + tbytes;
+  const size_t need = wbytes + dbytes;
   if (need > ws->size) {
     if (budget_left && need > budget_left) {
       *err = "epsilon-solve workspace of " + std::to_string(need) + " bytes exceeds the budget";
@@ -274,7 +306,6 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   }
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Np * ldw;
-  double* T = Dinv + (size_t)NB * NB;
   hipError_t e;
 #define EPS_CK(x, what)            \
   do {                             \
@@ -296,30 +327,23 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
     const int cols = (int)(ldw - K0 - NB);  // columns right of the diagonal block
     hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, s, W + K0 * ldw + K0, ldw, Dinv);
     EPS_CK(hipGetLastError(), "block inverse");
-    GemmArgs rp{Dinv, NB, W + K0 * ldw + K0 + NB, ldw, nullptr, 0, T, ldw, NB, cols, NB, 1.0, 0};
+    // normalise block row k in place: W[k, K0+NB :] = Dinv * W[k, K0+NB :]
+    GemmArgs rp{Dinv, NB, W + K0 * ldw + K0 + NB, ldw, nullptr, 0, W + K0 * ldw + K0 + NB, ldw, NB, cols, NB, 0, -1};
     EPS_CK(dgemm(rp, s), "row panel product");
-    const int below = (int)(Np - K0 - NB);
-    if (below > 0) {
-      GemmArgs tu{W + (K0 + NB) * ldw + K0, ldw, T, ldw, W + (K0 + NB) * ldw + K0 + NB, ldw,
-                  W + (K0 + NB) * ldw + K0 + NB, ldw, below, cols, NB, -1.0, 1};
+    // eliminate block column k from every other block row
+    if (nblk > 1) {
+      GemmArgs tu{W + K0, ldw, W + K0 * ldw + K0 + NB, ldw, W + K0 + NB, ldw, W + K0 + NB, ldw,
+                  (int)(Np - NB), cols, NB, 1, k};
       hipEvent_t ea = nullptr, eb = nullptr;
       if (timing && hipEventCreate(&ea) == hipSuccess && hipEventCreate(&eb) == hipSuccess) {
         (void)hipEventRecord(ea, s);
       }
-      EPS_CK(dgemm(tu, s), "trailing update");
+      EPS_CK(dgemm(tu, s), "elimination update");
       if (ea && eb) {
         (void)hipEventRecord(eb, s);
         evs.push_back({ea, eb});
       }
     }
-    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((cols + 255) / 256), NB), dim3(256), 0, s, T, ldw,
-                       W + K0 * ldw + K0 + NB, ldw, NB, cols);
-    EPS_CK(hipGetLastError(), "row panel copy");
-  }
-  for (int k = nblk - 1; k >= 1; --k) {
-    const int64_t K0 = (int64_t)k * NB;
-    GemmArgs bs{W + K0, ldw, W + K0 * ldw + Np, ldw, W + Np, ldw, W + Np, ldw, (int)K0, (int)Np, NB, -1.0, 1};
-    EPS_CK(dgemm(bs, s), "back substitution");
   }
   hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
                      (int)n, R, ldr, X_out, ldx);

@@ -184,3 +184,20 @@ def test_tile_configs_sizes(dl):
         a = dlgen.to_dense(n, dlgen.er_edges(n, 2.5 / n, n))
         for prec in ("i8", "bf16", "fp4"):
             _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
+
+
+def test_config_chung_lu_n32768(dl):
+    """Power-law digraph (Chung-Lu, gamma 2.1, mean out-degree 8), n = 32768:
+    int8 repeated squaring on 1 GiB matrices, the whole model compared.
+    The squaring count follows from the plain count: D = plain iters - 1."""
+    n = 32768
+    a = dlgen.to_dense(n, dlgen.chung_lu_edges(n, 0))
+    announce("chung-lu 32768")
+    r, iters = dl.dl_tc(dev(a), method=dl.DL_TC_SQUARE, prec="i8")
+    ref, ones, it_plain, _ = oracle.tc_seminaive(a)
+    got = host(r)
+    del r
+    assert int((got != ref).sum()) == 0
+    d = it_plain - 1
+    assert iters == (1 if d == 0 else 2 + int(np.ceil(np.log2(d))) if d > 1 else 2)
+    assert int(got.sum()) == int(ones[-1])
