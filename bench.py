@@ -292,6 +292,22 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
                    "eff_tops": round(2 * 2.0 * n ** 3 * (it - 1) / t / 1e12, 1),
                    "model_size": int(s.sum().item())})
     res["sg_n4096"] = sg
+
+    # same generation, epsilon form (fp64 Smith doubling), N = 4096 forests
+    sge = []
+    for seed in SEEDS:
+        ph = dlgen.to_dense(n, dlgen.forest_edges(n, seed))
+        p = torch.from_numpy(ph).cuda()
+        ref = torch.empty_like(p)
+        dl.dl_sg(p, prec=dl.DL_I8, out=ref, ctx=ctx)
+        s = torch.empty_like(p)
+        d = int(ph.sum(axis=1).max())
+        eps = 1.0 / (1 + d * d)
+        (_, _, dbl), t = timed(lambda: dl.dl_sg_eps(p, eps, out=s, ctx=ctx))
+        sge.append({"n": n, "seed": seed, "eps": eps, "doublings": dbl, "time_ms": round(t * 1e3, 2),
+                    "executed_tflops": round(6.0 * n ** 3 * dbl / t / 1e12, 2),
+                    "threshold_errors_vs_int8_model": int((s != ref).sum().item())})
+    res["sg_eps_fp64_n4096"] = sge
     return res
 
 

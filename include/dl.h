@@ -129,6 +129,20 @@ int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* 
 int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double eps, uint8_t* R,
                  int64_t ldr, double* X, int64_t ldx, int32_t* iters, void* stream);
 
+/* Same-generation epsilon form (Sec. 7.2): solves X = eps (I + P X P^T), a
+ * discrete Sylvester (Stein) equation (Sec. 6.3), in fp64 by Smith's
+ * doubling (X += A X A^T, A = A A, from X = eps I and A = sqrt(eps) P) until
+ * a doubling adds no positive entry (and, when X is requested, changes no
+ * fp64 value), then writes S = [X > 0], the same-generation model
+ * (Theorem 2).
+ *   eps  must satisfy 0 < eps <= 1 / (1 + ||P||_inf^2), the bound the paper
+ *        derives from ||P kron P||_inf (Sec. 6.3, Sec. 7.2); else DL_EINVAL.
+ *   X    optional device double [n x ldx] for the real solution (NULL to skip).
+ *   doublings  host int32: number of doublings run (the last one confirms).
+ * Device workspace: 5 (n rounded up to 128)^2 * 8 bytes. */
+int dl_sg_eps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, double eps, uint8_t* S, int64_t lds,
+              double* X, int64_t ldx, int32_t* doublings, void* stream);
+
 /* Largest eps that Lemma 1 allows for A: 1 / (1 + max row sum).  Computed on
  * the device; host double out. */
 int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* eps_max,

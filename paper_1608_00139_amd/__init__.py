@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
-    "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound",
+    "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
     "dl_padded_size", "Batch", "DL_EAGAIN",
 ]
 
@@ -67,6 +67,7 @@ def load() -> ctypes.CDLL:
         "dl_sg_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, pi64, pi32, pi32, vp], ctypes.c_int),
         "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
         "dl_eps_bound": ([vp, i64, vp, i64, ctypes.POINTER(dbl), vp], ctypes.c_int),
+        "dl_sg_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
         "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "dl_kernel_stats": ([vp, ctypes.c_int, pi64, ctypes.POINTER(dbl), ctypes.c_int], ctypes.c_int),
         "dl_padded_size": ([i64, ctypes.c_int, ctypes.c_int], i64),
@@ -254,6 +255,22 @@ def dl_solve_eps(A: torch.Tensor, eps: float, want_x: bool = False, out: torch.T
                                ctypes.c_void_p(X.data_ptr()) if X is not None else None, ldx,
                                ctypes.byref(it), _stream_ptr(stream)))
     return R, X
+
+
+def dl_sg_eps(P: torch.Tensor, eps: float, want_x: bool = False, out: torch.Tensor | None = None,
+              ctx: Context | None = None, stream=None):
+    """Same-generation epsilon form: returns (S, X or None, doublings)."""
+    n, ldp = _mat(P, "P")
+    S = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=P.device)
+    _, lds = _mat(S, "S")
+    X = torch.empty((n, n), dtype=torch.float64, device=P.device) if want_x else None
+    d = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_sg_eps(c.handle, n, ctypes.c_void_p(P.data_ptr()), ldp, float(eps),
+                            ctypes.c_void_p(S.data_ptr()), lds,
+                            ctypes.c_void_p(X.data_ptr()) if X is not None else None, max(n, 1),
+                            ctypes.byref(d), _stream_ptr(stream)))
+    return S, X, int(d.value)
 
 
 def dl_padded_size(n: int, kind: int, prec=DL_I8) -> int:

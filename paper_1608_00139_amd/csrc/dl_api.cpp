@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <climits>
 #include <cstdio>
 #include <cstring>
@@ -460,6 +461,40 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
   if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
   ctx->ms[1] += tmsum;
   ctx->launches[1] += tcount;
+  return DL_OK;
+}
+
+int dl_sg_eps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, double eps, uint8_t* S, int64_t lds,
+              double* X, int64_t ldx, int32_t* doublings, void* stream) {
+  int rc = check_common(ctx, n, P, ldp, S, lds);
+  if (rc) return rc;
+  if (X && n > 0) {
+    if (ldx < n) return fail(DL_EINVAL, "ldx < n");
+    if (overlaps(X, mat_span(n, ldx) * sizeof(double), P, mat_span(n, ldp)) ||
+        overlaps(X, mat_span(n, ldx) * sizeof(double), S, mat_span(n, lds)))
+      return fail(DL_EINVAL, "X overlaps another matrix");
+  }
+  if (!(eps > 0.0)) return fail(DL_EINVAL, "eps must be positive");
+  if (doublings) *doublings = 0;
+  if (n == 0) return DL_OK;
+  double bound1 = 0.0;
+  if ((rc = dl_eps_bound(ctx, n, P, ldp, &bound1, stream))) return rc;
+  const double d = std::round(1.0 / bound1 - 1.0);  // max row sum of P (an integer)
+  const double bound = 1.0 / (1.0 + d * d);
+  if (eps > bound * (1.0 + 1e-15)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "eps = %.17g exceeds 1/(1+||P||_inf^2) = %.17g", eps, bound);
+    return fail(DL_EINVAL, buf);
+  }
+  std::string err;
+  int32_t dbl = 0;
+  int64_t pos = 0;
+  hipError_t e = dl::sg_eps_solve(&ctx->eps, ctx->budget, n, P, ldp, eps, S, lds, X, ldx, 64, (hipStream_t)stream,
+                                  &dbl, &pos, (unsigned long long*)(ctx->dscratch + 8), ctx->h_ring, &err);
+  if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
+  if (e == hipErrorNotReady) return fail(DL_ENOCONV, "doubling cap reached");
+  if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
+  if (doublings) *doublings = dbl;
   return DL_OK;
 }
 

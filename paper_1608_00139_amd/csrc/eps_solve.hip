@@ -37,15 +37,16 @@ namespace dl {
 constexpr int NB = 128;  // block size of the elimination
 
 // ----------------------------------------------------------------- fp64 MFMA GEMM
-// D = C - A * B  (sub = 1)  or  D = A * B  (sub = 0);  A: M x K, B: K x N,
-// C/D: M x N, row-major.  128 x 128 output tiles, 4 waves of 64 x 64,
-// K slices of 16 double-buffered in LDS.  With sub = 1 the accumulators start
-// from C and A is negated on its way into LDS (exact), so C is read once at
-// the start of the tile and D written once at the end.  Row tiles at or after
+// D = A * B (cmode 0), D = C - A * B (cmode 1) or D = C + A * B (cmode 2);
+// A: M x K, B: K x N, C/D: M x N, row-major.  128 x 128 output tiles, 4 waves
+// of 64 x 64, K slices of 16 double-buffered in LDS.  With cmode 1 or 2 the
+// accumulators start from C (for cmode 1, A is negated on its way into LDS,
+// which is exact), so C is read once at the start of the tile and D written
+// once at the end.  Row tiles at or after
 // skip_tile are shifted down by one, which leaves out the row tile skip_tile
 // (the diagonal block row of an elimination step; -1 = none).  D may alias C
 // (every element is read and written by the same lane); D may also alias B
-// when M = K = 128 and sub = 0 (each workgroup reads its whole B column panel
+// when M = K = 128 and cmode = 0 (each workgroup reads its whole B column panel
 // before writing it).  A must not overlap D.
 struct GemmArgs {
   const double* A; int64_t lda;
@@ -53,7 +54,7 @@ struct GemmArgs {
   const double* C; int64_t ldc;
   double* D; int64_t ldd;
   int M, N, K;      // M counts the rows computed (without the skipped tile)
-  int sub;
+  int cmode;
   int skip_tile;
 };
 
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
   const int m0 = tm * BM, n0 = tn * BN;
 
   v4d acc[FM][FN];
-  if (CINIT && g.sub) {
+  if (CINIT && g.cmode) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -103,7 +104,8 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
   constexpr int BCH = BK * BN / 2;
   constexpr int AL = ACH / 256, BL = BCH / 256;
   static_assert(ACH % 256 == 0 && BCH % 256 == 0, "tile loads must divide evenly");
-  const double sgn = (CINIT && g.sub) ? -1.0 : 1.0;
+  // with C in the accumulators, C - A B is computed as C + (-A) B
+  const double sgn = (CINIT && g.cmode == 1) ? -1.0 : 1.0;
   double2 ra[AL], rb[BL];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
         f64_acc_coord(lane, v, r, c);
         const int64_t row = m0 + wm * WM + i * 16 + r, col = n0 + wn * WN + j * 16 + c;
         double x = acc[i][j][v];
-        if (!CINIT && g.sub) x = g.C[row * g.ldc + col] - x;
+        if (!CINIT && g.cmode) x = g.C[row * g.ldc + col] + (g.cmode == 1 ? -x : x);
         g.D[row * g.ldd + col] = x;
       }
 }
@@ -360,6 +362,162 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   }
 #undef EPS_CK
   return hipSuccess;
+}
+
+// ----------------------------------------------------------------- same-generation epsilon form
+// X = eps (I + P X P^T) (Sec. 7.2; a discrete Sylvester / Stein equation,
+// Sec. 6.3), solved by Smith's doubling in fp64:
+//   X_0 = eps I_n,  A_0 = sqrt(eps) P,
+//   X_{j+1} = X_j + A_j X_j A_j^T,  A_{j+1} = A_j A_j,
+// so X_j = eps sum_{m < 2^j} (sqrt(eps) P)^m ((sqrt(eps) P)^T)^m.  Every term is
+// >= 0, so the zero pattern of X_j is exact: it is the set of pairs joined
+// by equal-length walks of length < 2^j to a common constant, i.e. the
+// same-generation iterate S^(2^j).  When a doubling leaves the number of
+// positive entries unchanged, S^(2^(j+1)) = S^(2^j) and the fixpoint is
+// reached (the series of iterates is monotone).  When the real solution is
+// wanted as well, doublings go on until one also leaves every fp64 value
+// unchanged (the increments shrink doubly exponentially, so the truncated
+// series is then within rounding of the limit).  A Schur-based Sylvester
+// solver would cancel terms and lose the exact zero pattern.
+__global__ void __launch_bounds__(256)
+k_sg_eps_init(const uint8_t* P, int64_t ldp, int n, int Np, double eps, double seps, double* X, double* A) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
+    const double p = (i < n && j < n && P[(int64_t)i * ldp + j] != 0) ? 1.0 : 0.0;
+    X[(int64_t)i * Np + j] = (i == j && i < n) ? eps : 0.0;
+    A[(int64_t)i * Np + j] = seps * p;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_transpose_f64(const double* src, double* dst, int Np) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) tile[r][tx] = src[(int64_t)(by + r) * Np + bx + tx];
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) dst[(int64_t)(bx + r) * Np + by + tx] = tile[tx][r];
+}
+
+// X += I (the doubling's increment) in place; counts the positive entries of
+// the new X into out[0] and the entries whose value changed into out[1].
+__global__ void __launch_bounds__(256)
+k_sg_accumulate(double* X, const double* I, int Np, unsigned long long* out) {
+  const int i = blockIdx.y;
+  int pos = 0, chg = 0;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
+    const int64_t o = (int64_t)i * Np + j;
+    const double x = X[o];
+    const double y = x + I[o];
+    pos += y > 0.0;
+    chg += y != x;
+    X[o] = y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    pos += __shfl_xor(pos, off, 64);
+    chg += __shfl_xor(chg, off, 64);
+  }
+  __shared__ int red[2][4];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = pos;
+    red[1][threadIdx.x >> 6] = chg;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+    if (t) atomicAdd(out + threadIdx.x, (unsigned long long)t);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_sg_eps_emit(const double* X, int Np, int n, uint8_t* S, int64_t lds, double* Xo, int64_t ldx) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
+    const double x = X[(int64_t)i * Np + j];
+    S[(int64_t)i * lds + j] = x > 0.0 ? 1 : 0;
+    if (Xo) Xo[(int64_t)i * ldx + j] = x;
+  }
+}
+
+hipError_t sg_eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* P, int64_t ldp, double eps,
+                        uint8_t* S, int64_t lds, double* X_out, int64_t ldx, int max_doublings, hipStream_t s,
+                        int32_t* doublings, int64_t* positives, unsigned long long* d_counter,
+                        unsigned long long* h_counter, std::string* err) {
+  const int64_t Np = eps_padded_size(n);
+  const size_t mat = (size_t)Np * Np * sizeof(double);
+  const size_t need = 5 * mat;
+  if (need > ws->size) {
+    if (budget_left && need > budget_left) {
+      *err = "same-generation epsilon workspace of " + std::to_string(need) + " bytes exceeds the budget";
+      return hipErrorOutOfMemory;
+    }
+    eps_free(ws);
+    hipError_t e = hipMalloc(&ws->buf, need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ws->buf = nullptr;
+      *err = "hipMalloc of " + std::to_string(need) + " bytes for the same-generation epsilon solve failed";
+      return hipErrorOutOfMemory;
+    }
+    ws->size = need;
+  }
+  double* X = (double*)ws->buf;
+  double* A = X + (size_t)Np * Np;
+  double* AT = A + (size_t)Np * Np;
+  double* T = AT + (size_t)Np * Np;
+  double* An = T + (size_t)Np * Np;
+  hipError_t e;
+#define SG_CK(x, what)             \
+  do {                             \
+    e = (x);                       \
+    if (e != hipSuccess) {         \
+      *err = what;                 \
+      return e;                    \
+    }                              \
+  } while (0)
+  const dim3 rows((unsigned)((Np + 255) / 256), (unsigned)Np);
+  const dim3 tgrid((unsigned)(Np / 32), (unsigned)(Np / 32));
+  hipLaunchKernelGGL(k_sg_eps_init, rows, dim3(256), 0, s, P, ldp, (int)n, (int)Np, eps, sqrt(eps), X, A);
+  SG_CK(hipGetLastError(), "init");
+  hipLaunchKernelGGL(k_transpose_f64, tgrid, dim3(256), 0, s, A, AT, (int)Np);
+  SG_CK(hipGetLastError(), "transpose");
+  int64_t prev = n;  // X_0 = eps I has n positive entries
+  int j = 0;
+  bool done = false;
+  while (!done && j < max_doublings) {
+    // An = A A;  T = A X;  I = T A^T (into A's buffer, free once T is
+    // formed);  X += I;  A <- An (and its transpose).
+    GemmArgs g1{A, Np, A, Np, nullptr, 0, An, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    SG_CK(dgemm(g1, s), "A A");
+    GemmArgs g2{A, Np, X, Np, nullptr, 0, T, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    SG_CK(dgemm(g2, s), "A X");
+    GemmArgs g3{T, Np, AT, Np, nullptr, 0, A, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    SG_CK(dgemm(g3, s), "T A^T");
+    SG_CK(hipMemsetAsync(d_counter, 0, 2 * sizeof(unsigned long long), s), "counter clear");
+    hipLaunchKernelGGL(k_sg_accumulate, rows, dim3(256), 0, s, X, A, (int)Np, d_counter);
+    SG_CK(hipGetLastError(), "accumulate");
+    std::swap(A, An);
+    hipLaunchKernelGGL(k_transpose_f64, tgrid, dim3(256), 0, s, A, AT, (int)Np);
+    SG_CK(hipGetLastError(), "transpose");
+    SG_CK(hipMemcpyAsync(h_counter, d_counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+          "readback");
+    SG_CK(hipStreamSynchronize(s), "sync");
+    ++j;
+    const int64_t c = (int64_t)h_counter[0];
+    const bool values_fixed = h_counter[1] == 0;
+    done = c == prev && (X_out == nullptr || values_fixed);
+    prev = c;
+  }
+  hipLaunchKernelGGL(k_sg_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, X, (int)Np,
+                     (int)n, S, lds, X_out, ldx);
+  SG_CK(hipGetLastError(), "threshold");
+  SG_CK(hipStreamSynchronize(s), "sync");
+  if (doublings) *doublings = j;
+  if (positives) *positives = prev;
+#undef SG_CK
+  return done ? hipSuccess : hipErrorNotReady;
 }
 
 }  // namespace dl
