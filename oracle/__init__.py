@@ -29,6 +29,12 @@ What it computes, each piece with the passage it follows:
 * ``sg_eps_kron`` -- the same-generation epsilon equation
   X = eps (I + R1 X R1^T) solved through the vec/Kronecker form of Sec. 6.3
   (O(n^6): tiny n only).
+* ``linear_solve`` -- the tail-recursive equation X = eps (C + B X) of
+  Sec. 6.1 as one fp64 LAPACK solve.
+* ``two_sided_kron`` -- the two-sided equation X = eps (Q + B X C) of
+  Sec. 6.3 through its vec/Kronecker form (tiny n only).
+* ``oracle.program`` -- layered evaluation of linear programs (its own
+  module header says what it follows).
 
 Conventions: relations are dense n x n arrays, row = first argument (Sec. 2),
 nonzero = true; results are uint8 0/1.  ``ones[k]`` is the number of true
@@ -294,4 +300,26 @@ def sg_eps_kron(p, eps: float) -> np.ndarray:
     k = np.kron(pm, pm)
     vec_i = np.eye(n).reshape(-1, order="F")
     x = np.linalg.solve(np.eye(n * n) - eps * k, eps * vec_i)
+    return x.reshape((n, n), order="F")
+
+
+def linear_solve(b, c, eps: float) -> np.ndarray:
+    """Tail-recursive equation X = eps (C + B X) (Sec. 6.1) as one fp64 LAPACK
+    solve of (I - eps B) X = eps C."""
+    bm = _as_u8(b).astype(np.float64)
+    cm = _as_u8(c).astype(np.float64)
+    n = bm.shape[0]
+    return np.linalg.solve(np.eye(n) - eps * bm, eps * cm)
+
+
+def two_sided_kron(q, b, c, eps: float) -> np.ndarray:
+    """Two-sided equation X = eps (Q + B X C) (Sec. 6.3) through
+    vec(X) = eps (vec(Q) + (C^T kron B) vec(X)), using vec(B X C) =
+    (C^T kron B) vec(X).  O(n^6): tiny n only."""
+    qm = _as_u8(q).astype(np.float64)
+    bm = _as_u8(b).astype(np.float64)
+    cm = _as_u8(c).astype(np.float64)
+    n = qm.shape[0]
+    k = np.kron(cm.T, bm)
+    x = np.linalg.solve(np.eye(n * n) - eps * k, eps * qm.reshape(-1, order="F"))
     return x.reshape((n, n), order="F")

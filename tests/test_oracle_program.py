@@ -214,3 +214,65 @@ def test_planted_mistake_ignoring_argument_order_fails(monkeypatch):
         ground = oracle.naive_tdb(_facts(rels, n), rules)
         bad += not np.array_equal(model["r2"], _matrix(ground, "r2", n))
     assert bad > 0
+
+
+# ---------------------------------------------------------------- the epsilon forms of Sec. 6
+
+
+def test_linear_solve_threshold_residual_and_rationals():
+    """X = eps (C + B X): [X > 0] = C + TC(B) C (the Boolean least solution,
+    from the closure oracle), residual at rounding level, and exact rational
+    elimination on tiny inputs."""
+    from fractions import Fraction
+
+    for seed in range(5):
+        n = 6 + 7 * seed
+        b = _rand(n, 2.0 / n, seed)
+        c = _rand(n, 1.5 / n, 50 + seed)
+        eps = 1.0 / (1 + int(b.sum(axis=1).max()))
+        x = oracle.linear_solve(b, c, eps)
+        tcb = oracle.tc_seminaive(b)[0].astype(np.int64)
+        want = ((c.astype(np.int64) + tcb @ c.astype(np.int64)) > 0).astype(np.uint8)
+        assert np.array_equal((x > 0).astype(np.uint8), want)
+        bf, cf = b.astype(np.float64), c.astype(np.float64)
+        assert np.abs(x - eps * (cf + bf @ x)).max() < 1e-14
+        if n <= 13:
+            e = Fraction(eps).limit_denominator(1000)
+            m = [[Fraction(int(i == j)) - e * int(b[i, j]) for j in range(n)] + [e * int(c[i, j]) for j in range(n)]
+                 for i in range(n)]
+            for k in range(n):  # plain Gauss-Jordan on rationals
+                piv = m[k][k]
+                m[k] = [v / piv for v in m[k]]
+                for i in range(n):
+                    if i != k and m[i][k] != 0:
+                        f = m[i][k]
+                        m[i] = [vi - f * vk for vi, vk in zip(m[i], m[k])]
+            exact = np.array([[float(m[i][n + j]) for j in range(n)] for i in range(n)])
+            assert np.allclose(x, exact, rtol=1e-13, atol=1e-16)
+
+
+TWO_SIDED_TEXT = "r(X,Z) :- q(X,Z).\nr(X,Z) :- b(X,Y), r(Y,W), c(W,Z)."
+
+
+def test_two_sided_kron_threshold_series_and_residual():
+    """X = eps (Q + B X C): [X > 0] equals the layered oracle's model of the
+    matching two-sided program, X equals the partial sums of
+    eps sum_m eps^m B^m Q C^m, and the residual is at rounding level."""
+    for seed in range(5):
+        n = 4 + seed
+        q = _rand(n, 0.2, seed)
+        b = _rand(n, 0.3, 20 + seed)
+        c = _rand(n, 0.3, 40 + seed)
+        nb = int(b.sum(axis=1).max())
+        nc = int(c.sum(axis=0).max())
+        eps = 1.0 / (1 + nb * nc)
+        x = oracle.two_sided_kron(q, b, c, eps)
+        model, _ = prog.evaluate(TWO_SIDED_TEXT, {"q": q, "b": b, "c": c}, n)
+        assert np.array_equal((x > 0).astype(np.uint8), model["r"])
+        qf, bf, cf = (m.astype(np.float64) for m in (q, b, c))
+        series, term = np.zeros((n, n)), eps * qf
+        for _ in range(4000):
+            series += term
+            term = eps * (bf @ term @ cf)
+        assert np.allclose(x, series, rtol=1e-10, atol=1e-15)
+        assert np.abs(x - eps * (qf + bf @ x @ cf)).max() < 1e-14
