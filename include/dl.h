@@ -143,6 +143,33 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
 int dl_sg_eps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, double eps, uint8_t* S, int64_t lds,
               double* X, int64_t ldx, int32_t* doublings, void* stream);
 
+/* Tail-recursive equation X = eps (C + B X) (Sec. 6.1, the equation of the
+ * tail recursive class with the lower-layer part already summed into C):
+ * solves (I - eps B) X = eps C in fp64 by the same block elimination as
+ * dl_solve_eps and writes R = [X > 0].  B = C = A is dl_solve_eps.
+ *   B, C  device uint8 [n x ldb], [n x ldc], nonzero = true.
+ *   eps   0 < eps <= 1 / (1 + ||B||_inf) (the theorem on layered evaluation
+ *         asks eps (C + B 1) <= 1 entrywise); else DL_EINVAL.
+ *   X     optional device double [n x ldx] (NULL to skip).
+ * Device workspace as dl_solve_eps. */
+int dl_solve_linear(dl_ctx* ctx, int64_t n, const uint8_t* B, int64_t ldb, const uint8_t* C, int64_t ldc,
+                    double eps, uint8_t* R, int64_t ldr, double* X, int64_t ldx, void* stream);
+
+/* Two-sided equation X = eps (Q + B X C) (Sec. 6.3, a discrete Sylvester /
+ * Stein equation; the transposed class of Sec. 6.2 reduces to it), solved in
+ * fp64 by Smith's doubling: X_0 = eps Q, B_0 = sqrt(eps) B, C_0 = sqrt(eps) C,
+ * X += B X C, B = B B, C = C C, until a doubling adds no positive entry (and,
+ * when X is requested, changes no fp64 value); writes R = [X > 0].  Every
+ * term is non-negative, so the zero pattern is exact up to fp64 underflow.
+ *   eps  0 < eps <= 1 / (1 + ||C||_1 ||B||_inf), the bound the paper derives
+ *        from ||C^T kron B||_inf (Sec. 6.3); else DL_EINVAL.
+ *   X    optional device double [n x ldx] (NULL to skip).
+ *   doublings  host int32: doublings run (the last one confirms).
+ * Device workspace: 6 (n rounded up to 128)^2 * 8 bytes. */
+int dl_solve_two_sided(dl_ctx* ctx, int64_t n, const uint8_t* Q, int64_t ldq, const uint8_t* B, int64_t ldb,
+                       const uint8_t* C, int64_t ldc, double eps, uint8_t* R, int64_t ldr, double* X, int64_t ldx,
+                       int32_t* doublings, void* stream);
+
 /* Largest eps that Lemma 1 allows for A: 1 / (1 + max row sum).  Computed on
  * the device; host double out. */
 int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* eps_max,
@@ -207,6 +234,67 @@ int dl_batch_fetch(dl_batch* batch, int32_t slot, uint8_t* R, int64_t ldr, int64
 
 /* Occupancy: running requests, used slots, free pool bytes. */
 int dl_batch_info(dl_batch* batch, int32_t* active, int32_t* used_slots, size_t* pool_free_bytes);
+
+/* ---------------------------------------------------------------- programs
+ * Layered evaluation of a linear binary Datalog program (Sec. 5, Sec. 6,
+ * stratified negation as in Sec. 8).  Syntax, one clause per '.':
+ *     head(X,Y) :- atom, atom, ... .      atom = [not] pred(V,W)
+ * Names of predicates start lower case, variables upper case; '%' starts a
+ * comment; "\+" may replace "not".  Every body must be a chain of atoms from
+ * the head's first variable to its second (each other variable in exactly two
+ * atoms); an atom may name its variables in either order (the converse
+ * relation).  eq is the built-in equality over the n constants.  Predicates
+ * that head no clause are given relations, bound with dl_program_bind.
+ * dl_program_create splits the predicates into strongly connected components
+ * of the dependency graph (Tarjan's algorithm) and orders them as layers; it
+ * returns DL_EUNSUPPORTED for a body that is not a chain, two atoms of the
+ * head's layer in one body (not linear) or a negated atom of the head's layer
+ * (not stratified), and DL_EINVAL for a syntax error.  Each layer is the
+ * system R_h = min1(A_h + sum P R_j^o S) of its heads (R^o = R or R^T).
+ * dl_program_run evaluates the layers in order on the device:
+ *   DL_EVAL_ITERATION  every recursive layer by the Boolean series from 0
+ *                      (int8 matrix products, Jacobi order, first repeat);
+ *   DL_EVAL_MATRIX     tail-recursive layers as one stacked fp64 linear
+ *                      system, a single two-sided or transposed clause as a
+ *                      Stein equation (fp64 doubling), other layers by the
+ *                      series; fp64 results are thresholded at > 0.
+ * Both give the least (perfect) model, the epsilon forms up to fp64
+ * underflow of long derivations.  A program handle is used by one thread at
+ * a time; its results stay on the device until the next run or destroy. */
+typedef struct dl_program dl_program;
+typedef enum { DL_EVAL_ITERATION = 0, DL_EVAL_MATRIX = 1 } dl_eval_method;
+typedef enum {
+  DL_FORM_NONRECURSIVE = 0,
+  DL_FORM_RIGHT_TAIL = 1, /* every recursive atom ends its chain: R = A + sum P R_j */
+  DL_FORM_LEFT_TAIL = 2,  /* every recursive atom starts its chain: R = A + sum R_j S */
+  DL_FORM_TWO_SIDED = 3,  /* one head, one clause P R^o S */
+  DL_FORM_GENERAL = 4
+} dl_layer_form;
+
+int dl_program_create(dl_ctx* ctx, const char* text, dl_program** prog);
+int dl_program_destroy(dl_program* prog);
+/* Number of predicates (given, defined and eq) and of layers. */
+int dl_program_counts(dl_program* prog, int32_t* n_predicates, int32_t* n_layers);
+/* Predicate `index`: its name (owned by the program), kind (0 given,
+ * 1 defined, 2 eq) and layer (-1 unless defined). */
+int dl_program_predicate(dl_program* prog, int32_t index, const char** name, int32_t* kind,
+                         int32_t* layer);
+/* Binds a given relation to device uint8 [n x ldm] (nonzero = true).  The
+ * pointer is read by the next dl_program_run; every relation has the same n. */
+int dl_program_bind(dl_program* prog, const char* name, int64_t n, const uint8_t* M, int64_t ldm);
+/* Evaluates every layer (blocks until done).  Device memory: two int8
+ * (n rounded up to 256)^2 matrices per predicate plus per-layer temporaries
+ * and the fp64 workspace of the epsilon forms. */
+int dl_program_run(dl_program* prog, int method, void* stream);
+/* Layer `layer` of the last run: its heads (predicate indices, up to cap),
+ * form (dl_layer_form), the method used and its count: iterations of the
+ * series (including the confirming one), doublings, or 0 for a linear solve. */
+int dl_program_layer(dl_program* prog, int32_t layer, int32_t* n_heads, int32_t* heads, int32_t cap,
+                     int32_t* form, int32_t* method_used, int32_t* iters);
+/* Writes the model of a defined predicate into device uint8 [n x ldo] and
+ * its number of true entries into *ones (may be NULL). */
+int dl_program_fetch(dl_program* prog, const char* name, uint8_t* out, int64_t ldo, int64_t* ones,
+                     void* stream);
 
 const char* dl_status_str(int status);
 const char* dl_last_error(void);

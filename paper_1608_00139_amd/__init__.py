@@ -22,10 +22,13 @@ __all__ = [
     "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
     "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
-    "dl_padded_size", "Batch", "DL_EAGAIN",
+    "dl_padded_size", "Batch", "DL_EAGAIN", "dl_solve_linear", "dl_solve_two_sided", "Program",
+    "DL_EVAL_ITERATION", "DL_EVAL_MATRIX",
 ]
 
 DL_EAGAIN = 6
+DL_EVAL_ITERATION, DL_EVAL_MATRIX = 0, 1
+FORMS = ("nonrecursive", "right_tail", "left_tail", "two_sided", "general")
 
 DL_TC_PLAIN, DL_TC_SQUARE = 0, 1
 DL_I8, DL_F32, DL_BF16, DL_FP8, DL_FP4 = 0, 1, 2, 3, 4
@@ -78,6 +81,17 @@ def load() -> ctypes.CDLL:
         "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
         "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
         "dl_batch_info": ([vp, pi32, pi32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "dl_solve_linear": ([vp, i64, vp, i64, vp, i64, dbl, vp, i64, vp, i64, vp], ctypes.c_int),
+        "dl_solve_two_sided": ([vp, i64, vp, i64, vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp],
+                               ctypes.c_int),
+        "dl_program_create": ([vp, ctypes.c_char_p, ctypes.POINTER(vp)], ctypes.c_int),
+        "dl_program_destroy": ([vp], ctypes.c_int),
+        "dl_program_counts": ([vp, pi32, pi32], ctypes.c_int),
+        "dl_program_predicate": ([vp, i32, ctypes.POINTER(ctypes.c_char_p), pi32, pi32], ctypes.c_int),
+        "dl_program_bind": ([vp, ctypes.c_char_p, i64, vp, i64], ctypes.c_int),
+        "dl_program_run": ([vp, ctypes.c_int, vp], ctypes.c_int),
+        "dl_program_layer": ([vp, i32, pi32, pi32, i32, pi32, pi32, pi32], ctypes.c_int),
+        "dl_program_fetch": ([vp, ctypes.c_char_p, vp, i64, pi64, vp], ctypes.c_int),
         "dl_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "dl_last_error": ([], ctypes.c_char_p),
     }
@@ -271,6 +285,119 @@ def dl_sg_eps(P: torch.Tensor, eps: float, want_x: bool = False, out: torch.Tens
                             ctypes.c_void_p(X.data_ptr()) if X is not None else None, max(n, 1),
                             ctypes.byref(d), _stream_ptr(stream)))
     return S, X, int(d.value)
+
+
+def dl_solve_linear(B: torch.Tensor, C: torch.Tensor, eps: float, want_x: bool = False,
+                    out: torch.Tensor | None = None, ctx: Context | None = None, stream=None):
+    """Tail-recursive equation X = eps (C + B X): returns (R, X or None), R = [X > 0]."""
+    n, ldb = _mat(B, "B")
+    nc, ldc = _mat(C, "C")
+    if nc != n:
+        raise ValueError("B and C differ in size")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=B.device)
+    _, ldr = _mat(R, "R")
+    X = torch.empty((n, n), dtype=torch.float64, device=B.device) if want_x else None
+    c = _ctx(ctx)
+    _check(load().dl_solve_linear(c.handle, n, ctypes.c_void_p(B.data_ptr()), ldb, ctypes.c_void_p(C.data_ptr()),
+                                  ldc, float(eps), ctypes.c_void_p(R.data_ptr()), ldr,
+                                  ctypes.c_void_p(X.data_ptr()) if X is not None else None, max(n, 1),
+                                  _stream_ptr(stream)))
+    return R, X
+
+
+def dl_solve_two_sided(Q: torch.Tensor, B: torch.Tensor, C: torch.Tensor, eps: float, want_x: bool = False,
+                       out: torch.Tensor | None = None, ctx: Context | None = None, stream=None):
+    """Two-sided equation X = eps (Q + B X C): returns (R, X or None, doublings)."""
+    n, ldq = _mat(Q, "Q")
+    nb, ldb = _mat(B, "B")
+    nc, ldc = _mat(C, "C")
+    if not n == nb == nc:
+        raise ValueError("Q, B and C differ in size")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=Q.device)
+    _, ldr = _mat(R, "R")
+    X = torch.empty((n, n), dtype=torch.float64, device=Q.device) if want_x else None
+    d = ctypes.c_int32()
+    c = _ctx(ctx)
+    _check(load().dl_solve_two_sided(c.handle, n, ctypes.c_void_p(Q.data_ptr()), ldq, ctypes.c_void_p(B.data_ptr()),
+                                     ldb, ctypes.c_void_p(C.data_ptr()), ldc, float(eps),
+                                     ctypes.c_void_p(R.data_ptr()), ldr,
+                                     ctypes.c_void_p(X.data_ptr()) if X is not None else None, max(n, 1),
+                                     ctypes.byref(d), _stream_ptr(stream)))
+    return R, X, int(d.value)
+
+
+class Program:
+    """A linear binary Datalog program evaluated layer by layer (dl_program_*).
+
+    ``Program(text)`` parses and layers the program; ``bind(name, M)`` gives a
+    relation (uint8 device matrix); ``run(method)`` evaluates; ``fetch(name)``
+    returns a defined relation; ``layers()`` describes the layers of the last
+    run.  Bound tensors must stay alive until ``run`` returns."""
+
+    def __init__(self, text: str, ctx: Context | None = None):
+        lib = load()
+        self.ctx = _ctx(ctx)
+        self._h = ctypes.c_void_p()
+        self._bound = {}
+        _check(lib.dl_program_create(self.ctx.handle, text.encode(), ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if self._h:
+            load().dl_program_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def predicates(self) -> list[tuple[str, int, int]]:
+        lib = load()
+        npred, nl = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.dl_program_counts(self._h, ctypes.byref(npred), ctypes.byref(nl)))
+        out = []
+        for i in range(npred.value):
+            name, kind, layer = ctypes.c_char_p(), ctypes.c_int32(), ctypes.c_int32()
+            _check(lib.dl_program_predicate(self._h, i, ctypes.byref(name), ctypes.byref(kind), ctypes.byref(layer)))
+            out.append((name.value.decode(), kind.value, layer.value))
+        return out
+
+    def bind(self, name: str, M: torch.Tensor) -> None:
+        n, ld = _mat(M, name)
+        _check(load().dl_program_bind(self._h, name.encode(), n, ctypes.c_void_p(M.data_ptr()), ld))
+        self._bound[name] = M
+
+    def run(self, method: int = DL_EVAL_ITERATION, stream=None) -> None:
+        _check(load().dl_program_run(self._h, int(method), _stream_ptr(stream)))
+
+    def layers(self) -> list[dict]:
+        lib = load()
+        names = [p[0] for p in self.predicates()]
+        npred, nl = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.dl_program_counts(self._h, ctypes.byref(npred), ctypes.byref(nl)))
+        out = []
+        for L in range(nl.value):
+            nh, form, meth, it = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            heads = (ctypes.c_int32 * max(1, npred.value))()
+            _check(lib.dl_program_layer(self._h, L, ctypes.byref(nh), heads, npred.value, ctypes.byref(form),
+                                        ctypes.byref(meth), ctypes.byref(it)))
+            out.append({"heads": sorted(names[heads[i]] for i in range(nh.value)),
+                        "form": FORMS[form.value] if form.value >= 0 else None,
+                        "method": meth.value, "iters": it.value})
+        return out
+
+    def fetch(self, name: str, out: torch.Tensor | None = None, n: int | None = None, stream=None):
+        """Returns (model, ones)."""
+        if out is None:
+            if n is None:
+                n = next(iter(self._bound.values())).shape[0] if self._bound else 0
+            out = torch.empty((n, n), dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        nn, ld = _mat(out, "out")
+        ones = ctypes.c_int64()
+        _check(load().dl_program_fetch(self._h, name.encode(), ctypes.c_void_p(out.data_ptr()), ld,
+                                       ctypes.byref(ones), _stream_ptr(stream)))
+        return out, int(ones.value)
 
 
 def dl_padded_size(n: int, kind: int, prec=DL_I8) -> int:

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libdl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["bool_kernels.hip", "eps_solve.hip", "dl_api.cpp", "serve.cpp"]
+SOURCES = ["bool_kernels.hip", "eps_solve.hip", "prog_kernels.hip", "dl_api.cpp", "serve.cpp", "program.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -42,7 +42,7 @@ def _compile(src: str, objdir: str) -> str:
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

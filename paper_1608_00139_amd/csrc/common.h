@@ -88,6 +88,12 @@ hipError_t launch_ring_clear(unsigned long long* ones, int* conv, int s0, int co
                              hipStream_t s);
 hipError_t launch_ring_set(unsigned long long* ones, int slot, unsigned long long value, hipStream_t s);
 hipError_t launch_row_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s);
+hipError_t launch_col_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s);
+// out = (a | b | [ident] I), or its complement within the n x n constants when
+// `complement` is set; int8 0/1 Np x Np operands (a, b, out, outT may be null;
+// out may alias a or b).  Adds the ones of the result to *cnt if cnt is set.
+hipError_t launch_bytes_op(const int8_t* a, const int8_t* b, int ident, int complement, int n, int Np, int8_t* out,
+                           int8_t* outT, unsigned long long* cnt, hipStream_t s);
 hipError_t bool_kernels_init();
 hipError_t launch_group_step(const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
 int group_tile();

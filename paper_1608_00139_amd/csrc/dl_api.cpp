@@ -13,6 +13,7 @@
 
 #include "../../include/dl.h"
 #include "common.h"
+#include "ctx.h"
 #include "eps_solve.h"
 
 using namespace dl;
@@ -37,32 +38,12 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
   } while (0)
 
-struct EventPair {
-  hipEvent_t a, b;
-};
-
 }  // namespace
 
 namespace dl {
 void set_last_error(const std::string& m) { g_last_error = m; }
 }  // namespace dl
 
-struct dl_ctx {
-  int device = 0;
-  size_t budget = 0;
-  void* ws = nullptr;  // main workspace
-  size_t ws_size = 0;
-  unsigned long long* ring = nullptr;  // device ring of model sizes (kRing slots)
-  int* conv = nullptr;                 // device convergence step
-  int* dscratch = nullptr;             // small device scratch (row max, ...)
-  unsigned long long* h_ring = nullptr;  // pinned host mirror of the ring
-  int* h_conv = nullptr;                 // pinned: conv step, scratch ints
-  bool timing = false;
-  int64_t launches[3] = {0, 0, 0};
-  double ms[3] = {0, 0, 0};
-  std::vector<EventPair> events;
-  dl::EpsWorkspace eps;  // workspace of the epsilon solve
-};
 
 namespace {
 
@@ -455,7 +436,7 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
   (void)launches_before;
   double tmsum = 0.0;
   int64_t tcount = 0;
-  hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, A, lda, eps, R, ldr, X, ldx, s, ctx->timing,
+  hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, A, lda, A, lda, eps, R, ldr, X, ldx, s, ctx->timing,
                                &tmsum, &tcount, &err);
   if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
   if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
@@ -491,6 +472,80 @@ int dl_sg_eps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, double eps,
   int64_t pos = 0;
   hipError_t e = dl::sg_eps_solve(&ctx->eps, ctx->budget, n, P, ldp, eps, S, lds, X, ldx, 64, (hipStream_t)stream,
                                   &dbl, &pos, (unsigned long long*)(ctx->dscratch + 8), ctx->h_ring, &err);
+  if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
+  if (e == hipErrorNotReady) return fail(DL_ENOCONV, "doubling cap reached");
+  if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
+  if (doublings) *doublings = dbl;
+  return DL_OK;
+}
+
+int dl_solve_linear(dl_ctx* ctx, int64_t n, const uint8_t* B, int64_t ldb, const uint8_t* C, int64_t ldc,
+                    double eps, uint8_t* R, int64_t ldr, double* X, int64_t ldx, void* stream) {
+  int rc = check_common(ctx, n, B, ldb, R, ldr);
+  if (rc) return rc;
+  if ((rc = check_common(ctx, n, C, ldc, R, ldr))) return rc;
+  if (X && n > 0) {
+    if (ldx < n) return fail(DL_EINVAL, "ldx < n");
+    const size_t xs = mat_span(n, ldx) * sizeof(double);
+    if (overlaps(X, xs, B, mat_span(n, ldb)) || overlaps(X, xs, C, mat_span(n, ldc)) ||
+        overlaps(X, xs, R, mat_span(n, ldr)))
+      return fail(DL_EINVAL, "X overlaps another matrix");
+  }
+  if (!(eps > 0.0)) return fail(DL_EINVAL, "eps must be positive");
+  if (n == 0) return DL_OK;
+  double bound = 0.0;
+  if ((rc = dl_eps_bound(ctx, n, B, ldb, &bound, stream))) return rc;
+  if (eps > bound) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "eps = %.17g exceeds 1/(1+||B||_inf) = %.17g", eps, bound);
+    return fail(DL_EINVAL, buf);
+  }
+  std::string err;
+  double tmsum = 0.0;
+  int64_t tcount = 0;
+  hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, B, ldb, C, ldc, eps, R, ldr, X, ldx, (hipStream_t)stream,
+                               false, &tmsum, &tcount, &err);
+  if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
+  if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
+  return DL_OK;
+}
+
+int dl_solve_two_sided(dl_ctx* ctx, int64_t n, const uint8_t* Q, int64_t ldq, const uint8_t* B, int64_t ldb,
+                       const uint8_t* C, int64_t ldc, double eps, uint8_t* R, int64_t ldr, double* X, int64_t ldx,
+                       int32_t* doublings, void* stream) {
+  int rc;
+  if ((rc = check_common(ctx, n, Q, ldq, R, ldr))) return rc;
+  if ((rc = check_common(ctx, n, B, ldb, R, ldr))) return rc;
+  if ((rc = check_common(ctx, n, C, ldc, R, ldr))) return rc;
+  if (X && n > 0) {
+    if (ldx < n) return fail(DL_EINVAL, "ldx < n");
+    const size_t xs = mat_span(n, ldx) * sizeof(double);
+    if (overlaps(X, xs, Q, mat_span(n, ldq)) || overlaps(X, xs, B, mat_span(n, ldb)) ||
+        overlaps(X, xs, C, mat_span(n, ldc)) || overlaps(X, xs, R, mat_span(n, ldr)))
+      return fail(DL_EINVAL, "X overlaps another matrix");
+  }
+  if (!(eps > 0.0)) return fail(DL_EINVAL, "eps must be positive");
+  if (doublings) *doublings = 0;
+  if (n == 0) return DL_OK;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // ||B||_inf (max row sum) and ||C||_1 (max column sum)
+  DL_HIP(hipMemsetAsync(ctx->dscratch, 0, 2 * sizeof(int), s));
+  DL_HIP(launch_row_max(B, ldb, (int)n, ctx->dscratch, s));
+  DL_HIP(launch_col_max(C, ldc, (int)n, ctx->dscratch + 1, s));
+  DL_HIP(hipMemcpyAsync(ctx->h_conv + 1, ctx->dscratch, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  DL_HIP(hipStreamSynchronize(s));
+  const double bound = 1.0 / (1.0 + (double)ctx->h_conv[1] * (double)ctx->h_conv[2]);
+  if (eps > bound * (1.0 + 1e-15)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "eps = %.17g exceeds 1/(1+||C||_1 ||B||_inf) = %.17g", eps, bound);
+    return fail(DL_EINVAL, buf);
+  }
+  std::string err;
+  int32_t dbl = 0;
+  hipError_t e = dl::two_sided_solve(&ctx->eps, ctx->budget, n, Q, ldq, B, ldb, C, ldc, eps, R, ldr, X, ldx, nullptr, 0,
+                                     nullptr, 64, s, &dbl, (unsigned long long*)(ctx->dscratch + 8), ctx->h_ring,
+                                     &err);
   if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
   if (e == hipErrorNotReady) return fail(DL_ENOCONV, "doubling cap reached");
   if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));

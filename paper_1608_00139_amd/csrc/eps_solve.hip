@@ -248,16 +248,18 @@ __global__ void __launch_bounds__(1024) k_block_inverse(const double* W, int64_t
 }
 
 // ----------------------------------------------------------------- setup / copy / emit
-// W[i][j] = [i == j] - eps a_ij  and  W[i][Np + j] = eps a_ij, padded rows and
+// W[i][j] = [i == j] - eps b_ij  and  W[i][Np + j] = eps c_ij, padded rows and
 // columns carry the identity and zeros.
-__global__ void __launch_bounds__(256)
-k_eps_init(const uint8_t* A, int64_t lda, int n, int Np, double eps, double* W) {
+__global__ void __launch_bounds__(256) k_eps_init(const uint8_t* B, int64_t ldb, const uint8_t* C, int64_t ldc,
+                                                  int n, int Np, double eps, double* W) {
   const int i = blockIdx.y;
   const int64_t ld = 2 * (int64_t)Np;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
-    const double a = (i < n && j < n && A[(int64_t)i * lda + j] != 0) ? 1.0 : 0.0;
-    W[i * ld + j] = (i == j ? 1.0 : 0.0) - eps * a;
-    W[i * ld + Np + j] = eps * a;
+    const bool in = i < n && j < n;
+    const double b = (in && B[(int64_t)i * ldb + j] != 0) ? 1.0 : 0.0;
+    const double c = (in && C[(int64_t)i * ldc + j] != 0) ? 1.0 : 0.0;
+    W[i * ld + j] = (i == j ? 1.0 : 0.0) - eps * b;
+    W[i * ld + Np + j] = eps * c;
   }
 }
 
@@ -281,49 +283,39 @@ void eps_free(EpsWorkspace* ws) {
   ws->size = 0;
 }
 
-hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* A, int64_t lda,
-                     double eps, uint8_t* R, int64_t ldr, double* X_out, int64_t ldx, hipStream_t s,
-                     bool timing, double* trailing_ms, int64_t* trailing_launches, std::string* err) {
-  *trailing_ms = 0.0;
-  *trailing_launches = 0;
-  const int64_t Np = eps_padded_size(n);
-  const int64_t ldw = 2 * Np;
-  const size_t wbytes = (size_t)Np * ldw * sizeof(double);
-  const size_t dbytes = (size_t)NB * NB * sizeof(double);
-  const size_t need = wbytes + dbytes;
-  if (need > ws->size) {
-    if (budget_left && need > budget_left) {
-      *err = "epsilon-solve workspace of " + std::to_string(need) + " bytes exceeds the budget";
-      return hipErrorOutOfMemory;
-    }
-    eps_free(ws);
-    hipError_t e = hipMalloc(&ws->buf, need);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      ws->buf = nullptr;
-      *err = "hipMalloc of " + std::to_string(need) + " bytes for the epsilon solve failed";
-      return hipErrorOutOfMemory;
-    }
-    ws->size = need;
+static hipError_t ensure(EpsWorkspace* ws, size_t budget_left, size_t need, const char* what, std::string* err) {
+  if (need <= ws->size) return hipSuccess;
+  if (budget_left && need > budget_left) {
+    *err = std::string(what) + " workspace of " + std::to_string(need) + " bytes exceeds the budget";
+    return hipErrorOutOfMemory;
   }
-  double* W = (double*)ws->buf;
-  double* Dinv = W + (size_t)Np * ldw;
-  hipError_t e;
+  eps_free(ws);
+  hipError_t e = hipMalloc(&ws->buf, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ws->buf = nullptr;
+    *err = "hipMalloc of " + std::to_string(need) + " bytes for the " + what + " failed";
+    return hipErrorOutOfMemory;
+  }
+  ws->size = need;
+  return hipSuccess;
+}
+
 #define EPS_CK(x, what)            \
   do {                             \
-    e = (x);                       \
-    if (e != hipSuccess) {         \
+    hipError_t e_ = (x);           \
+    if (e_ != hipSuccess) {        \
       *err = what;                 \
-      return e;                    \
+      return e_;                   \
     }                              \
   } while (0)
 
-  hipLaunchKernelGGL(k_eps_init, dim3((unsigned)((Np + 255) / 256), (unsigned)Np), dim3(256), 0, s, A, lda,
-                     (int)n, (int)Np, eps, W);
-  EPS_CK(hipGetLastError(), "epsilon init");
-
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  const int nblk = (int)(Np / NB);
+// Block Gauss-Jordan elimination of the Ns x Ns system held in the left part
+// of W (Ns rows, row stride ldw >= Ns + right-hand-side columns); afterwards
+// columns Ns .. ldw of W hold the solution.  Ns is a multiple of NB.
+static hipError_t gj_eliminate(double* W, int64_t Ns, int64_t ldw, double* Dinv, hipStream_t s, bool timing,
+                               std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs, std::string* err) {
+  const int nblk = (int)(Ns / NB);
   for (int k = 0; k < nblk; ++k) {
     const int64_t K0 = (int64_t)k * NB;
     const int cols = (int)(ldw - K0 - NB);  // columns right of the diagonal block
@@ -335,7 +327,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
     // eliminate block column k from every other block row
     if (nblk > 1) {
       GemmArgs tu{W + K0, ldw, W + K0 * ldw + K0 + NB, ldw, W + K0 + NB, ldw, W + K0 + NB, ldw,
-                  (int)(Np - NB), cols, NB, 1, k};
+                  (int)(Ns - NB), cols, NB, 1, k};
       hipEvent_t ea = nullptr, eb = nullptr;
       if (timing && hipEventCreate(&ea) == hipSuccess && hipEventCreate(&eb) == hipSuccess) {
         (void)hipEventRecord(ea, s);
@@ -343,49 +335,144 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
       EPS_CK(dgemm(tu, s), "elimination update");
       if (ea && eb) {
         (void)hipEventRecord(eb, s);
-        evs.push_back({ea, eb});
+        evs->push_back({ea, eb});
       }
     }
   }
-  hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
-                     (int)n, R, ldr, X_out, ldx);
-  EPS_CK(hipGetLastError(), "threshold");
-  EPS_CK(hipStreamSynchronize(s), "epsilon solve sync");
+  return hipSuccess;
+}
+
+hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* B, int64_t ldb,
+                     const uint8_t* C, int64_t ldc, double eps, uint8_t* R, int64_t ldr, double* X_out,
+                     int64_t ldx, hipStream_t s, bool timing, double* trailing_ms, int64_t* trailing_launches,
+                     std::string* err) {
+  *trailing_ms = 0.0;
+  *trailing_launches = 0;
+  const int64_t Np = eps_padded_size(n);
+  const int64_t ldw = 2 * Np;
+  const size_t wbytes = (size_t)Np * ldw * sizeof(double);
+  const size_t dbytes = (size_t)NB * NB * sizeof(double);
+  EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "epsilon-solve", err), *err);
+  double* W = (double*)ws->buf;
+  double* Dinv = W + (size_t)Np * ldw;
+
+  hipLaunchKernelGGL(k_eps_init, dim3((unsigned)((Np + 255) / 256), (unsigned)Np), dim3(256), 0, s, B, ldb, C, ldc,
+                     (int)n, (int)Np, eps, W);
+  EPS_CK(hipGetLastError(), "epsilon init");
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  hipError_t e = gj_eliminate(W, Np, ldw, Dinv, s, timing, &evs, err);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
+                       (int)n, R, ldr, X_out, ldx);
+    e = hipGetLastError();
+    if (e != hipSuccess) *err = "threshold";
+  }
+  if (e == hipSuccess) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) *err = "epsilon solve sync";
+  }
   for (auto& p : evs) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, p.first, p.second) == hipSuccess) {
+    if (e == hipSuccess && hipEventElapsedTime(&t, p.first, p.second) == hipSuccess) {
       *trailing_ms += t;
       *trailing_launches += 1;
     }
     (void)hipEventDestroy(p.first);
     (void)hipEventDestroy(p.second);
   }
-#undef EPS_CK
+  return e;
+}
+
+// ----------------------------------------------------------------- stacked tail-recursive system
+// W = [ I - E BB | E AA ] for the heads h = 0 .. M-1 of one layer (Ns = M Np
+// rows, ldw = Ns + Np): block (h, j) of BB is the int8 0/1 matrix B[h][j]
+// (null = zero), block h of AA is A[h], E = diag(eps_h) row-block-wise.
+__global__ void __launch_bounds__(256) k_stack_init(StackDesc d, int64_t Ns, int64_t ldw, double* W) {
+  const int64_t i = blockIdx.y;
+  const int h = (int)(i / d.Np), ii = (int)(i % d.Np);
+  const double eps = d.eps[h];
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ldw; j += (int64_t)gridDim.x * 256) {
+    double v;
+    if (j < Ns) {
+      const int jb = (int)(j / d.Np), jj = (int)(j % d.Np);
+      const int8_t* b = d.B[h][jb];
+      const double bij = (b && b[(int64_t)ii * d.Np + jj] != 0) ? 1.0 : 0.0;
+      v = (i == j ? 1.0 : 0.0) - eps * bij;
+    } else {
+      const int8_t* a = d.A[h];
+      const int jj = (int)(j - Ns);
+      v = (a && a[(int64_t)ii * d.Np + jj] != 0) ? eps : 0.0;
+    }
+    W[i * ldw + j] = v;
+  }
+}
+
+// R[h] = [X_h > 0] as int8 0/1 (Np x Np), counting the ones of each head.
+__global__ void __launch_bounds__(256) k_stack_emit(StackDesc d, int64_t Ns, int64_t ldw, const double* W) {
+  const int64_t i = blockIdx.y;
+  const int h = (int)(i / d.Np), ii = (int)(i % d.Np);
+  int c = 0;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < d.Np; j += gridDim.x * 256) {
+    const int8_t v = W[i * ldw + Ns + j] > 0.0 ? 1 : 0;
+    d.R[h][(int64_t)ii * (d.ldr ? d.ldr : d.Np) + j] = v;
+    c += v;
+  }
+  if (!d.cnt) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int t = red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(d.cnt + h, (unsigned long long)t);
+  }
+}
+
+hipError_t stacked_solve(EpsWorkspace* ws, size_t budget_left, const StackDesc& d, hipStream_t s, std::string* err) {
+  if (d.M < 1 || d.M > kMaxStack || d.Np % NB) {
+    *err = "bad stacked system";
+    return hipErrorInvalidValue;
+  }
+  const int64_t Ns = (int64_t)d.M * d.Np;
+  const int64_t ldw = Ns + d.Np;
+  const size_t wbytes = (size_t)Ns * ldw * sizeof(double);
+  const size_t dbytes = (size_t)NB * NB * sizeof(double);
+  EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "stacked linear solve", err), *err);
+  double* W = (double*)ws->buf;
+  double* Dinv = W + (size_t)Ns * ldw;
+  hipLaunchKernelGGL(k_stack_init, dim3((unsigned)((ldw + 255) / 256), (unsigned)Ns), dim3(256), 0, s, d, Ns, ldw, W);
+  EPS_CK(hipGetLastError(), "stacked init");
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  EPS_CK(gj_eliminate(W, Ns, ldw, Dinv, s, false, &evs, err), *err);
+  hipLaunchKernelGGL(k_stack_emit, dim3((unsigned)((d.Np + 255) / 256), (unsigned)Ns), dim3(256), 0, s, d, Ns, ldw,
+                     (const double*)W);
+  EPS_CK(hipGetLastError(), "stacked threshold");
   return hipSuccess;
 }
 
-// ----------------------------------------------------------------- same-generation epsilon form
-// X = eps (I + P X P^T) (Sec. 7.2; a discrete Sylvester / Stein equation,
-// Sec. 6.3), solved by Smith's doubling in fp64:
-//   X_0 = eps I_n,  A_0 = sqrt(eps) P,
-//   X_{j+1} = X_j + A_j X_j A_j^T,  A_{j+1} = A_j A_j,
-// so X_j = eps sum_{m < 2^j} (sqrt(eps) P)^m ((sqrt(eps) P)^T)^m.  Every term is
-// >= 0, so the zero pattern of X_j is exact: it is the set of pairs joined
-// by equal-length walks of length < 2^j to a common constant, i.e. the
-// same-generation iterate S^(2^j).  When a doubling leaves the number of
-// positive entries unchanged, S^(2^(j+1)) = S^(2^j) and the fixpoint is
-// reached (the series of iterates is monotone).  When the real solution is
-// wanted as well, doublings go on until one also leaves every fp64 value
-// unchanged (the increments shrink doubly exponentially, so the truncated
-// series is then within rounding of the limit).  A Schur-based Sylvester
-// solver would cancel terms and lose the exact zero pattern.
+// ----------------------------------------------------------------- two-sided (Stein) equations
+// X = Q + B X C with B, C, Q >= 0 and a convergent series, solved by Smith's
+// doubling in fp64:
+//   X_0 = Q,  B_0 = B,  C_0 = C,
+//   X_{j+1} = X_j + B_j X_j C_j,  B_{j+1} = B_j B_j,  C_{j+1} = C_j C_j,
+// so X_j = sum_{m < 2^j} B^m Q C^m.  Every term is >= 0, so the zero pattern
+// of X_j is exact: it is the 2^j-th iterate of the Boolean series
+// Y' = [Q + B Y C] from Y = 0.  When a doubling leaves the number of positive
+// entries unchanged, that series has repeated (it is monotone), so the
+// pattern is the least model.  When the real solution is wanted as well,
+// doublings go on until one also leaves every fp64 value unchanged (the
+// increments shrink doubly exponentially, so the truncated series is then
+// within rounding of the limit).  A Schur-based Sylvester solver would
+// cancel terms and lose the exact zero pattern.  For the same-generation
+// form C = B^T, which is kept as the transpose of B instead of a product.
 __global__ void __launch_bounds__(256)
-k_sg_eps_init(const uint8_t* P, int64_t ldp, int n, int Np, double eps, double seps, double* X, double* A) {
+k_f64_from_bytes(const uint8_t* src, int64_t ld, int n, int Np, double scale, int identity, double* dst) {
   const int i = blockIdx.y;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
-    const double p = (i < n && j < n && P[(int64_t)i * ldp + j] != 0) ? 1.0 : 0.0;
-    X[(int64_t)i * Np + j] = (i == j && i < n) ? eps : 0.0;
-    A[(int64_t)i * Np + j] = seps * p;
+    double v = 0.0;
+    if (i < n && j < n) v = identity ? (i == j ? scale : 0.0) : (src[(int64_t)i * ld + j] != 0 ? scale : 0.0);
+    dst[(int64_t)i * Np + j] = v;
   }
 }
 
@@ -400,39 +487,50 @@ __global__ void __launch_bounds__(256) k_transpose_f64(const double* src, double
   for (int r = ty; r < 32; r += 8) dst[(int64_t)(bx + r) * Np + by + tx] = tile[tx][r];
 }
 
-// X += I (the doubling's increment) in place; counts the positive entries of
-// the new X into out[0] and the entries whose value changed into out[1].
-__global__ void __launch_bounds__(256)
-k_sg_accumulate(double* X, const double* I, int Np, unsigned long long* out) {
-  const int i = blockIdx.y;
-  int pos = 0, chg = 0;
-  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
-    const int64_t o = (int64_t)i * Np + j;
-    const double x = X[o];
-    const double y = x + I[o];
-    pos += y > 0.0;
-    chg += y != x;
-    X[o] = y;
-  }
+// Block sums of per-thread counts into out[0..K): one atomic per workgroup and counter.
+template <int K>
+__device__ inline void block_count(int (&c)[K], unsigned long long* out) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    pos += __shfl_xor(pos, off, 64);
-    chg += __shfl_xor(chg, off, 64);
-  }
-  __shared__ int red[2][4];
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = pos;
-    red[1][threadIdx.x >> 6] = chg;
-  }
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c[k] += __shfl_xor(c[k], off, 64);
+  __shared__ int red[K][4];
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][threadIdx.x >> 6] = c[k];
   __syncthreads();
-  if (threadIdx.x < 2) {
+  if (threadIdx.x < K) {
     const int t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
     if (t) atomicAdd(out + threadIdx.x, (unsigned long long)t);
   }
 }
 
+__global__ void __launch_bounds__(256) k_count_positive(const double* X, int Np, unsigned long long* out) {
+  const int i = blockIdx.y;
+  int c[1] = {0};
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) c[0] += X[(int64_t)i * Np + j] > 0.0;
+  block_count<1>(c, out);
+}
+
+// X += I (the doubling's increment) in place; counts the positive entries of
+// the new X into out[0] and the entries whose value changed into out[1].
 __global__ void __launch_bounds__(256)
-k_sg_eps_emit(const double* X, int Np, int n, uint8_t* S, int64_t lds, double* Xo, int64_t ldx) {
+k_stein_accumulate(double* X, const double* I, int Np, unsigned long long* out) {
+  const int i = blockIdx.y;
+  int c[2] = {0, 0};
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
+    const int64_t o = (int64_t)i * Np + j;
+    const double x = X[o];
+    const double y = x + I[o];
+    c[0] += y > 0.0;
+    c[1] += y != x;
+    X[o] = y;
+  }
+  block_count<2>(c, out);
+}
+
+__global__ void __launch_bounds__(256)
+k_f64_emit(const double* X, int Np, int n, uint8_t* S, int64_t lds, double* Xo, int64_t ldx) {
   const int i = blockIdx.y;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
     const double x = X[(int64_t)i * Np + j];
@@ -441,83 +539,137 @@ k_sg_eps_emit(const double* X, int Np, int n, uint8_t* S, int64_t lds, double* X
   }
 }
 
+// Doubling loop on buffers already initialised: X = Q, B, and C (= B^T when
+// c_is_bt).  T, Bn (and Cn unless c_is_bt) are scratch.  On return *Xp points
+// at the buffer holding X.
+static hipError_t stein_doubling(int64_t Np, double* X, double* B, double* C, double* T, double* Bn, double* Cn,
+                                 bool c_is_bt, bool want_values, int max_doublings, hipStream_t s,
+                                 unsigned long long* d_counter, unsigned long long* h_counter, int64_t* positives,
+                                 int32_t* doublings, bool* done_out, std::string* err) {
+  const dim3 rows((unsigned)((Np + 255) / 256), (unsigned)Np);
+  const dim3 tgrid((unsigned)(Np / 32), (unsigned)(Np / 32));
+  EPS_CK(hipMemsetAsync(d_counter, 0, sizeof(unsigned long long), s), "counter clear");
+  hipLaunchKernelGGL(k_count_positive, rows, dim3(256), 0, s, (const double*)X, (int)Np, d_counter);
+  EPS_CK(hipGetLastError(), "count");
+  EPS_CK(hipMemcpyAsync(h_counter, d_counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "readback");
+  EPS_CK(hipStreamSynchronize(s), "sync");
+  int64_t prev = (int64_t)h_counter[0];
+  int j = 0;
+  bool done = false;
+  while (!done && j < max_doublings) {
+    // Bn = B B;  Cn = C C;  T = B X;  I = T C (into B's buffer, free once T
+    // is formed);  X += I;  B <- Bn, C <- Cn (or B^T).
+    GemmArgs g1{B, Np, B, Np, nullptr, 0, Bn, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    EPS_CK(dgemm(g1, s), "B B");
+    if (!c_is_bt) {
+      GemmArgs g1c{C, Np, C, Np, nullptr, 0, Cn, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+      EPS_CK(dgemm(g1c, s), "C C");
+    }
+    GemmArgs g2{B, Np, X, Np, nullptr, 0, T, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    EPS_CK(dgemm(g2, s), "B X");
+    GemmArgs g3{T, Np, C, Np, nullptr, 0, B, Np, (int)Np, (int)Np, (int)Np, 0, -1};
+    EPS_CK(dgemm(g3, s), "T C");
+    EPS_CK(hipMemsetAsync(d_counter, 0, 2 * sizeof(unsigned long long), s), "counter clear");
+    hipLaunchKernelGGL(k_stein_accumulate, rows, dim3(256), 0, s, X, (const double*)B, (int)Np, d_counter);
+    EPS_CK(hipGetLastError(), "accumulate");
+    std::swap(B, Bn);
+    if (c_is_bt) {
+      hipLaunchKernelGGL(k_transpose_f64, tgrid, dim3(256), 0, s, (const double*)B, C, (int)Np);
+      EPS_CK(hipGetLastError(), "transpose");
+    } else {
+      std::swap(C, Cn);
+    }
+    EPS_CK(hipMemcpyAsync(h_counter, d_counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+           "readback");
+    EPS_CK(hipStreamSynchronize(s), "sync");
+    ++j;
+    const int64_t c = (int64_t)h_counter[0];
+    done = c == prev && (!want_values || h_counter[1] == 0);
+    prev = c;
+  }
+  *positives = prev;
+  *doublings = j;
+  *done_out = done;
+  return hipSuccess;
+}
+
 hipError_t sg_eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* P, int64_t ldp, double eps,
                         uint8_t* S, int64_t lds, double* X_out, int64_t ldx, int max_doublings, hipStream_t s,
                         int32_t* doublings, int64_t* positives, unsigned long long* d_counter,
                         unsigned long long* h_counter, std::string* err) {
   const int64_t Np = eps_padded_size(n);
-  const size_t mat = (size_t)Np * Np * sizeof(double);
-  const size_t need = 5 * mat;
-  if (need > ws->size) {
-    if (budget_left && need > budget_left) {
-      *err = "same-generation epsilon workspace of " + std::to_string(need) + " bytes exceeds the budget";
-      return hipErrorOutOfMemory;
-    }
-    eps_free(ws);
-    hipError_t e = hipMalloc(&ws->buf, need);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      ws->buf = nullptr;
-      *err = "hipMalloc of " + std::to_string(need) + " bytes for the same-generation epsilon solve failed";
-      return hipErrorOutOfMemory;
-    }
-    ws->size = need;
-  }
+  const size_t mat = (size_t)Np * Np;
+  EPS_CK(ensure(ws, budget_left, 5 * mat * sizeof(double), "same-generation epsilon solve", err), *err);
   double* X = (double*)ws->buf;
-  double* A = X + (size_t)Np * Np;
-  double* AT = A + (size_t)Np * Np;
-  double* T = AT + (size_t)Np * Np;
-  double* An = T + (size_t)Np * Np;
-  hipError_t e;
-#define SG_CK(x, what)             \
-  do {                             \
-    e = (x);                       \
-    if (e != hipSuccess) {         \
-      *err = what;                 \
-      return e;                    \
-    }                              \
-  } while (0)
+  double* A = X + mat;
+  double* AT = A + mat;
+  double* T = AT + mat;
+  double* An = T + mat;
   const dim3 rows((unsigned)((Np + 255) / 256), (unsigned)Np);
-  const dim3 tgrid((unsigned)(Np / 32), (unsigned)(Np / 32));
-  hipLaunchKernelGGL(k_sg_eps_init, rows, dim3(256), 0, s, P, ldp, (int)n, (int)Np, eps, sqrt(eps), X, A);
-  SG_CK(hipGetLastError(), "init");
-  hipLaunchKernelGGL(k_transpose_f64, tgrid, dim3(256), 0, s, A, AT, (int)Np);
-  SG_CK(hipGetLastError(), "transpose");
-  int64_t prev = n;  // X_0 = eps I has n positive entries
-  int j = 0;
+  // X_0 = eps I, A_0 = sqrt(eps) P, C = A^T
+  hipLaunchKernelGGL(k_f64_from_bytes, rows, dim3(256), 0, s, (const uint8_t*)nullptr, (int64_t)0, (int)n, (int)Np,
+                     eps, 1, X);
+  hipLaunchKernelGGL(k_f64_from_bytes, rows, dim3(256), 0, s, P, ldp, (int)n, (int)Np, sqrt(eps), 0, A);
+  hipLaunchKernelGGL(k_transpose_f64, dim3((unsigned)(Np / 32), (unsigned)(Np / 32)), dim3(256), 0, s,
+                     (const double*)A, AT, (int)Np);
+  EPS_CK(hipGetLastError(), "init");
   bool done = false;
-  while (!done && j < max_doublings) {
-    // An = A A;  T = A X;  I = T A^T (into A's buffer, free once T is
-    // formed);  X += I;  A <- An (and its transpose).
-    GemmArgs g1{A, Np, A, Np, nullptr, 0, An, Np, (int)Np, (int)Np, (int)Np, 0, -1};
-    SG_CK(dgemm(g1, s), "A A");
-    GemmArgs g2{A, Np, X, Np, nullptr, 0, T, Np, (int)Np, (int)Np, (int)Np, 0, -1};
-    SG_CK(dgemm(g2, s), "A X");
-    GemmArgs g3{T, Np, AT, Np, nullptr, 0, A, Np, (int)Np, (int)Np, (int)Np, 0, -1};
-    SG_CK(dgemm(g3, s), "T A^T");
-    SG_CK(hipMemsetAsync(d_counter, 0, 2 * sizeof(unsigned long long), s), "counter clear");
-    hipLaunchKernelGGL(k_sg_accumulate, rows, dim3(256), 0, s, X, A, (int)Np, d_counter);
-    SG_CK(hipGetLastError(), "accumulate");
-    std::swap(A, An);
-    hipLaunchKernelGGL(k_transpose_f64, tgrid, dim3(256), 0, s, A, AT, (int)Np);
-    SG_CK(hipGetLastError(), "transpose");
-    SG_CK(hipMemcpyAsync(h_counter, d_counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
-          "readback");
-    SG_CK(hipStreamSynchronize(s), "sync");
-    ++j;
-    const int64_t c = (int64_t)h_counter[0];
-    const bool values_fixed = h_counter[1] == 0;
-    done = c == prev && (X_out == nullptr || values_fixed);
-    prev = c;
-  }
-  hipLaunchKernelGGL(k_sg_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, X, (int)Np,
-                     (int)n, S, lds, X_out, ldx);
-  SG_CK(hipGetLastError(), "threshold");
-  SG_CK(hipStreamSynchronize(s), "sync");
-  if (doublings) *doublings = j;
-  if (positives) *positives = prev;
-#undef SG_CK
+  EPS_CK(stein_doubling(Np, X, A, AT, T, An, nullptr, true, X_out != nullptr, max_doublings, s, d_counter, h_counter,
+                        positives, doublings, &done, err),
+         *err);
+  hipLaunchKernelGGL(k_f64_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, (const double*)X,
+                     (int)Np, (int)n, S, lds, X_out, ldx);
+  EPS_CK(hipGetLastError(), "threshold");
+  EPS_CK(hipStreamSynchronize(s), "sync");
   return done ? hipSuccess : hipErrorNotReady;
 }
+
+hipError_t two_sided_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* Q, int64_t ldq,
+                           const uint8_t* B, int64_t ldb, const uint8_t* C, int64_t ldc, double eps, uint8_t* R,
+                           int64_t ldr, double* X_out, int64_t ldx, int8_t* R8, int64_t ld8,
+                           unsigned long long* r8_count, int max_doublings, hipStream_t s, int32_t* doublings, unsigned long long* d_counter,
+                           unsigned long long* h_counter, std::string* err) {
+  const int64_t Np = eps_padded_size(n);
+  const size_t mat = (size_t)Np * Np;
+  EPS_CK(ensure(ws, budget_left, 6 * mat * sizeof(double), "two-sided solve", err), *err);
+  double* X = (double*)ws->buf;
+  double* Bd = X + mat;
+  double* Cd = Bd + mat;
+  double* T = Cd + mat;
+  double* Bn = T + mat;
+  double* Cn = Bn + mat;
+  const dim3 rows((unsigned)((Np + 255) / 256), (unsigned)Np);
+  // X = eps (Q + B X C): X_0 = eps Q, B_0 = sqrt(eps) B, C_0 = sqrt(eps) C
+  const double se = sqrt(eps);
+  hipLaunchKernelGGL(k_f64_from_bytes, rows, dim3(256), 0, s, Q, ldq, (int)n, (int)Np, eps, 0, X);
+  hipLaunchKernelGGL(k_f64_from_bytes, rows, dim3(256), 0, s, B, ldb, (int)n, (int)Np, se, 0, Bd);
+  hipLaunchKernelGGL(k_f64_from_bytes, rows, dim3(256), 0, s, C, ldc, (int)n, (int)Np, se, 0, Cd);
+  EPS_CK(hipGetLastError(), "init");
+  bool done = false;
+  int64_t pos = 0;
+  EPS_CK(stein_doubling(Np, X, Bd, Cd, T, Bn, Cn, false, X_out != nullptr, max_doublings, s, d_counter, h_counter,
+                        &pos, doublings, &done, err),
+         *err);
+  if (R) {
+    hipLaunchKernelGGL(k_f64_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, (const double*)X,
+                       (int)Np, (int)n, R, ldr, X_out, ldx);
+    EPS_CK(hipGetLastError(), "threshold");
+  }
+  if (R8) {
+    StackDesc d{};
+    d.M = 1;
+    d.Np = (int)Np;
+    d.R[0] = R8;
+    d.ldr = ld8;
+    d.cnt = r8_count;
+    hipLaunchKernelGGL(k_stack_emit, dim3((unsigned)((Np + 255) / 256), (unsigned)Np), dim3(256), 0, s, d,
+                       (int64_t)0, (int64_t)Np, (const double*)X);
+    EPS_CK(hipGetLastError(), "threshold");
+  }
+  EPS_CK(hipStreamSynchronize(s), "sync");
+  return done ? hipSuccess : hipErrorNotReady;
+}
+
+#undef EPS_CK
 
 }  // namespace dl

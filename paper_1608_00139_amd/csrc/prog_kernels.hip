@@ -1,0 +1,87 @@
+// prog_kernels.hip -- elementwise kernels of layered program evaluation on
+// int8 0/1 matrices (Np x Np, row-major, zero padded): disjunction of
+// relations, complement for negated atoms (Sec. 8), transposed copies for
+// converse atoms, and the column-sum norm.
+#include "common.h"
+
+namespace dl {
+
+// out = op(a | b | I) on a 64 x 64 tile per workgroup (256 threads, 16 bytes
+// each); `complement` turns the tile into [i < n, j < n] & !v.  Writes out
+// and/or outT (the transpose, through LDS) and adds the tile's ones to *cnt.
+__global__ void __launch_bounds__(256)
+k_bytes_op(const int8_t* a, const int8_t* b, int ident, int complement, int n, int Np,
+           int8_t* out, int8_t* outT, unsigned long long* cnt) {
+  __shared__ uint8_t tile[64][64 + 16];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int r = tid >> 2, c0 = (tid & 3) * 16;
+  const int gi = bi * 64 + r, gj0 = bj * 64 + c0;
+  const int64_t off = (int64_t)gi * Np + gj0;
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if (a) v |= *(const u32x4*)(a + off);
+  if (b) v |= *(const u32x4*)(b + off);
+  if (ident && gi < n && gi >= gj0 && gi < gj0 + 16) {
+    const int t = gi - gj0;
+    v[t >> 2] |= 1u << (8 * (t & 3));
+  }
+  if (complement) {
+    u32x4 m = {0u, 0u, 0u, 0u};
+    if (gi < n) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (gj0 + t < n) m[t >> 2] |= 1u << (8 * (t & 3));
+    }
+    v = m & ~v;
+  }
+  if (out) *(u32x4*)(out + off) = v;
+  int ones = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) ones += __popc(v[w]);
+  if (outT) {
+    *(u32x4*)&tile[r][c0] = v;
+    __syncthreads();
+    u32x4 t;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      t[w] = (unsigned)tile[c0 + 4 * w][r] | ((unsigned)tile[c0 + 4 * w + 1][r] << 8) |
+             ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
+    *(u32x4*)(outT + (int64_t)(bj * 64 + r) * Np + bi * 64 + c0) = t;
+  }
+  if (cnt) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ones += __shfl_xor(ones, o, 64);
+    __shared__ int red[4];
+    if ((tid & 63) == 0) red[tid >> 6] = ones;
+    __syncthreads();
+    if (tid == 0) {
+      const int t = red[0] + red[1] + red[2] + red[3];
+      if (t) atomicAdd(cnt, (unsigned long long)t);
+    }
+  }
+}
+
+hipError_t launch_bytes_op(const int8_t* a, const int8_t* b, int ident, int complement, int n, int Np, int8_t* out,
+                           int8_t* outT, unsigned long long* cnt, hipStream_t s) {
+  if (Np % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bytes_op, dim3(Np / 64, Np / 64), dim3(256), 0, s, a, b, ident, complement, n, Np, out, outT,
+                     cnt);
+  return hipGetLastError();
+}
+
+// Largest column sum: each thread walks one column (consecutive threads take
+// consecutive columns, so every row read is coalesced).
+__global__ void __launch_bounds__(256) k_col_max(const uint8_t* A, int64_t lda, int n, int* out_max) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  int s = 0;
+  for (int i = 0; i < n; ++i) s += A[(int64_t)i * lda + j] != 0;
+  atomicMax(out_max, s);
+}
+
+hipError_t launch_col_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_max, dim3((n + 255) / 256), dim3(256), 0, s, A, lda, n, out_max);
+  return hipGetLastError();
+}
+
+}  // namespace dl

@@ -1,0 +1,212 @@
+"""Layered program evaluation on the GPU through the C ABI, bit-exact against
+the layered oracle; the tail-recursive and two-sided epsilon solvers against
+their fp64 oracles."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import dlgen
+import oracle
+from oracle import program as oprog
+from tests.gpu_util import announce, dev, gpu, host
+from tests.test_oracle_program import CASES, NEG_TEXT, TWO_SIDED_TEXT
+
+pytestmark = gpu
+
+FORMS = {
+    "tc_right": ["right_tail"],
+    "tc_left": ["left_tail"],
+    "sg": ["two_sided"],
+    "transposed": ["two_sided"],
+    "two_sided": ["two_sided"],
+    "even_odd": ["right_tail"],
+    "layers": ["right_tail", "nonrecursive", "left_tail"],
+    "mixed_general": ["general"],
+}
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import paper_1608_00139_amd as m
+
+    m.load()
+    return m
+
+
+def _rand(n, p, seed, loops=True):
+    return dlgen.to_dense(n, dlgen.er_edges(n, min(p, 1.0), seed, self_loops=loops))
+
+
+def _run(dl, text, rels, n, method):
+    prog = dl.Program(text)
+    keep = {k: dev(v) for k, v in rels.items()}
+    for k, t in keep.items():
+        prog.bind(k, t)
+    prog.run(method)
+    return prog
+
+
+def _compare(dl, text, rels, n, tag):
+    ref, ref_layers = oprog.evaluate(text, rels, n)
+    ref_iters = {tuple(h): it for h, it in ref_layers}
+    for method in (dl.DL_EVAL_ITERATION, dl.DL_EVAL_MATRIX):
+        announce("program", tag, n, method)
+        prog = _run(dl, text, rels, n, method)
+        for name, want in ref.items():
+            got, ones = prog.fetch(name, n=n)
+            got = host(got)
+            mism = int((got != want).sum())
+            assert mism == 0, f"{tag} n={n} method={method} {name}: {mism} entries differ"
+            assert ones == int(want.sum())
+        layers = prog.layers()
+        assert sorted(tuple(l["heads"]) for l in layers) == sorted(tuple(h) for h, _ in ref_layers)
+        for l in layers:
+            if l["method"] == dl.DL_EVAL_ITERATION:
+                assert l["iters"] == ref_iters[tuple(l["heads"])], (tag, l)
+        prog.close()
+    return layers
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("n", [1, 5, 64, 257, 600])
+def test_cases_vs_oracle(dl, name, n):
+    text, _, edbs = CASES[name]
+    for seed in range(2):
+        rels = {e: _rand(n, 2.0 / n if n > 8 else 0.3, 100 * seed + k) for k, e in enumerate(edbs)}
+        if name == "sg":
+            rels = {"p": dlgen.to_dense(n, dlgen.forest_edges(n, seed))}
+        layers = _compare(dl, text, rels, n, f"{name} seed={seed}")
+        assert [l["form"] for l in layers] == FORMS[name]
+
+
+@pytest.mark.parametrize("n", [4, 100, 300])
+def test_stratified_negation(dl, n):
+    for seed in range(3):
+        rels = {"e": _rand(n, 1.5 / n if n > 8 else 0.35, seed), "f": _rand(n, 1.0 / n if n > 8 else 0.3, 9 + seed)}
+        _compare(dl, NEG_TEXT, rels, n, f"negation seed={seed}")
+
+
+def test_negated_eq_and_converse_in_constant_terms(dl):
+    text = ("d(X,Y) :- not eq(X,Y).\n"
+            "u(X,Y) :- e(Y,X).\n"
+            "w(X,Z) :- d(X,Y), e(Z,Y).\n"
+            "v(X,Z) :- e(X,Y), not e(Y,Z).\nv(X,Z) :- v(Y,X), e(Y,Z).")
+    n = 130
+    _compare(dl, text, {"e": _rand(n, 3.0 / n, 4)}, n, "constants")
+
+
+def test_dense_and_empty_relations(dl):
+    n = 70
+    for rel in (np.zeros((n, n), np.uint8), np.ones((n, n), np.uint8)):
+        for name in ("tc_right", "transposed", "mixed_general"):
+            text, _, edbs = CASES[name]
+            _compare(dl, text, {e: rel for e in edbs}, n, f"{name} const")
+
+
+def test_program_errors(dl):
+    with pytest.raises(dl.DLError) as ei:
+        dl.Program("t(X,Z) :- e(X,Z).\nt(X,Z) :- t(X,Y), t(Y,Z).")
+    assert ei.value.status == 5  # not linear
+    with pytest.raises(dl.DLError) as ei:
+        dl.Program("p(X,Y) :- e(X,Y).\nq(X,Y) :- e(X,Z), not p(Z,Y).\np(X,Y) :- q(X,Y).")
+    assert ei.value.status == 5  # not stratified
+    with pytest.raises(dl.DLError) as ei:
+        dl.Program("p(X,Y) :- e(X,Y), e(Y,X).")
+    assert ei.value.status == 5  # not a chain
+    with pytest.raises(dl.DLError) as ei:
+        dl.Program("p(X,Y) :- e(X,Y)")
+    assert ei.value.status == 1  # syntax
+    with pytest.raises(dl.DLError) as ei:
+        dl.Program("p(X,Y) :- e(X,y).")
+    assert ei.value.status == 1
+    prog = dl.Program("p(X,Y) :- e(X,Y).\nq(X,Z) :- p(Y,X), f(Y,Z).")
+    with pytest.raises(dl.DLError):
+        prog.bind("p", dev(np.eye(4, dtype=np.uint8)))  # defined, not given
+    prog.bind("e", dev(np.eye(4, dtype=np.uint8)))
+    with pytest.raises(dl.DLError):
+        prog.bind("f", dev(np.eye(5, dtype=np.uint8)))  # different n
+    with pytest.raises(dl.DLError):
+        prog.run()  # f unbound
+    with pytest.raises(dl.DLError):
+        prog.fetch("p", n=4)  # not run yet
+
+
+def test_config_tc_program_n4096(dl):
+    """Closure program at n = 4096 (ER 1/n and 4/n): both methods against the closure oracle."""
+    n = 4096
+    for p in (1.0 / n, 4.0 / n):
+        a = _rand(n, p, 0, loops=False)
+        ref, _, iters, _ = oracle.tc_seminaive(a)
+        for method in (dl.DL_EVAL_ITERATION, dl.DL_EVAL_MATRIX):
+            announce("tc program 4096", p, method)
+            prog = _run(dl, CASES["tc_right"][0], {"e": a}, n, method)
+            got, ones = prog.fetch("tc", n=n)
+            assert int((host(got) != ref).sum()) == 0
+            if method == dl.DL_EVAL_ITERATION:
+                assert prog.layers()[0]["iters"] == iters
+            prog.close()
+
+
+def test_config_sg_program_n4096(dl):
+    n = 4096
+    p = dlgen.to_dense(n, dlgen.forest_edges(n, 1))
+    ref, _, iters, _ = oracle.sg_seminaive(p)
+    for method in (dl.DL_EVAL_ITERATION, dl.DL_EVAL_MATRIX):
+        announce("sg program 4096", method)
+        prog = _run(dl, CASES["sg"][0], {"p": p}, n, method)
+        got, _ = prog.fetch("sg", n=n)
+        assert int((host(got) != ref).sum()) == 0
+        prog.close()
+
+
+# ---------------------------------------------------------------- epsilon solvers
+
+
+@pytest.mark.parametrize("n", [1, 7, 129, 300])
+def test_solve_linear_vs_lapack(dl, n):
+    for seed in range(2):
+        b = _rand(n, 2.0 / n if n > 8 else 0.3, seed)
+        c = _rand(n, 1.5 / n if n > 8 else 0.3, 30 + seed)
+        eps = dl.dl_eps_bound(dev(b))
+        announce("solve_linear", n, seed)
+        r, x = dl.dl_solve_linear(dev(b), dev(c), eps, want_x=True)
+        ref = oracle.linear_solve(b, c, eps)
+        assert np.allclose(host(x), ref, rtol=1e-12, atol=1e-15)
+        tcb = oracle.tc_seminaive(b)[0].astype(np.int64)
+        want = ((c.astype(np.int64) + tcb @ c.astype(np.int64)) > 0).astype(np.uint8)
+        assert np.array_equal(host(r), want)
+
+
+def test_solve_linear_validation(dl):
+    b = _rand(20, 0.2, 1)
+    eps = dl.dl_eps_bound(dev(b))
+    with pytest.raises(dl.DLError):
+        dl.dl_solve_linear(dev(b), dev(b), eps * 1.01)
+    with pytest.raises(dl.DLError):
+        dl.dl_solve_linear(dev(b), dev(b), 0.0)
+
+
+def test_solve_two_sided_vs_kron(dl):
+    for seed in range(4):
+        n = 5 + 2 * seed
+        q, b, c = _rand(n, 0.2, seed), _rand(n, 0.3, 20 + seed), _rand(n, 0.3, 40 + seed)
+        eps = 1.0 / (1 + int(b.sum(axis=1).max()) * int(c.sum(axis=0).max()))
+        announce("two_sided kron", n)
+        r, x, dbl = dl.dl_solve_two_sided(dev(q), dev(b), dev(c), eps, want_x=True)
+        assert np.allclose(host(x), oracle.two_sided_kron(q, b, c, eps), rtol=1e-12, atol=1e-15)
+        model, _ = oprog.evaluate(TWO_SIDED_TEXT, {"q": q, "b": b, "c": c}, n)
+        assert np.array_equal(host(r), model["r"])
+
+
+@pytest.mark.parametrize("n", [60, 300])
+def test_solve_two_sided_threshold(dl, n):
+    for seed in range(2):
+        q, b, c = _rand(n, 1.0 / n, seed), _rand(n, 2.0 / n, 20 + seed), _rand(n, 2.0 / n, 40 + seed)
+        eps = 1.0 / (1 + int(b.sum(axis=1).max()) * int(c.sum(axis=0).max()))
+        announce("two_sided", n)
+        r, _, dbl = dl.dl_solve_two_sided(dev(q), dev(b), dev(c), eps)
+        model, _ = oprog.evaluate(TWO_SIDED_TEXT, {"q": q, "b": b, "c": c}, n)
+        assert np.array_equal(host(r), model["r"])
+    with pytest.raises(dl.DLError):
+        dl.dl_solve_two_sided(dev(q), dev(b), dev(c), eps * 1.5)
