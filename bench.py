@@ -60,7 +60,17 @@ def main() -> int:
                     help="run three plain 1 GiB device copies (traffic-counter calibration) and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
                     help="per-launch HBM traffic of the step kernel from rocprofv3 --pmc CSVs and exit")
+    ap.add_argument("--programs-only", action="store_true",
+                    help="run only the layered program workloads (both methods) and print their JSON")
     args = ap.parse_args()
+    if args.programs_only:
+        import torch
+
+        import paper_1608_00139_amd as dl
+
+        torch.cuda.set_device(0)
+        print(json.dumps(run_programs(dl, dl.Context(0), torch)))
+        return 0
     if args.trace_summary:
         return trace_summary(args.trace_summary)
     if args.pmc_summary:
@@ -308,7 +318,81 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
                     "executed_tflops": round(6.0 * n ** 3 * dbl / t / 1e12, 2),
                     "threshold_errors_vs_int8_model": int((s != ref).sum().item())})
     res["sg_eps_fp64_n4096"] = sge
+    torch.cuda.empty_cache()
+    res["programs"] = run_programs(dl, ctx, torch)
     return res
+
+
+PROGRAMS = {
+    # four layers: a right-tail closure, two non-recursive layers with negation,
+    # and a left-tail recursion over a complemented relation
+    "layers_negation": (
+        "tc(X,Y) :- e(X,Y).\ntc(X,Y) :- e(X,Z), tc(Z,Y).\n"
+        "nr(X,Y) :- not tc(X,Y).\nr(X,Z) :- e(X,Y), not tc(Y,Z).\n"
+        "s(X,Z) :- f(X,Z).\ns(X,Z) :- s(X,Y), not e(Y,Z).",
+        8192, {"e": ("er", 4.0), "f": ("er", 1.0)}),
+    # mutual recursion (walks of odd / even length)
+    "even_odd": (
+        "odd(X,Z) :- e(X,Z).\nodd(X,Z) :- e(X,Y), even(Y,Z).\neven(X,Z) :- e(X,Y), odd(Y,Z).",
+        8192, {"e": ("er", 1.0)}),
+    # transposed class (Sec. 6.2): r2(x,z) <- r1(x,y), r2(z,y)
+    "transposed": ("r2(X,Z) :- r1(X,Z).\nr2(X,Z) :- r1(X,Y), r2(Z,Y).", 4096, {"r1": ("er", 1.0)}),
+    # same generation as a program (two-sided clause with eq)
+    "same_generation": ("sg(X,Y) :- eq(X,Y).\nsg(X,Y) :- p(X,U), sg(U,V), p(Y,V).", 4096, {"p": ("forest", 0)}),
+}
+
+
+def run_programs(dl, ctx, torch):
+    """Layered evaluation of whole programs: both methods on the same bound
+    relations (seed 0; ER with mean degree c as p = c/N), wall time of
+    dl_program_run, product-kernel launches and their time, and the number of
+    entries where the two methods' models differ (must be 0)."""
+    import dlgen
+
+    out = {}
+    for name, (text, n, rels) in PROGRAMS.items():
+        bound = {}
+        for k, (rname, (gen, arg)) in enumerate(rels.items()):
+            if gen == "er":
+                m = dlgen.to_dense(n, dlgen.er_edges(n, arg / n, k))
+            else:
+                m = dlgen.to_dense(n, dlgen.forest_edges(n, arg))
+            bound[rname] = torch.from_numpy(m).cuda()
+        rows, models = [], []
+        for method in (dl.DL_EVAL_ITERATION, dl.DL_EVAL_MATRIX):
+            prog = dl.Program(text, ctx=ctx)
+            for k, t in bound.items():
+                prog.bind(k, t)
+            prog.run(method)  # warm-up (allocations, first launches)
+            ctx.kernel_stats(0, reset=True)
+            ctx.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prog.run(method)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            ctx.set_timing(False)
+            launches, kms = ctx.kernel_stats(0, reset=True)
+            np_ = dl.dl_padded_size(n, 0, dl.DL_I8)
+            heads = sorted({h for l in prog.layers() for h in l["heads"]})
+            got = {h: prog.fetch(h, n=n)[0] for h in heads}
+            models.append(got)
+            rows.append({"method": "iteration" if method == dl.DL_EVAL_ITERATION else "matrix",
+                         "time_ms": round(t * 1e3, 2), "product_launches": launches,
+                         "product_kernel_ms": round(kms, 2),
+                         "product_kernel_tops": round(2.0 * np_ ** 3 * launches / (kms * 1e-3) / 1e12, 1)
+                         if launches else None,
+                         "layers": [{"heads": l["heads"], "form": l["form"],
+                                     "method": "iteration" if l["method"] == 0 else "matrix",
+                                     "iters": l["iters"]} for l in prog.layers()],
+                         "ones": {h: int(v.sum().item()) for h, v in got.items()}})
+            prog.close()
+        diff = sum(int((models[0][h] != models[1][h]).sum().item()) for h in models[0])
+        out[name] = {"n": n, "runs": rows, "entries_differing_between_methods": diff}
+        log(f"program {name}: " + ", ".join(f"{r['method']} {r['time_ms']} ms" for r in rows) + f", diff {diff}")
+        del bound, models
+        torch.cuda.empty_cache()
+    return out
 
 
 def graphs_dev_release(graphs):

@@ -365,6 +365,7 @@ struct Runner {
   int cfg;
   TileCfg tc;
   std::vector<void*> temps;  // freed after each layer
+  std::vector<EventPair> evs;  // product launches, when the context times kernels
 
   int alloc(int8_t** p, bool keep) {
     const size_t b = (size_t)Np * Np;
@@ -421,8 +422,29 @@ struct Runner {
     p.check = 0;
     p.tiles_m = (int)(Np / tc.bm);
     p.tiles_n = (int)(Np / tc.bn);
+    EventPair ev{nullptr, nullptr};
+    if (g->ctx->timing && hipEventCreate(&ev.a) == hipSuccess && hipEventCreate(&ev.b) == hipSuccess)
+      (void)hipEventRecord(ev.a, s);
     P_HIP(launch_nt_step(P_I8, cfg, p, s));
+    if (ev.a && ev.b) {
+      (void)hipEventRecord(ev.b, s);
+      evs.push_back(ev);
+    }
     return DL_OK;
+  }
+  // Adds the recorded product launches to the context's class-0 statistics
+  // (after the stream has been synchronised) and frees the events.
+  void collect_events(bool ok) {
+    for (auto& e : evs) {
+      float t = 0.f;
+      if (ok && hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+        g->ctx->ms[0] += t;
+        g->ctx->launches[0] += 1;
+      }
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    evs.clear();
   }
 
   Mat view(const Factor& f) {
@@ -893,6 +915,7 @@ int dl_program_run(dl_program* g, int method, void* stream) {
   }
   r.free_temps();
   if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = perr(DL_EHIP, "stream synchronisation failed");
+  r.collect_events(rc == DL_OK);
   if (rc) {
     release(g);
     return rc;
