@@ -554,6 +554,11 @@ struct DmaKernel {
   static constexpr size_t EPI_BYTES = (size_t)BM * EST;
   static constexpr size_t LDS_BYTES = OPER_BYTES > EPI_BYTES ? OPER_BYTES : EPI_BYTES;
   static constexpr int NIB = elem_nibbles(Op::kPrec);  // 4-bit units per element
+  // 16 x 16 fragments with whole groups of four column tiles per wave use the
+  // register epilogue (operands swapped in the MFMA so that a lane holds four
+  // consecutive columns of one output row); not fp8, whose 32-byte fragments
+  // leave no registers for it at four waves per SIMD
+  static constexpr bool SWAPPED = FR == 16 && FN % 4 == 0 && BN == 256 && Op::kPrec != P_FP8;
   static_assert(KC == 4 || KC == 8, "64- or 128-byte slices");
   static_assert(KC % KSTEP_CHUNKS == 0, "slice must hold whole MFMA k-steps");
   static_assert(((BM + BN) / ROWS_PER_DMA) % NWAVES == 0, "DMA instructions must divide evenly");
@@ -567,6 +572,96 @@ template <int N>
 __device__ inline void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Register epilogue of the direct-to-LDS kernel.  With the MFMA operands
+// swapped, item v of lane (g, c) = (lane / 16, lane % 16) in tile (i, j) is
+// C[row WM wm + 16 i + c][col WN wn + 16 j + 4 g + v], so a lane holds four
+// consecutive bytes of one output row.  Four lanes (g = 0..3, same c) hold a
+// row's 64 bytes over the column tiles 4q .. 4q + 3; a 4 x 4 dword transpose
+// across them (shuffles on lane ^ 16 r) leaves lane g with the 16 bytes of
+// tile 4q + g, which are OR-ed with the addend and stored straight to
+// global memory (16 rows x 64 contiguous bytes per instruction).  For the
+// transposed copy the segments also go to LDS (chunk m of row r at chunk
+// m ^ h(r), h(r) = (r ^ (r >> 4)) & 15: conflict-free for the 16-byte
+// writes and the dword reads below); each thread then reads a 16 x 4 byte
+// block as 16 dwords, transposes it in registers with byte permutes and
+// stores four 16-byte segments of out^T.  Returns this thread's ones.
+__device__ inline int ep_swz(int r) { return (r ^ (r >> 4)) & 15; }
+
+template <class K, class Op>
+__device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op::Acc (&acc)[K::FM][K::FN],
+                                           uint8_t* et, int row0, int col0, int wm, int wn, int lane, int tid) {
+  static_assert(K::FR == 16 && Op::NI == 4, "16 x 16 fragments");
+  constexpr int BM = K::WAVES_M * K::FM * 16, BN = K::WAVES_N * K::FN * 16;
+  constexpr int CHUNKS = BN / 16;
+  static_assert(CHUNKS == 16, "the LDS swizzle assumes 256-byte tile rows");
+  const int g = lane >> 4, c = lane & 15;
+  uint8_t* outb = (uint8_t*)p.out;
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i) {
+    const int lr = wm * (K::FM * 16) + 16 * i + c;  // row within the tile
+    const int gr = row0 + lr;
+#pragma unroll
+    for (int q = 0; q < K::FN / 4; ++q) {
+      unsigned P[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const auto& a = acc[i][4 * q + t];
+        P[t] = (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
+               (Op::nz(a, 3) ? 0x1000000u : 0u);
+      }
+      u32x4 v = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = g ^ r;  // offer P[g ^ r]; receive lane (g ^ r)'s P[g] into dword g ^ r
+        const unsigned offer = k == 0 ? P[0] : (k == 1 ? P[1] : (k == 2 ? P[2] : P[3]));
+        const unsigned got = r == 0 ? offer : (unsigned)__shfl_xor((int)offer, 16 * r, 64);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = d == k ? got : v[d];
+      }
+      const int lc = wn * (K::FN * 16) + 16 * (4 * q + g);  // column within the tile
+      const int gc = col0 + lc;
+      if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+      if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+        const int b = gr - gc;
+        v[b >> 2] |= 1u << (8 * (b & 3));
+      }
+      cnt += popc16(v);
+      store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
+      if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = v;
+    }
+  }
+  if (p.outT) {
+    __syncthreads();
+    uint8_t* outt = (uint8_t*)p.outT;
+    constexpr int RB = BM / 16, CB = BN / 4;
+    for (int blk = tid; blk < RB * CB; blk += K::NT) {
+      const int x = blk & 3, rb = (blk >> 2) % RB, w = (blk >> 2) / RB;
+      const int cb = 4 * w + x;  // dword column: tile columns 4 cb .. 4 cb + 3
+      unsigned d[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int lr = 16 * rb + k;
+        d[k] = *(const unsigned*)(et + lr * BN + 16 * ((cb >> 2) ^ ep_swz(lr)) + 4 * x);
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        // byte qq of d[k] is element (row 16 rb + k, column 4 cb + qq)
+        const unsigned sel = (unsigned)qq | ((unsigned)(4 + qq) << 8);
+        u32x4 t;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const unsigned lo = __builtin_amdgcn_perm(d[4 * m + 1], d[4 * m], sel) & 0xffffu;
+          const unsigned hi = __builtin_amdgcn_perm(d[4 * m + 3], d[4 * m + 2], sel);
+          t[m] = lo | (hi << 16);
+        }
+        store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + 4 * cb + qq) * p.ld + row0 + 16 * rb) * K::NIB / 2, t);
+      }
+    }
+  }
+  return cnt;
 }
 
 template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
@@ -647,7 +742,12 @@ k_nt_dma(NTParams p) {
 #pragma unroll
       for (int i = 0; i < K::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < K::FN; ++j) acc[i][j] = Op::mma(af[ks & 1][i], bf[ks & 1][j], acc[i][j]);
+        for (int j = 0; j < K::FN; ++j) {
+          if constexpr (K::SWAPPED)
+            acc[i][j] = Op::mma(bf[ks & 1][j], af[ks & 1][i], acc[i][j]);  // tile of C^T
+          else
+            acc[i][j] = Op::mma(af[ks & 1][i], bf[ks & 1][j], acc[i][j]);
+        }
     }
   };
 
@@ -668,56 +768,60 @@ k_nt_dma(NTParams p) {
   wait_vmcnt<0>();
   __syncthreads();
 
-  // ---- epilogue (identical to k_nt_step)
-  uint8_t* et = smem;
-#pragma unroll
-  for (int i = 0; i < K::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < K::FN; ++j)
-#pragma unroll
-      for (int v = 0; v < Op::NI; ++v) {
-        int r, c;
-        Op::coord(lane, v, r, c);
-        et[(wm * WM + i * K::FR + r) * K::EST + wn * WN + j * K::FR + c] = Op::nz(acc[i][j], v) ? 1 : 0;
-      }
-  __syncthreads();
-
   int cnt = 0;
-  constexpr int SEG_PER_ROW = BN / 16;
-  constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
-  uint8_t* outb = (uint8_t*)p.out;
-#pragma unroll 4
-  for (int i = 0; i < SEGS; ++i) {
-    const int q = tid + i * K::NT;
-    const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
-    u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
-    const int gr = row0 + r, gc = col0 + cs * 16;
-    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
-    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-      const int b = gr - gc;
-      v[b >> 2] |= 1u << (8 * (b & 3));
-    }
-    cnt += popc16(v);
-    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-    if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
-  }
-  if (p.outT) {
-    __syncthreads();
-    constexpr int SEG_PER_COL = BM / 16;
-    constexpr int TSEGS = BN * SEG_PER_COL / K::NT;
-    uint8_t* outt = (uint8_t*)p.outT;
-#pragma unroll 2
-    for (int i = 0; i < TSEGS; ++i) {
-      const int q = tid + i * K::NT;
-      const int c = q % BN, rs = q / BN;
-      u32x4 v;
+  if constexpr (K::SWAPPED) {
+    cnt = dma_epilogue_swapped<K, Op>(p, acc, smem, row0, col0, wm, wn, lane, tid);
+  } else {
+    // ---- epilogue of k_nt_step: the 0/1 tile through LDS byte by byte
+    uint8_t* et = smem;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint8_t* e = et + (rs * 16 + 4 * w) * K::EST + c;
-        v[w] = (unsigned)e[0] | ((unsigned)e[K::EST] << 8) | ((unsigned)e[2 * K::EST] << 16) |
-               ((unsigned)e[3 * K::EST] << 24);
+    for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < K::FN; ++j)
+#pragma unroll
+        for (int v = 0; v < Op::NI; ++v) {
+          int r, c;
+          Op::coord(lane, v, r, c);
+          et[(wm * WM + i * K::FR + r) * K::EST + wn * WN + j * K::FR + c] = Op::nz(acc[i][j], v) ? 1 : 0;
+        }
+    __syncthreads();
+
+    constexpr int SEG_PER_ROW = BN / 16;
+    constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
+    uint8_t* outb = (uint8_t*)p.out;
+#pragma unroll 4
+    for (int i = 0; i < SEGS; ++i) {
+      const int q = tid + i * K::NT;
+      const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
+      u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
+      const int gr = row0 + r, gc = col0 + cs * 16;
+      if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+      if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+        const int b = gr - gc;
+        v[b >> 2] |= 1u << (8 * (b & 3));
       }
-      store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::NIB / 2, v);
+      cnt += popc16(v);
+      store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
+      if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
+    }
+    if (p.outT) {
+      __syncthreads();
+      constexpr int SEG_PER_COL = BM / 16;
+      constexpr int TSEGS = BN * SEG_PER_COL / K::NT;
+      uint8_t* outt = (uint8_t*)p.outT;
+#pragma unroll 2
+      for (int i = 0; i < TSEGS; ++i) {
+        const int q = tid + i * K::NT;
+        const int c = q % BN, rs = q / BN;
+        u32x4 v;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint8_t* e = et + (rs * 16 + 4 * w) * K::EST + c;
+          v[w] = (unsigned)e[0] | ((unsigned)e[K::EST] << 8) | ((unsigned)e[2 * K::EST] << 16) |
+                 ((unsigned)e[3 * K::EST] << 24);
+        }
+        store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + c) * p.ld + row0 + rs * 16) * K::NIB / 2, v);
+      }
     }
   }
   if (p.count) {
@@ -864,45 +968,51 @@ template <int PREC>
 __global__ void __launch_bounds__(256)
 k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, int8_t* AT8,
          uint8_t* Aop, uint8_t* ATop, unsigned long long* ones_slot) {
+  // one 64-row strip per blockIdx.y; the strip's 64 x 64 tiles are shared out
+  // over gridDim.x workgroups, so the ones counter takes few atomics
   __shared__ uint8_t tile[64][64 + 16];
-  const int bi = blockIdx.y, bj = blockIdx.x;
+  const int bi = blockIdx.y;
   const int tid = threadIdx.x;
   const int r = tid >> 2, c0 = (tid & 3) * 16;
   const int gi = bi * 64 + r;
-  const int gj0 = bj * 64 + c0;
-  u32x4 v = {0u, 0u, 0u, 0u};
-  if (gi < n) {
-    const uint8_t* src = A + (int64_t)gi * lda + gj0;
-    if (gj0 + 16 <= n && (((uintptr_t)src) & 15) == 0) {
-      // whole 16-byte segment: fold each byte's bits into its bit 0
-      u32x4 x = *(const u32x4*)src;
-      x |= x >> 4;
-      x |= x >> 2;
-      x |= x >> 1;
-      v = x & 0x01010101u;
-    } else {
+  int cnt = 0;
+  for (int bj = blockIdx.x; bj < Np / 64; bj += gridDim.x) {
+    const int gj0 = bj * 64 + c0;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (gi < n) {
+      const uint8_t* src = A + (int64_t)gi * lda + gj0;
+      if (gj0 + 16 <= n && (((uintptr_t)src) & 15) == 0) {
+        // whole 16-byte segment: fold each byte's bits into its bit 0
+        u32x4 x = *(const u32x4*)src;
+        x |= x >> 4;
+        x |= x >> 2;
+        x |= x >> 1;
+        v = x & 0x01010101u;
+      } else {
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const unsigned b = (gj0 + t < n && src[t] != 0) ? 1u : 0u;
-        v[t >> 2] |= b << (8 * (t & 3));
+        for (int t = 0; t < 16; ++t) {
+          const unsigned b = (gj0 + t < n && src[t] != 0) ? 1u : 0u;
+          v[t >> 2] |= b << (8 * (t & 3));
+        }
       }
     }
-  }
-  *(u32x4*)&tile[r][c0] = v;
-  const int64_t off = (int64_t)gi * Np + bj * 64 + c0;
-  if (A8) *(u32x4*)(A8 + off) = v;
-  if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v);
-  int cnt = popc16(v);
-  __syncthreads();
-  if (AT8 || ATop) {
-    u32x4 t;
+    const int64_t off = (int64_t)gi * Np + bj * 64 + c0;
+    if (A8) *(u32x4*)(A8 + off) = v;
+    if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v);
+    cnt += popc16(v);
+    if (AT8 || ATop) {
+      *(u32x4*)&tile[r][c0] = v;
+      __syncthreads();
+      u32x4 t;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
-      t[w] = (unsigned)tile[c0 + 4 * w][r] | ((unsigned)tile[c0 + 4 * w + 1][r] << 8) |
-             ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
-    const int64_t toff = (int64_t)(bj * 64 + r) * Np + bi * 64 + c0;
-    if (AT8) *(u32x4*)(AT8 + toff) = t;
-    if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
+      for (int w = 0; w < 4; ++w)
+        t[w] = (unsigned)tile[c0 + 4 * w][r] | ((unsigned)tile[c0 + 4 * w + 1][r] << 8) |
+               ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
+      const int64_t toff = (int64_t)(bj * 64 + r) * Np + bi * 64 + c0;
+      if (AT8) *(u32x4*)(AT8 + toff) = t;
+      if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
+      __syncthreads();  // the tile is refilled by the next iteration
+    }
   }
   if (ones_slot) {
     __shared__ int red[4];
@@ -919,7 +1029,7 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
 hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
                          int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
                          hipStream_t s) {
-  dim3 grid(Np / 64, Np / 64);
+  dim3 grid(Np / 64 < 8 ? Np / 64 : 8, Np / 64);
   uint8_t* a = (uint8_t*)Aop;
   uint8_t* at = (uint8_t*)ATop;
   switch (prec) {
