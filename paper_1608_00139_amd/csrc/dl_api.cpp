@@ -199,9 +199,11 @@ int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, 
   std::vector<int64_t> ones_hist(2, 0);
   int64_t iters = -1;  // set when the repeat is seen
   int64_t computed = max_steps >= 1 ? 1 : 0;
-  // chunk sizes: squaring needs about 2 + log2(D) steps, so one chunk of the
-  // worst case; the plain and same-generation series grow their chunk
-  int chunk = mode == M_SQUARE ? 18 : 4;
+  // chunk sizes: squaring needs 2 + log2(D) steps (at most 18 for n <= 65536):
+  // a first chunk of 6 covers D <= 16, then 4, 8, ...; launches after the
+  // fixpoint return at once but still cost a few microseconds each.  The
+  // plain and same-generation series start at 4 and double.
+  int chunk = mode == M_SQUARE ? 6 : 4;
   int64_t s0 = 2;
   int steps_launched = 0;
 
@@ -266,7 +268,7 @@ int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, 
       }
       if ((rc = readback(s0 + cnt - 1))) return rc;
       s0 += cnt;
-      chunk = std::min(chunk * 2, 256);
+      chunk = (mode == M_SQUARE && s0 == 8) ? 4 : std::min(chunk * 2, 256);
     }
   }
 
@@ -343,7 +345,7 @@ int dl_destroy(dl_ctx* c) {
     (void)hipEventDestroy(ep.a);
     (void)hipEventDestroy(ep.b);
   }
-  dl::eps_free(&c->eps);
+  dl::eps_release(&c->eps);
   delete c;
   return DL_OK;
 }

@@ -11,9 +11,13 @@ namespace dl {
 struct EpsWorkspace {
   void* buf = nullptr;
   size_t size = 0;
+  hipStream_t side = nullptr;  // look-ahead stream of the elimination (default priority)
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
+// eps_free releases the buffer; eps_release also the stream and events.
 void eps_free(EpsWorkspace* ws);
+void eps_release(EpsWorkspace* ws);
 int64_t eps_padded_size(int64_t n);
 
 // Solves (I - eps B) X = eps C for X (fp64; B, C caller 0/1 bytes, nonzero =

@@ -283,6 +283,15 @@ void eps_free(EpsWorkspace* ws) {
   ws->size = 0;
 }
 
+void eps_release(EpsWorkspace* ws) {
+  eps_free(ws);
+  for (auto& e : ws->ev)
+    if (e) (void)hipEventDestroy(e);
+  ws->ev[0] = ws->ev[1] = nullptr;
+  if (ws->side) (void)hipStreamDestroy(ws->side);
+  ws->side = nullptr;
+}
+
 static hipError_t ensure(EpsWorkspace* ws, size_t budget_left, size_t need, const char* what, std::string* err) {
   if (need <= ws->size) return hipSuccess;
   if (budget_left && need > budget_left) {
@@ -313,30 +322,59 @@ static hipError_t ensure(EpsWorkspace* ws, size_t budget_left, size_t need, cons
 // Block Gauss-Jordan elimination of the Ns x Ns system held in the left part
 // of W (Ns rows, row stride ldw >= Ns + right-hand-side columns); afterwards
 // columns Ns .. ldw of W hold the solution.  Ns is a multiple of NB.
-static hipError_t gj_eliminate(double* W, int64_t Ns, int64_t ldw, double* Dinv, hipStream_t s, bool timing,
-                               std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs, std::string* err) {
+// Look-ahead: the update of block step k is split into the next block
+// column (K0+NB .. K0+2NB) and the rest; once the former is done, the
+// diagonal block k+1 is final and its inverse runs on the side stream while
+// the rest of the update runs on s.  Dinv holds two NB x NB inverses
+// (steps alternate between them).
+static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t ldw, double* Dinv, hipStream_t s,
+                               bool timing, std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs, std::string* err) {
   const int nblk = (int)(Ns / NB);
+  if (!ws->side) {
+    EPS_CK(hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking), "side stream");
+    for (auto& e : ws->ev) EPS_CK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  }
+  auto timed = [&](const GemmArgs& g) -> hipError_t {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (timing && hipEventCreate(&ea) == hipSuccess && hipEventCreate(&eb) == hipSuccess) (void)hipEventRecord(ea, s);
+    hipError_t e = dgemm(g, s);
+    if (ea && eb) {
+      (void)hipEventRecord(eb, s);
+      evs->push_back({ea, eb});
+    }
+    return e;
+  };
+  hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, s, (const double*)W, ldw, Dinv);
+  EPS_CK(hipGetLastError(), "block inverse");
   for (int k = 0; k < nblk; ++k) {
     const int64_t K0 = (int64_t)k * NB;
+    double* Dk = Dinv + (size_t)(k & 1) * NB * NB;
+    double* Dn = Dinv + (size_t)((k + 1) & 1) * NB * NB;
     const int cols = (int)(ldw - K0 - NB);  // columns right of the diagonal block
-    hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, s, W + K0 * ldw + K0, ldw, Dinv);
-    EPS_CK(hipGetLastError(), "block inverse");
-    // normalise block row k in place: W[k, K0+NB :] = Dinv * W[k, K0+NB :]
-    GemmArgs rp{Dinv, NB, W + K0 * ldw + K0 + NB, ldw, nullptr, 0, W + K0 * ldw + K0 + NB, ldw, NB, cols, NB, 0, -1};
+    // normalise block row k in place: W[k, K0+NB :] = Dinv_k * W[k, K0+NB :]
+    GemmArgs rp{Dk, NB, W + K0 * ldw + K0 + NB, ldw, nullptr, 0, W + K0 * ldw + K0 + NB, ldw, NB, cols, NB, 0, -1};
     EPS_CK(dgemm(rp, s), "row panel product");
-    // eliminate block column k from every other block row
-    if (nblk > 1) {
-      GemmArgs tu{W + K0, ldw, W + K0 * ldw + K0 + NB, ldw, W + K0 + NB, ldw, W + K0 + NB, ldw,
-                  (int)(Ns - NB), cols, NB, 1, k};
-      hipEvent_t ea = nullptr, eb = nullptr;
-      if (timing && hipEventCreate(&ea) == hipSuccess && hipEventCreate(&eb) == hipSuccess) {
-        (void)hipEventRecord(ea, s);
+    if (nblk == 1) break;
+    // eliminate block column k from every other block row: first the next
+    // block column, then (while the next diagonal block is inverted) the rest
+    const bool ahead = k + 1 < nblk;
+    const int first = ahead ? NB : cols;
+    GemmArgs ua{W + K0, ldw, W + K0 * ldw + K0 + NB, ldw, W + K0 + NB, ldw, W + K0 + NB, ldw,
+                (int)(Ns - NB), first, NB, 1, k};
+    EPS_CK(timed(ua), "elimination update");
+    if (ahead) {
+      EPS_CK(hipEventRecord(ws->ev[0], s), "event");
+      EPS_CK(hipStreamWaitEvent(ws->side, ws->ev[0], 0), "wait");
+      hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, ws->side,
+                         (const double*)(W + (K0 + NB) * ldw + K0 + NB), ldw, Dn);
+      EPS_CK(hipGetLastError(), "block inverse");
+      EPS_CK(hipEventRecord(ws->ev[1], ws->side), "event");
+      if (cols > NB) {
+        GemmArgs ub{W + K0, ldw, W + K0 * ldw + K0 + 2 * NB, ldw, W + K0 + 2 * NB, ldw, W + K0 + 2 * NB, ldw,
+                    (int)(Ns - NB), cols - NB, NB, 1, k};
+        EPS_CK(timed(ub), "elimination update");
       }
-      EPS_CK(dgemm(tu, s), "elimination update");
-      if (ea && eb) {
-        (void)hipEventRecord(eb, s);
-        evs->push_back({ea, eb});
-      }
+      EPS_CK(hipStreamWaitEvent(s, ws->ev[1], 0), "wait");
     }
   }
   return hipSuccess;
@@ -351,7 +389,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   const int64_t Np = eps_padded_size(n);
   const int64_t ldw = 2 * Np;
   const size_t wbytes = (size_t)Np * ldw * sizeof(double);
-  const size_t dbytes = (size_t)NB * NB * sizeof(double);
+  const size_t dbytes = 2 * (size_t)NB * NB * sizeof(double);
   EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "epsilon-solve", err), *err);
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Np * ldw;
@@ -360,7 +398,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
                      (int)n, (int)Np, eps, W);
   EPS_CK(hipGetLastError(), "epsilon init");
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  hipError_t e = gj_eliminate(W, Np, ldw, Dinv, s, timing, &evs, err);
+  hipError_t e = gj_eliminate(ws, W, Np, ldw, Dinv, s, timing, &evs, err);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
                        (int)n, R, ldr, X_out, ldx);
@@ -437,14 +475,14 @@ hipError_t stacked_solve(EpsWorkspace* ws, size_t budget_left, const StackDesc& 
   const int64_t Ns = (int64_t)d.M * d.Np;
   const int64_t ldw = Ns + d.Np;
   const size_t wbytes = (size_t)Ns * ldw * sizeof(double);
-  const size_t dbytes = (size_t)NB * NB * sizeof(double);
+  const size_t dbytes = 2 * (size_t)NB * NB * sizeof(double);
   EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "stacked linear solve", err), *err);
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Ns * ldw;
   hipLaunchKernelGGL(k_stack_init, dim3((unsigned)((ldw + 255) / 256), (unsigned)Ns), dim3(256), 0, s, d, Ns, ldw, W);
   EPS_CK(hipGetLastError(), "stacked init");
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  EPS_CK(gj_eliminate(W, Ns, ldw, Dinv, s, false, &evs, err), *err);
+  EPS_CK(gj_eliminate(ws, W, Ns, ldw, Dinv, s, false, &evs, err), *err);
   hipLaunchKernelGGL(k_stack_emit, dim3((unsigned)((d.Np + 255) / 256), (unsigned)Ns), dim3(256), 0, s, d, Ns, ldw,
                      (const double*)W);
   EPS_CK(hipGetLastError(), "stacked threshold");
