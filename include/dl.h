@@ -184,6 +184,14 @@ int dl_set_timing(dl_ctx* ctx, int enable);
 int dl_kernel_stats(dl_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms,
                     int reset);
 
+/* Measured matrix-core peak of this device: every compute unit runs chains of
+ * independent MFMAs on register operands for a few milliseconds; *ops_per_s
+ * receives the rate in operations per second (2 M N K per instruction).
+ * kind: 0 int8 (32x32x32, the faster int8 shape), 1 fp32 16x16x4, 2 bf16
+ * 16x16x32, 3 fp8 e4m3 and 4 fp4 e2m1 16x16x128, 5 fp64 16x16x4.  A reference for the kernels' rates
+ * beside the datasheet figures. */
+int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream);
+
 /* Padded size Np the library uses for n in this mode (multiple of its tile);
  * lets callers size budgets.  kind: 0 = closure, 1 = same generation,
  * 2 = epsilon solve. */

@@ -23,7 +23,7 @@ __all__ = [
     "DLError", "Context", "lib_path", "load",
     "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
     "dl_padded_size", "Batch", "DL_EAGAIN", "dl_solve_linear", "dl_solve_two_sided", "Program",
-    "DL_EVAL_ITERATION", "DL_EVAL_MATRIX",
+    "DL_EVAL_ITERATION", "DL_EVAL_MATRIX", "dl_measure_peak",
 ]
 
 DL_EAGAIN = 6
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
         "dl_program_run": ([vp, ctypes.c_int, vp], ctypes.c_int),
         "dl_program_layer": ([vp, i32, pi32, pi32, i32, pi32, pi32, pi32], ctypes.c_int),
         "dl_program_fetch": ([vp, ctypes.c_char_p, vp, i64, pi64, vp], ctypes.c_int),
+        "dl_measure_peak": ([vp, ctypes.c_int, ctypes.POINTER(dbl), vp], ctypes.c_int),
         "dl_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "dl_last_error": ([], ctypes.c_char_p),
     }
@@ -398,6 +399,17 @@ class Program:
         _check(load().dl_program_fetch(self._h, name.encode(), ctypes.c_void_p(out.data_ptr()), ld,
                                        ctypes.byref(ones), _stream_ptr(stream)))
         return out, int(ones.value)
+
+
+PEAK_KINDS = {"i8": 0, "f32": 1, "bf16": 2, "fp8": 3, "fp4": 4, "f64": 5}
+
+
+def dl_measure_peak(kind: str, ctx: Context | None = None, stream=None) -> float:
+    """Measured MFMA throughput of the device in operations per second."""
+    out = ctypes.c_double()
+    c = _ctx(ctx)
+    _check(load().dl_measure_peak(c.handle, PEAK_KINDS[kind], ctypes.byref(out), _stream_ptr(stream)))
+    return float(out.value)
 
 
 def dl_padded_size(n: int, kind: int, prec=DL_I8) -> int:

@@ -558,7 +558,7 @@ struct DmaKernel {
   // register epilogue (operands swapped in the MFMA so that a lane holds four
   // consecutive columns of one output row); not fp8, whose 32-byte fragments
   // leave no registers for it at four waves per SIMD
-  static constexpr bool SWAPPED = FR == 16 && FN % 4 == 0 && BN == 256 && Op::kPrec != P_FP8;
+  static constexpr bool SWAPPED = ((FR == 16 && FN % 4 == 0) || FR == 32) && BN == 256 && Op::kPrec != P_FP8;
   static_assert(KC == 4 || KC == 8, "64- or 128-byte slices");
   static_assert(KC % KSTEP_CHUNKS == 0, "slice must hold whole MFMA k-steps");
   static_assert(((BM + BN) / ROWS_PER_DMA) % NWAVES == 0, "DMA instructions must divide evenly");
@@ -575,13 +575,15 @@ __device__ inline void wait_vmcnt() {
 }
 
 // Register epilogue of the direct-to-LDS kernel.  With the MFMA operands
-// swapped, item v of lane (g, c) = (lane / 16, lane % 16) in tile (i, j) is
-// C[row WM wm + 16 i + c][col WN wn + 16 j + 4 g + v], so a lane holds four
-// consecutive bytes of one output row.  Four lanes (g = 0..3, same c) hold a
-// row's 64 bytes over the column tiles 4q .. 4q + 3; a 4 x 4 dword transpose
-// across them (shuffles on lane ^ 16 r) leaves lane g with the 16 bytes of
-// tile 4q + g, which are OR-ed with the addend and stored straight to
-// global memory (16 rows x 64 contiguous bytes per instruction).  For the
+// swapped, item v of lane (g, c) = (lane / 16, lane % 16) in 16 x 16 tile
+// (i, j) is C[row WM wm + 16 i + c][col WN wn + 16 j + 4 g + v], so a lane
+// holds four consecutive bytes of one output row.  Four lanes (g = 0..3,
+// same c) hold a row's 64 bytes over the column tiles 4q .. 4q + 3; a 4 x 4
+// dword transpose across them (shuffles on lane ^ 16 r) leaves lane g with
+// the 16 bytes of tile 4q + g, which are OR-ed with the addend and stored
+// straight to global memory (16 rows x 64 contiguous bytes per instruction).
+// 32 x 32 tiles need only one exchange of two dwords between lanes l and
+// l + 32 (32 rows x 32 bytes per instruction).  For the
 // transposed copy the segments also go to LDS (chunk m of row r at chunk
 // m ^ h(r), h(r) = (r ^ (r >> 4)) & 15: conflict-free for the 16-byte
 // writes and the dword reads below); each thread then reads a 16 x 4 byte
@@ -592,45 +594,71 @@ __device__ inline int ep_swz(int r) { return (r ^ (r >> 4)) & 15; }
 template <class K, class Op>
 __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op::Acc (&acc)[K::FM][K::FN],
                                            uint8_t* et, int row0, int col0, int wm, int wn, int lane, int tid) {
-  static_assert(K::FR == 16 && Op::NI == 4, "16 x 16 fragments");
-  constexpr int BM = K::WAVES_M * K::FM * 16, BN = K::WAVES_N * K::FN * 16;
+  static_assert((K::FR == 16 && Op::NI == 4) || (K::FR == 32 && Op::NI == 16), "16 x 16 or 32 x 32 fragments");
+  constexpr int BM = K::WAVES_M * K::FM * K::FR, BN = K::WAVES_N * K::FN * K::FR;
   constexpr int CHUNKS = BN / 16;
   static_assert(CHUNKS == 16, "the LDS swizzle assumes 256-byte tile rows");
-  const int g = lane >> 4, c = lane & 15;
   uint8_t* outb = (uint8_t*)p.out;
   int cnt = 0;
+  // one 16-byte output segment: addend, identity, count, store, LDS copy
+  auto emit = [&](u32x4 v, int lr, int lc) {
+    const int gr = row0 + lr, gc = col0 + lc;
+    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+      const int b = gr - gc;
+      v[b >> 2] |= 1u << (8 * (b & 3));
+    }
+    cnt += popc16(v);
+    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
+    if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = v;
+  };
+  if constexpr (K::FR == 16) {
+    const int g = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int i = 0; i < K::FM; ++i) {
-    const int lr = wm * (K::FM * 16) + 16 * i + c;  // row within the tile
-    const int gr = row0 + lr;
+    for (int i = 0; i < K::FM; ++i) {
+      const int lr = wm * (K::FM * 16) + 16 * i + c;  // row within the tile
 #pragma unroll
-    for (int q = 0; q < K::FN / 4; ++q) {
-      unsigned P[4];
+      for (int q = 0; q < K::FN / 4; ++q) {
+        unsigned P[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const auto& a = acc[i][4 * q + t];
-        P[t] = (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
-               (Op::nz(a, 3) ? 0x1000000u : 0u);
+        for (int t = 0; t < 4; ++t) {
+          const auto& a = acc[i][4 * q + t];
+          P[t] = (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
+                 (Op::nz(a, 3) ? 0x1000000u : 0u);
+        }
+        u32x4 v = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = g ^ r;  // offer P[g ^ r]; receive lane (g ^ r)'s P[g] into dword g ^ r
+          const unsigned offer = k == 0 ? P[0] : (k == 1 ? P[1] : (k == 2 ? P[2] : P[3]));
+          const unsigned got = r == 0 ? offer : (unsigned)__shfl_xor((int)offer, 16 * r, 64);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) v[d] = d == k ? got : v[d];
+        }
+        emit(v, lr, wn * (K::FN * 16) + 16 * (4 * q + g));
       }
-      u32x4 v = {0u, 0u, 0u, 0u};
+    }
+  } else {
+    // 32 x 32 fragments: item 4 q + b of lane (h, r) = (lane / 32, lane % 32)
+    // is C[row 32 i + r][column 32 j + 8 q + 4 h + b]; lanes r and r + 32
+    // swap two dwords so that lane h holds columns 16 h .. 16 h + 15
+    const int h = lane >> 5, rl = lane & 31;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = g ^ r;  // offer P[g ^ r]; receive lane (g ^ r)'s P[g] into dword g ^ r
-        const unsigned offer = k == 0 ? P[0] : (k == 1 ? P[1] : (k == 2 ? P[2] : P[3]));
-        const unsigned got = r == 0 ? offer : (unsigned)__shfl_xor((int)offer, 16 * r, 64);
+    for (int i = 0; i < K::FM; ++i) {
+      const int lr = wm * (K::FM * 32) + 32 * i + rl;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) v[d] = d == k ? got : v[d];
+      for (int j = 0; j < K::FN; ++j) {
+        const auto& a = acc[i][j];
+        unsigned D[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          D[q] = (Op::nz(a, 4 * q) ? 1u : 0u) | (Op::nz(a, 4 * q + 1) ? 0x100u : 0u) |
+                 (Op::nz(a, 4 * q + 2) ? 0x10000u : 0u) | (Op::nz(a, 4 * q + 3) ? 0x1000000u : 0u);
+        const unsigned r0 = (unsigned)__shfl_xor((int)(h ? D[0] : D[2]), 32, 64);
+        const unsigned r1 = (unsigned)__shfl_xor((int)(h ? D[1] : D[3]), 32, 64);
+        const u32x4 v = h ? u32x4{r0, D[2], r1, D[3]} : u32x4{D[0], r0, D[1], r1};
+        emit(v, lr, wn * (K::FN * 32) + 32 * j + 16 * h);
       }
-      const int lc = wn * (K::FN * 16) + 16 * (4 * q + g);  // column within the tile
-      const int gc = col0 + lc;
-      if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
-      if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-        const int b = gr - gc;
-        v[b >> 2] |= 1u << (8 * (b & 3));
-      }
-      cnt += popc16(v);
-      store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-      if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = v;
     }
   }
   if (p.outT) {

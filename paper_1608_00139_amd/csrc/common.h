@@ -95,6 +95,10 @@ hipError_t launch_col_max(const uint8_t* A, int64_t lda, int n, int* out_max, hi
 hipError_t launch_bytes_op(const int8_t* a, const int8_t* b, int ident, int complement, int n, int Np, int8_t* out,
                            int8_t* outT, unsigned long long* cnt, hipStream_t s);
 hipError_t bool_kernels_init();
+// Measured matrix-core throughput (operations per second) of MFMA kind 0 int8,
+// 1 fp32, 2 bf16, 3 fp8, 4 fp4, 5 fp64 on the current device; `sink` must hold
+// 256 ints (never written).
+hipError_t measure_peak(int kind, int* sink, double* ops_per_s, hipStream_t s);
 hipError_t launch_group_step(const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
 int group_tile();
 

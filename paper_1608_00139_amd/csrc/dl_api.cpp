@@ -555,6 +555,15 @@ int dl_solve_two_sided(dl_ctx* ctx, int64_t n, const uint8_t* Q, int64_t ldq, co
   return DL_OK;
 }
 
+int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream) {
+  if (!ctx || !ops_per_s) return fail(DL_EINVAL, "NULL argument");
+  if (kind < 0 || kind > 5) return fail(DL_EINVAL, "unknown MFMA kind");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  DL_HIP(measure_peak(kind, (int*)ctx->ring, ops_per_s, (hipStream_t)stream));
+  return DL_OK;
+}
+
 int dl_set_timing(dl_ctx* ctx, int enable) {
   if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
   ctx->timing = enable != 0;

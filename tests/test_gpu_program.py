@@ -210,3 +210,14 @@ def test_solve_two_sided_threshold(dl, n):
         assert np.array_equal(host(r), model["r"])
     with pytest.raises(dl.DLError):
         dl.dl_solve_two_sided(dev(q), dev(b), dev(c), eps * 1.5)
+
+
+def test_measure_peak_sane(dl):
+    """The measured matrix-core rates are positive and below the datasheet peaks
+    (int8 5.0, fp8 5.0, fp4 10.1, bf16 2.5, fp32 0.157, fp64 0.0786 P/s) with
+    10% margin for clock boost."""
+    caps = {"i8": 5.0e15, "fp8": 5.0e15, "fp4": 10.1e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
+    for kind, cap in caps.items():
+        announce("peak", kind)
+        r = dl.dl_measure_peak(kind)
+        assert 0.05 * cap < r < 1.1 * cap, (kind, r)
