@@ -43,8 +43,9 @@ constexpr int NB = 128;  // block size of the elimination
 // accumulators start from C (for cmode 1, A is negated on its way into LDS,
 // which is exact), so C is read once at the start of the tile and D written
 // once at the end.  Row tiles at or after
-// skip_tile are shifted down by one, which leaves out the row tile skip_tile
-// (the diagonal block row of an elimination step; -1 = none).  D may alias C
+// skip_tile are shifted down by skip_count, which leaves out the row tiles
+// skip_tile .. skip_tile + skip_count - 1 (the pivot rows of an elimination
+// step; skip_tile -1 = none).  D may alias C
 // (every element is read and written by the same lane); D may also alias B
 // when M = K = 128 and cmode = 0 (each workgroup reads its whole B column panel
 // before writing it).  A must not overlap D.
@@ -53,9 +54,10 @@ struct GemmArgs {
   const double* B; int64_t ldb;
   const double* C; int64_t ldc;
   double* D; int64_t ldd;
-  int M, N, K;      // M counts the rows computed (without the skipped tile)
+  int M, N, K;      // M counts the rows computed (without the skipped tiles)
   int cmode;
   int skip_tile;
+  int skip_count = 1;
 };
 
 // Output coordinate of accumulator element `item` of lane `lane` for
@@ -78,7 +80,7 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
   // column-major walk over tiles keeps one B column panel hot across rows
   int tm = blockIdx.x % tiles_m;
   const int tn = blockIdx.x / tiles_m;
-  if (g.skip_tile >= 0 && tm >= g.skip_tile) ++tm;
+  if (g.skip_tile >= 0 && tm >= g.skip_tile) tm += g.skip_count;
   const int m0 = tm * BM, n0 = tn * BN;
 
   v4d acc[FM][FN];
@@ -319,17 +321,60 @@ static hipError_t ensure(EpsWorkspace* ws, size_t budget_left, size_t need, cons
     }                              \
   } while (0)
 
+// Gauss-Jordan elimination, block size NB, of the Ns x Ns system in the left
+// part of V (row stride ldv, Ns + right-hand-side columns); afterwards the
+// columns Ns .. ldv of V hold the solution.  Used on the P x 2P panel
+// systems [D | I] below, whose right half becomes D^-1.  Dinv: NB x NB.
+static hipError_t gj_blocks(double* V, int64_t Ns, int64_t ldv, double* Dinv, hipStream_t s, std::string* err) {
+  const int nblk = (int)(Ns / NB);
+  for (int k = 0; k < nblk; ++k) {
+    const int64_t K0 = (int64_t)k * NB;
+    const int cols = (int)(ldv - K0 - NB);
+    hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, s, (const double*)(V + K0 * ldv + K0), ldv, Dinv);
+    EPS_CK(hipGetLastError(), "block inverse");
+    GemmArgs rp{Dinv, NB, V + K0 * ldv + K0 + NB, ldv, nullptr, 0, V + K0 * ldv + K0 + NB, ldv, NB, cols, NB, 0, -1};
+    EPS_CK(dgemm(rp, s), "row panel product");
+    if (nblk > 1) {
+      GemmArgs up{V + K0, ldv, V + K0 * ldv + K0 + NB, ldv, V + K0 + NB, ldv, V + K0 + NB, ldv,
+                  (int)(Ns - NB), cols, NB, 1, k};
+      EPS_CK(dgemm(up, s), "elimination update");
+    }
+  }
+  return hipSuccess;
+}
+
+// V = [ W[r0 : r0 + P, r0 : r0 + P] | I_P ]  (P x 2P)
+__global__ void __launch_bounds__(256)
+k_panel_copy(const double* W, int64_t ldw, int64_t r0, int P, double* V) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < 2 * P; j += gridDim.x * 256)
+    V[(int64_t)i * 2 * P + j] = j < P ? W[(r0 + i) * ldw + r0 + j] : (j - P == i ? 1.0 : 0.0);
+}
+
+// W[r0 + i, c0 + j] = Y[i, j] for i < P, j < n (Y row stride ldy)
+__global__ void __launch_bounds__(256)
+k_rows_store(const double* Y, int64_t ldy, int P, int64_t n, double* W, int64_t ldw, int64_t r0, int64_t c0) {
+  const int i = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+    W[(r0 + i) * ldw + c0 + j] = Y[i * ldy + j];
+}
+
 // Block Gauss-Jordan elimination of the Ns x Ns system held in the left part
 // of W (Ns rows, row stride ldw >= Ns + right-hand-side columns); afterwards
 // columns Ns .. ldw of W hold the solution.  Ns is a multiple of NB.
-// Look-ahead: the update of block step k is split into the next block
-// column (K0+NB .. K0+2NB) and the rest; once the former is done, the
-// diagonal block k+1 is final and its inverse runs on the side stream while
-// the rest of the update runs on s.  Dinv holds two NB x NB inverses
-// (steps alternate between them).
-static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t ldw, double* Dinv, hipStream_t s,
+// Pivot panels of P = kPanel rows and columns: with D = W[p, p] and T the
+// columns right of the panel,
+//   Y = D^-1 W[p, T];   W[q, T] -= W[q, p] Y for every row q outside p;
+//   W[p, T] = Y,
+// so the trailing matrix is read and written once per panel with K = P in
+// the update product (fp64 MFMA; the update is bound by that traffic at
+// small K).  D^-1 comes from gj_blocks on [D | I].  Look-ahead: the update
+// of the next panel's columns runs first; the next D is then final and is
+// inverted on the side stream while the rest of the update runs.
+constexpr int kPanel = 4 * NB;
+
+static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t ldw, double* scratch, hipStream_t s,
                                bool timing, std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs, std::string* err) {
-  const int nblk = (int)(Ns / NB);
   if (!ws->side) {
     EPS_CK(hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking), "side stream");
     for (auto& e : ws->ev) EPS_CK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
@@ -344,40 +389,60 @@ static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t 
     }
     return e;
   };
-  hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, s, (const double*)W, ldw, Dinv);
-  EPS_CK(hipGetLastError(), "block inverse");
-  for (int k = 0; k < nblk; ++k) {
-    const int64_t K0 = (int64_t)k * NB;
-    double* Dk = Dinv + (size_t)(k & 1) * NB * NB;
-    double* Dn = Dinv + (size_t)((k + 1) & 1) * NB * NB;
-    const int cols = (int)(ldw - K0 - NB);  // columns right of the diagonal block
-    // normalise block row k in place: W[k, K0+NB :] = Dinv_k * W[k, K0+NB :]
-    GemmArgs rp{Dk, NB, W + K0 * ldw + K0 + NB, ldw, nullptr, 0, W + K0 * ldw + K0 + NB, ldw, NB, cols, NB, 0, -1};
-    EPS_CK(dgemm(rp, s), "row panel product");
-    if (nblk == 1) break;
-    // eliminate block column k from every other block row: first the next
-    // block column, then (while the next diagonal block is inverted) the rest
-    const bool ahead = k + 1 < nblk;
-    const int first = ahead ? NB : cols;
-    GemmArgs ua{W + K0, ldw, W + K0 * ldw + K0 + NB, ldw, W + K0 + NB, ldw, W + K0 + NB, ldw,
-                (int)(Ns - NB), first, NB, 1, k};
-    EPS_CK(timed(ua), "elimination update");
+  // scratch: V[2] (kPanel x 2 kPanel each), Dinv (NB x NB), Y (kPanel x ldw)
+  double* V[2] = {scratch, scratch + (size_t)2 * kPanel * kPanel};
+  double* Dinv = V[1] + (size_t)2 * kPanel * kPanel;
+  double* Y = Dinv + (size_t)NB * NB;
+  auto invert = [&](int64_t r0, int P, double* v, hipStream_t st) -> hipError_t {
+    hipLaunchKernelGGL(k_panel_copy, dim3((unsigned)((2 * P + 255) / 256), (unsigned)P), dim3(256), 0, st,
+                       (const double*)W, ldw, r0, P, v);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return gj_blocks(v, P, 2 * P, Dinv, st, err);  // panel inversions never overlap
+  };
+  int P = (int)std::min<int64_t>(kPanel, Ns);
+  EPS_CK(invert(0, P, V[0], s), "panel inverse");
+  int t = 0;
+  for (int64_t K0 = 0; K0 < Ns; K0 += P, ++t) {
+    P = (int)std::min<int64_t>(kPanel, Ns - K0);
+    const double* Dp = V[t & 1] + P;  // D^-1, row stride 2P
+    const int64_t T0 = K0 + P;
+    const int nT = (int)(ldw - T0);
+    // Y = D^-1 W[p, T]
+    GemmArgs gy{Dp, 2 * P, W + K0 * ldw + T0, ldw, nullptr, 0, Y, ldw, P, nT, P, 0, -1};
+    EPS_CK(dgemm(gy, s), "panel row product");
+    const bool ahead = T0 < Ns;
+    const int Pn = ahead ? (int)std::min<int64_t>(kPanel, Ns - T0) : 0;
+    const int first = ahead ? Pn : nT;
+    if (Ns > P) {
+      GemmArgs ua{W + K0, ldw, Y, ldw, W + T0, ldw, W + T0, ldw, (int)(Ns - P), first, P, 1, (int)(K0 / 128)};
+      ua.skip_count = P / 128;
+      EPS_CK(timed(ua), "elimination update");
+    }
     if (ahead) {
       EPS_CK(hipEventRecord(ws->ev[0], s), "event");
       EPS_CK(hipStreamWaitEvent(ws->side, ws->ev[0], 0), "wait");
-      hipLaunchKernelGGL(k_block_inverse, dim3(1), dim3(1024), 0, ws->side,
-                         (const double*)(W + (K0 + NB) * ldw + K0 + NB), ldw, Dn);
-      EPS_CK(hipGetLastError(), "block inverse");
+      EPS_CK(invert(T0, Pn, V[(t + 1) & 1], ws->side), "panel inverse");
       EPS_CK(hipEventRecord(ws->ev[1], ws->side), "event");
-      if (cols > NB) {
-        GemmArgs ub{W + K0, ldw, W + K0 * ldw + K0 + 2 * NB, ldw, W + K0 + 2 * NB, ldw, W + K0 + 2 * NB, ldw,
-                    (int)(Ns - NB), cols - NB, NB, 1, k};
+      if (nT > Pn) {
+        GemmArgs ub{W + K0, ldw, Y + Pn, ldw, W + T0 + Pn, ldw, W + T0 + Pn, ldw, (int)(Ns - P), nT - Pn, P, 1,
+                    (int)(K0 / 128)};
+        ub.skip_count = P / 128;
         EPS_CK(timed(ub), "elimination update");
       }
-      EPS_CK(hipStreamWaitEvent(s, ws->ev[1], 0), "wait");
     }
+    // the pivot rows take Y
+    hipLaunchKernelGGL(k_rows_store, dim3((unsigned)((nT + 255) / 256), (unsigned)P), dim3(256), 0, s,
+                       (const double*)Y, ldw, P, (int64_t)nT, W, ldw, K0, T0);
+    EPS_CK(hipGetLastError(), "pivot rows");
+    if (ahead) EPS_CK(hipStreamWaitEvent(s, ws->ev[1], 0), "wait");
   }
   return hipSuccess;
+}
+
+// Scratch doubles gj_eliminate needs beyond W.
+static size_t gj_scratch_doubles(int64_t ldw) {
+  return (size_t)4 * kPanel * kPanel + (size_t)NB * NB + (size_t)kPanel * ldw;
 }
 
 hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* B, int64_t ldb,
@@ -389,7 +454,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   const int64_t Np = eps_padded_size(n);
   const int64_t ldw = 2 * Np;
   const size_t wbytes = (size_t)Np * ldw * sizeof(double);
-  const size_t dbytes = 2 * (size_t)NB * NB * sizeof(double);
+  const size_t dbytes = gj_scratch_doubles(ldw) * sizeof(double);
   EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "epsilon-solve", err), *err);
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Np * ldw;
@@ -475,7 +540,7 @@ hipError_t stacked_solve(EpsWorkspace* ws, size_t budget_left, const StackDesc& 
   const int64_t Ns = (int64_t)d.M * d.Np;
   const int64_t ldw = Ns + d.Np;
   const size_t wbytes = (size_t)Ns * ldw * sizeof(double);
-  const size_t dbytes = 2 * (size_t)NB * NB * sizeof(double);
+  const size_t dbytes = gj_scratch_doubles(ldw) * sizeof(double);
   EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "stacked linear solve", err), *err);
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Ns * ldw;

@@ -221,3 +221,59 @@ def test_measure_peak_sane(dl):
         announce("peak", kind)
         r = dl.dl_measure_peak(kind)
         assert 0.05 * cap < r < 1.1 * cap, (kind, r)
+
+
+def test_edge_sizes_and_strides(dl):
+    """n = 0 and n = 1 for the solvers and programs; strided (ld > n) inputs
+    and outputs are read and written correctly (padding columns untouched)."""
+    import torch
+
+    z = torch.zeros((0, 0), dtype=torch.uint8, device="cuda")
+    r, x = dl.dl_solve_linear(z, z, 0.5, want_x=True)
+    assert r.shape == (0, 0)
+    r, x, d = dl.dl_solve_two_sided(z, z, z, 0.5)
+    assert r.shape == (0, 0) and d == 0
+    one = dev(np.ones((1, 1), np.uint8))
+    r, x = dl.dl_solve_linear(one, one, 0.5, want_x=True)
+    assert host(r)[0, 0] == 1 and abs(host(x)[0, 0] - 1.0) < 1e-15  # x = 0.5 (1 + x)
+    n = 150
+    b = _rand(n, 2.0 / n, 3)
+    c = _rand(n, 2.0 / n, 4)
+    big = np.zeros((n, n + 21), np.uint8)
+    big[:, :n] = b * 7
+    bview = dev(big)[:, :n]
+    out_big = torch.full((n, n + 9), 5, dtype=torch.uint8, device="cuda")
+    eps = dl.dl_eps_bound(dev(b))
+    announce("strided solve_linear")
+    dl.dl_solve_linear(bview, dev(c), eps, out=out_big[:, :n])
+    tcb = oracle.tc_seminaive(b)[0].astype(np.int64)
+    want = ((c.astype(np.int64) + tcb @ c.astype(np.int64)) > 0).astype(np.uint8)
+    assert np.array_equal(host(out_big)[:, :n], want)
+    assert np.all(host(out_big)[:, n:] == 5)
+    announce("strided program")
+    prog = dl.Program(CASES["tc_right"][0])
+    prog.bind("e", bview)
+    prog.run(dl.DL_EVAL_MATRIX)
+    o2 = torch.full((n, n + 3), 9, dtype=torch.uint8, device="cuda")
+    _, ones = prog.fetch("tc", out=o2[:, :n])
+    ref = oracle.tc_seminaive(b)[0]
+    assert np.array_equal(host(o2)[:, :n], ref) and ones == int(ref.sum())
+    assert np.all(host(o2)[:, n:] == 9)
+    prog.close()
+
+
+def test_program_rerun_and_rebind(dl):
+    """A program can be run again after rebinding its relations; results follow."""
+    n = 90
+    prog = dl.Program(CASES["even_odd"][0])
+    for seed in range(3):
+        e = _rand(n, 2.0 / n, 50 + seed, loops=False)
+        ed = dev(e)
+        prog.bind("e", ed)
+        for method in (dl.DL_EVAL_MATRIX, dl.DL_EVAL_ITERATION):
+            announce("rerun", seed, method)
+            prog.run(method)
+            want, _ = oprog.evaluate(CASES["even_odd"][0], {"e": e}, n)
+            for name in ("odd", "even"):
+                assert np.array_equal(host(prog.fetch(name, n=n)[0]), want[name]), (seed, method, name)
+    prog.close()
