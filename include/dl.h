@@ -116,11 +116,12 @@ int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* 
                 void* stream);
 
 /* Linear epsilon form (Sec. 4, Proposition 1 and Theorem 1): solves
- * (I - eps A) X = eps A in fp64 by block Gaussian elimination without
- * pivoting (each diagonal block inverted, panels and trailing updates as
- * fp64 matrix products) and block back substitution, then writes
- * R = [X > 0].  Device workspace: (n rounded up to 128)^2 * 16 bytes plus
- * a panel.
+ * (I - eps A) X = eps A in fp64 by block Gauss-Jordan elimination without
+ * pivoting (diagonal panels inverted, the rows and the trailing matrix
+ * updated by fp64 matrix products), then writes R = [X > 0].  Without
+ * pivoting, every update adds terms of one sign, so R is exact up to fp64
+ * underflow.  Device workspace: (n rounded up to 128)^2 * 16 bytes plus
+ * 512 x (2 n) doubles of panel scratch.
  *   eps  must satisfy 0 < eps <= 1 / (1 + ||A||_inf), ||A||_inf = max row
  *        sum of the 0/1 matrix (Lemma 1); otherwise DL_EINVAL.
  *   X    optional device double [n x ldx] receiving the real solution

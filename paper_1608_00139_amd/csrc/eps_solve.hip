@@ -2,15 +2,16 @@
 // X = (I - eps A)^-1 eps A in fp64, then R = [X > 0].
 //
 // Method: block Gauss-Jordan elimination without pivoting on the augmented
-// matrix W = [ I - eps A | eps A ]  (Np x 2Np, row-major), block size
-// NB = 128:
-//   for each block row k (rows K0 .. K0+NB):
-//     Dinv = W_kk^-1                                  (Gauss-Jordan, one workgroup)
-//     W[k, K0+NB :] = Dinv * W[k, K0+NB :]             (fp64 MFMA product, in place)
-//     W[i, K0+NB :] -= W[i, K0 : K0+NB] * W[k, K0+NB :]  for every block row i != k
-// Columns left of K0+NB are never touched again (they would hold the
-// identity and zeros), so after the last block the right half of W is X.
-// 3 Np^3 flops, almost all in one full-height product per block step.
+// matrix W = [ I - eps A | eps A ]  (Np x 2Np, row-major), in pivot panels
+// p of 512 rows and columns (T = the columns right of the panel):
+//   D^-1 = W[p, p]^-1             (the same elimination at block size 128 on
+//                                  [W[p, p] | I]; 128 x 128 blocks inverted
+//                                  by Gauss-Jordan in one workgroup)
+//   Y = D^-1 W[p, T];  W[q, T] -= W[q, p] Y for every row q outside p;
+//   W[p, T] = Y                    (fp64 MFMA products)
+// Columns left of T are never touched again (they would hold the identity
+// and zeros), so after the last panel the right half of W is X.  About
+// 3 Np^3 flops, almost all in one full-height product per panel.
 //
 // Why no pivoting: M = I - eps A has unit diagonal and off-diagonal entries
 // <= 0 with eps * (row sum of A) < 1 (Lemma 1's eps bound), so M is a
