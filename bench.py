@@ -80,8 +80,8 @@ def main() -> int:
     if args.eps_only:
         return eps_only()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path, so --gpus above 1 "
+              "is not supported", file=sys.stderr)
         return 2
 
     import numpy as np
