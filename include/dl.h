@@ -2,13 +2,17 @@
  * dl.h -- C ABI of the MI355X (gfx950) library for linear-algebraic Datalog
  * evaluation (T. Sato, "A Linear Algebraic Approach to Datalog Evaluation").
  *
- * The library computes least Herbrand models of two linear, binary-predicate
- * programs as fixpoints of thresholded dense N x N matrix products:
+ * The library computes least Herbrand models of linear, binary-predicate
+ * Datalog programs as fixpoints of thresholded dense N x N matrix products:
  *   - transitive closure   R = min1(R1 + R1 R)           (Sec. 3, program DB1)
  *     and its repeated-squaring form R = min1(R1 + R R)  (Sec. 8)
  *   - same generation      S = min1(I + R1 S R1^T)       (Sec. 7.2)
  *   - the purely linear form of Sec. 4, Proposition 1:
  *     X = (I - eps R1)^-1 eps R1, thresholded at > 0      (Theorem 1)
+ *   - the epsilon forms of Sec. 6: tail-recursive X = eps (C + B X) and
+ *     two-sided X = eps (Q + B X C) equations, the same-generation one
+ *   - whole programs, layered by strongly connected components (Sec. 5),
+ *     with stratified negation (Sec. 8)
  *
  * Matrix conventions (all entry points):
  *   - Every matrix is n x n, row-major, 0-based: element (i, j) at p[i*ld + j],
@@ -40,7 +44,8 @@
  * with iters = 1 (the empty model).
  *
  * Threading: a context may be used by one thread at a time; use one
- * context per thread (or per stream) for concurrency.
+ * context per thread (or per stream) for concurrency.  Programs and batches
+ * use their context's scratch, so their calls count as calls on it.
  */
 #ifndef DL_H_
 #define DL_H_
