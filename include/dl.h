@@ -44,8 +44,8 @@
  * with iters = 1 (the empty model).
  *
  * Threading: a context may be used by one thread at a time; use one
- * context per thread (or per stream) for concurrency.  Programs and batches
- * use their context's scratch, so their calls count as calls on it.
+ * context per thread (or per stream) for concurrency.  A program uses its
+ * context's scratch, so calls on the program count as calls on the context.
  */
 #ifndef DL_H_
 #define DL_H_
