@@ -132,7 +132,7 @@ void settle(Req& r) {
 extern "C" {
 
 int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** out) {
-  if (!out || pool_bytes == 0 || max_active <= 0) return bfail(DL_EINVAL, "bad batch arguments");
+  if (!out || pool_bytes == 0 || max_active <= 0 || max_active > kRing) return bfail(DL_EINVAL, "bad batch arguments");
   *out = nullptr;
   (void)ctx;
   dl_batch* b = new (std::nothrow) dl_batch();
