@@ -231,6 +231,15 @@ int dl_batch_destroy(dl_batch* batch);
 int dl_batch_submit(dl_batch* batch, int kind, int64_t n, const uint8_t* A, int64_t lda, int64_t tag,
                     int32_t* slot, void* stream);
 
+/* Admit a request given as an edge list: edges is a device int32 array of m
+ * pairs (i, j), row-major [m x 2], meaning r(e_i, e_j); pairs outside
+ * [0, n) are skipped and repeated pairs count once.  The relation is built
+ * directly in the request's pool buffers (one clear and one scatter launch,
+ * no dense n x n input).  Otherwise as dl_batch_submit; the caller may
+ * reuse edges after the stream reaches this point. */
+int dl_batch_submit_edges(dl_batch* batch, int kind, int64_t n, const int32_t* edges, int64_t m, int64_t tag,
+                          int32_t* slot, void* stream);
+
 /* One round (blocks until its model sizes are read back).  *active receives
  * the number of requests still running, *finished the number that finished
  * in this round. */

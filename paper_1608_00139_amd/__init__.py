@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
         "dl_batch_create": ([vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "dl_batch_destroy": ([vp], ctypes.c_int),
         "dl_batch_submit": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
+        "dl_batch_submit_edges": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
         "dl_batch_step": ([vp, pi32, pi32, vp], ctypes.c_int),
         "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
         "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
@@ -451,6 +452,23 @@ class Batch:
         slot = ctypes.c_int32()
         rc = load().dl_batch_submit(self._h, int(kind), n, ctypes.c_void_p(A.data_ptr()), lda, int(tag),
                                     ctypes.byref(slot), _stream_ptr(self.stream))
+        if rc == DL_EAGAIN:
+            return None
+        _check(rc)
+        return int(slot.value)
+
+    def dl_batch_submit_edges(self, kind: int, n: int, edges: torch.Tensor, tag: int) -> int | None:
+        """Admit a request given as a device int32 [m, 2] edge list over n
+        constants; returns its slot, or None when the pool is full."""
+        if not isinstance(edges, torch.Tensor) or not edges.is_cuda or edges.dtype != torch.int32:
+            raise TypeError("edges must be a device int32 tensor")
+        if edges.numel() and (edges.dim() != 2 or edges.shape[1] != 2 or not edges.is_contiguous()):
+            raise ValueError("edges must be a contiguous [m, 2] tensor")
+        m = edges.shape[0] if edges.numel() else 0
+        slot = ctypes.c_int32()
+        rc = load().dl_batch_submit_edges(self._h, int(kind), int(n),
+                                          ctypes.c_void_p(edges.data_ptr()) if m else None, m, int(tag),
+                                          ctypes.byref(slot), _stream_ptr(self.stream))
         if rc == DL_EAGAIN:
             return None
         _check(rc)

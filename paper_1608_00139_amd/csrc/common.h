@@ -94,6 +94,11 @@ hipError_t launch_col_max(const uint8_t* A, int64_t lda, int n, int* out_max, hi
 // out may alias a or b).  Adds the ones of the result to *cnt if cnt is set.
 hipError_t launch_bytes_op(const int8_t* a, const int8_t* b, int ident, int complement, int n, int Np, int8_t* out,
                            int8_t* outT, unsigned long long* cnt, hipStream_t s);
+// Sets byte (i, j) of M (and of M2, and byte (j, i) of MT, when not null) for
+// every edge (i, j) of the device list edges[2 m] with 0 <= i, j < n; adds
+// the number of distinct edges to *ones.  The matrices must be zeroed.
+hipError_t launch_scatter_edges(const int32_t* edges, int64_t m, int n, int Np, int8_t* M, int8_t* M2, int8_t* MT,
+                                unsigned long long* ones, hipStream_t s);
 hipError_t bool_kernels_init();
 // Measured matrix-core throughput (operations per second) of MFMA kind 0 int8,
 // 1 fp32, 2 bf16, 3 fp8, 4 fp4, 5 fp64 on the current device; `sink` must hold

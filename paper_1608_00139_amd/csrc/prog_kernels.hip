@@ -1,7 +1,7 @@
-// prog_kernels.hip -- elementwise kernels of layered program evaluation on
-// int8 0/1 matrices (Np x Np, row-major, zero padded): disjunction of
-// relations, complement for negated atoms (Sec. 8), transposed copies for
-// converse atoms, and the column-sum norm.
+// prog_kernels.hip -- elementwise kernels on int8 0/1 matrices (Np x Np,
+// row-major, zero padded): disjunction of relations, complement for negated
+// atoms (Sec. 8), transposed copies for converse atoms, the column-sum norm,
+// and the edge-list scatter that admits serving requests.
 #include "common.h"
 
 namespace dl {
@@ -81,6 +81,47 @@ __global__ void __launch_bounds__(256) k_col_max(const uint8_t* A, int64_t lda, 
 
 hipError_t launch_col_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s) {
   hipLaunchKernelGGL(k_col_max, dim3((n + 255) / 256), dim3(256), 0, s, A, lda, n, out_max);
+  return hipGetLastError();
+}
+
+// Relation from an edge list: for each (i, j) with 0 <= i, j < n, set byte
+// (i, j) of M and, when set, of M2 and byte (j, i) of MT (all Np x Np, zeroed
+// beforehand).  Duplicate edges are counted once: the byte of M is set with
+// an atomic OR on its 32-bit word, and only the edge that flips it counts.
+// Edges outside [0, n) are skipped.
+__global__ void __launch_bounds__(256)
+k_scatter_edges(const int32_t* __restrict__ edges, int64_t m, int n, int Np, int8_t* M, int8_t* M2, int8_t* MT,
+                unsigned long long* ones) {
+  int c = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
+    const int i = edges[2 * e], j = edges[2 * e + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n) continue;
+    const int64_t off = (int64_t)i * Np + j;
+    unsigned* w = (unsigned*)(M + (off & ~(int64_t)3));
+    const unsigned bit = 1u << (8 * (off & 3));
+    const unsigned old = atomicOr(w, bit);
+    if (!(old & bit)) ++c;
+    if (M2) M2[off] = 1;
+    if (MT) MT[(int64_t)j * Np + i] = 1;
+  }
+  if (!ones) return;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int t = red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(ones, (unsigned long long)t);
+  }
+}
+
+hipError_t launch_scatter_edges(const int32_t* edges, int64_t m, int n, int Np, int8_t* M, int8_t* M2, int8_t* MT,
+                                unsigned long long* ones, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t blocks = (m + 255) / 256;
+  hipLaunchKernelGGL(k_scatter_edges, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, edges, m, n,
+                     Np, M, M2, MT, ones);
   return hipGetLastError();
 }
 

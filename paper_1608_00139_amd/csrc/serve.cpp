@@ -185,12 +185,17 @@ int dl_batch_destroy(dl_batch* b) {
   return DL_OK;
 }
 
-int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t lda, int64_t tag, int32_t* slot_out,
-                    void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Admission shared by both submit calls: a slot, pool memory, the request's
+// buffers; `fill` writes the relation into them.
+template <class Fill>
+int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipStream_t s, Fill fill) {
   if (!b || !slot_out) return bfail(DL_EINVAL, "NULL argument");
   if (kind != 0 && kind != 1) return bfail(DL_EINVAL, "kind must be 0 (closure) or 1 (same generation)");
-  if (n <= 0 || n > 16384 || !A || lda < n) return bfail(DL_EINVAL, "bad relation (1 <= n <= 16384, lda >= n)");
-  hipStream_t s = (hipStream_t)stream;
+  if (n <= 0 || n > 16384) return bfail(DL_EINVAL, "bad relation size (1 <= n <= 16384)");
   int slot = -1;
   for (int i = 0; i < b->max_active; ++i)
     if (!b->req[i].used) {
@@ -220,18 +225,62 @@ int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t 
     r.add = base;
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * (1 + i);  // R0, R0T, R1, R1T
     BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
-    BHIP(launch_ingest(P_I8, A, lda, (int)n, (int)Np, (int8_t*)r.add, nullptr, r.b[2], r.b[3], adm, s));
+    // addend A, R^(1) = A, R^(1)T = A^T
+    int rc = fill(n, Np, (int8_t*)r.add, (int8_t*)r.b[2], (int8_t*)r.b[3], adm);
+    if (rc) {
+      pool_free(b, off, bytes);
+      r = Req();
+      return rc;
+    }
     r.computed = 1;
     r.admit_count = true;
   } else {
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // P, S0, S1, T
-    BHIP(launch_ingest(P_I8, A, lda, (int)n, (int)Np, nullptr, nullptr, r.b[0], nullptr, nullptr, s));
+    int rc = fill(n, Np, (int8_t*)r.b[0], nullptr, nullptr, nullptr);
+    if (rc) {
+      pool_free(b, off, bytes);
+      r = Req();
+      return rc;
+    }
     BHIP(launch_identity(P_I8, r.b[2], (int)Np, (int)n, s));
     r.computed = 1;
     r.ones.push_back(n);  // S^(1) = I: one fact diag(x, x) per constant
   }
   *slot_out = slot;
   return DL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t lda, int64_t tag, int32_t* slot_out,
+                    void* stream) {
+  if (!A || lda < n) return bfail(DL_EINVAL, "bad relation (A NULL or lda < n)");
+  hipStream_t s = (hipStream_t)stream;
+  return admit(b, kind, n, tag, slot_out, s,
+               [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
+                 // closure: M = addend, M2 = R^(1), MT = R^(1)T; same generation: M = P
+                 if (M2)
+                   BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, M, nullptr, M2, MT, ones, s));
+                 else
+                   BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, nullptr, nullptr, M, nullptr, nullptr, s));
+                 return DL_OK;
+               });
+}
+
+int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges, int64_t m, int64_t tag,
+                          int32_t* slot_out, void* stream) {
+  if (m < 0 || (m > 0 && !edges)) return bfail(DL_EINVAL, "bad edge list");
+  hipStream_t s = (hipStream_t)stream;
+  return admit(b, kind, n, tag, slot_out, s,
+               [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
+                 const size_t mb = (size_t)Np * Np;
+                 // the request's buffers are contiguous: clear them in one call
+                 BHIP(hipMemsetAsync(M, 0, (kind == 0 ? 5 : 1) * mb, s));
+                 BHIP(launch_scatter_edges(edges, m, (int)nn, (int)Np, M, M2, MT, ones, s));
+                 return DL_OK;
+               });
 }
 
 int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void* stream) {

@@ -60,7 +60,8 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
                batch: Batch | None = None) -> tuple[StreamStats, dict]:
     """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
 
-    make_input(req) returns the request's relation as a uint8 device tensor.
+    make_input(req) returns the request's relation as a uint8 device tensor
+    (dense n x n) or as a device int32 [m, 2] edge list.
     Returns the statistics and, if keep_results, {rid: (model tensor, iters)}.
     """
     b = batch or Batch(pool_bytes, max_active)
@@ -78,7 +79,11 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
         while waiting:
             req = waiting[0]
             kind = Batch.TC if req.kind == "tc" else Batch.SG
-            slot = b.dl_batch_submit(kind, make_input(req), req.rid)
+            rel = make_input(req)
+            if rel.dtype == torch.int32:
+                slot = b.dl_batch_submit_edges(kind, req.n, rel, req.rid)
+            else:
+                slot = b.dl_batch_submit(kind, rel, req.rid)
             if slot is None:
                 if not inflight:
                     raise RuntimeError(f"request {req.rid} (n={req.n}) does not fit an empty pool")

@@ -107,3 +107,48 @@ def test_edge_requests(dl):
     assert small.dl_batch_submit(small.TC, dev(np.zeros((300, 300), np.uint8)), 7) is None
     with pytest.raises(dl.DLError):
         b.dl_batch_fetch(3)  # never used slot
+
+
+def test_edge_list_admission(dl):
+    """Requests admitted as device edge lists give the same models and
+    iteration counts as dense admission and the oracle; repeated pairs count
+    once, pairs outside [0, n) are skipped, an empty list is the empty relation."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    reqs = dlgen.serving_stream(30, seed=11, rate=0.0, n_lo=64, n_hi=900)
+
+    def edges_of(r):
+        e = dlgen.request_edges(r).astype(np.int32)
+        rng = np.random.default_rng(r.rid)
+        extra = [e[: min(len(e), 5)], np.array([[r.n, 0], [0, r.n], [-1, 3], [2, -5]], np.int32)]
+        return torch.from_numpy(np.concatenate([e] + extra)).cuda()
+
+    announce("serve edges", len(reqs))
+    stats, results = run_stream(reqs, edges_of, pool_bytes=1 << 30, max_active=16, keep_results=True)
+    _, dense = run_stream(reqs, _make_input, pool_bytes=1 << 30, max_active=16, keep_results=True)
+    for r in reqs:
+        got, iters = results[r.rid]
+        assert np.array_equal(host(got), host(dense[r.rid][0])), (r.rid, r.kind, r.n)
+        assert iters == dense[r.rid][1]
+        assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
+    # model sizes: ones[1] (the relation itself) counts distinct pairs
+    b = dl.Batch(pool_bytes=1 << 26, max_active=4)
+    n = 100
+    e = np.array([[1, 2], [2, 3], [1, 2], [1, 2], [3, 1], [99, 0]], np.int32)
+    slot = b.dl_batch_submit_edges(dl.Batch.TC, n, torch.from_numpy(e).cuda(), 7)
+    empty = b.dl_batch_submit_edges(dl.Batch.TC, 5, torch.zeros((0, 2), dtype=torch.int32, device="cuda"), 8)
+    fin = {}
+    while len(fin) < 2:
+        b.dl_batch_step()
+        for tag, sl, iters in b.dl_batch_poll():
+            out = torch.empty((n if tag == 7 else 5,) * 2, dtype=torch.uint8, device="cuda")
+            ones = b.dl_batch_fetch(sl, out)
+            fin[tag] = (host(out), iters, ones)
+    a = np.zeros((n, n), np.uint8)
+    a[e[:, 0], e[:, 1]] = 1
+    ref, _, it, _ = oracle.tc_seminaive(a)
+    assert np.array_equal(fin[7][0], ref) and fin[7][2] == int(ref.sum())
+    assert fin[8][1] == 1 and fin[8][2] == 0 and not fin[8][0].any()
+    b.close()
