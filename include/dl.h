@@ -205,8 +205,10 @@ int64_t dl_padded_size(int64_t n, int kind, int prec);
 
 /* ---------------------------------------------------------------- batching
  * Many independent fixpoints over uneven n, resident in one device pool and
- * advanced together: every dl_batch_step is one grouped launch that moves
- * each unfinished request forward by one product (a closure request by one
+ * advanced together: every dl_batch_step is one round of grouped launches
+ * (64 x 64 output tiles for requests with n <= 256, 128 x 128 tiles for the
+ * others) that moves each unfinished request forward by one product (a
+ * closure request by one
  * repeated-squaring step R' = min1(A + R R), Sec. 8; a same-generation
  * request by one of the two products T = min1(P S), S' = min1(I + T P^T),
  * Sec. 7.2), followed by one read-back of the per-request model sizes.
@@ -218,8 +220,8 @@ typedef struct dl_batch dl_batch;
 
 /* pool_bytes of device memory hold the admitted requests (a request of n
  * constants takes 5 Np^2 bytes for closure, 4 Np^2 for same generation,
- * Np = n rounded up to 64); max_active (<= 4096) bounds the requests
- * admitted and not yet fetched. */
+ * Np = n rounded up to 64 for n <= 256, else to 128); max_active (<= 4096)
+ * bounds the requests admitted and not yet fetched. */
 int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** batch);
 int dl_batch_destroy(dl_batch* batch);
 

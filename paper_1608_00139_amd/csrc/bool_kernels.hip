@@ -477,8 +477,9 @@ k_nt_step(NTParams p) {
 // desc[a].tile_start is the running tile count.  A persistent grid walks the
 // list with a stride of gridDim.x, so every workgroup ends after at most
 // ceil(total / gridDim.x) tiles.
-constexpr int kGroupTile = 64;
-
+// T x T tiles, four waves of (T/2) x (T/2): 64 for small requests, 128 for
+// the others (four times the work per tile, twice the operand reuse).
+template <int T>
 __global__ void __launch_bounds__(256)
 k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -491,7 +492,7 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     }
     const GroupDesc& g = desc[lo];
     const int local = item - g.tile_start;
-    const int tiles_n = g.Np / kGroupTile;
+    const int tiles_n = g.Np / T;
     const int tm = local / tiles_n, tn = local % tiles_n;
     NTParams p{};
     p.X = g.X;
@@ -504,18 +505,23 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.out = g.out;
     p.outT = g.outT;
     __syncthreads();  // the previous tile's epilogue is done with LDS
-    nt_tile<kGroupTile, kGroupTile, 32, 32, 64, OpI8, 2, 1>(p, tm * kGroupTile, tn * kGroupTile, g.cnt, smem);
+    nt_tile<T, T, T / 2, T / 2, 64, OpI8, 2, 1>(p, tm * T, tn * T, g.cnt, smem);
   }
 }
 
-hipError_t launch_group_step(const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
+hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
   if (nreq <= 0 || total_tiles <= 0) return hipSuccess;
-  typedef NTKernel<kGroupTile, kGroupTile, 32, 32, 64, OpI8, 2, 1> K;
-  hipLaunchKernelGGL(k_group_step, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+  if (tile == 64) {
+    typedef NTKernel<64, 64, 32, 32, 64, OpI8, 2, 1> K;
+    hipLaunchKernelGGL(k_group_step<64>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+  } else if (tile == 128) {
+    typedef NTKernel<128, 128, 64, 64, 64, OpI8, 2, 1> K;
+    hipLaunchKernelGGL(k_group_step<128>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
-
-int group_tile() { return kGroupTile; }
 
 // ----------------------------------------------------------------- direct-to-LDS variant
 // Same product and epilogue as k_nt_step, but the K slices are fetched with

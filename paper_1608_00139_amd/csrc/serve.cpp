@@ -2,12 +2,14 @@
 // (repeated squaring) and same-generation requests, resident in one device
 // pool, advanced together by one grouped launch per round.
 //
-// A request is admitted with dl_batch_submit (its relation is normalised into
-// pool buffers, padded to a multiple of 64).  Each dl_batch_step is one round:
-// every unfinished request advances by one product -- a closure request by one
-// squaring step R' = [A + R R], a same-generation request by one of the two
-// products of its step (T = [P S], then S' = [I + T P^T]) -- all in a single
-// persistent launch over the concatenated 64 x 64 tile lists.  The round ends
+// A request is admitted with dl_batch_submit or dl_batch_submit_edges (its
+// relation is normalised into pool buffers, padded to a multiple of 64 for
+// n <= 256, else of 128).  Each dl_batch_step is one round: every unfinished
+// request advances by one product -- a closure request by one squaring step
+// R' = [A + R R], a same-generation request by one of the two products of its
+// step (T = [P S], then S' = [I + T P^T]) -- in two persistent launches, one
+// over the concatenated 64 x 64 tile lists of the small requests and one over
+// the 128 x 128 tile lists of the others.  The round ends
 // with one read-back of the per-request model sizes; a request whose model
 // size repeats is finished (its iteration count follows the same convention
 // as dl_tc/dl_sg) and can be fetched, which frees its slot and pool memory.
@@ -56,7 +58,7 @@ struct Req {
   int phase = 0;            // same generation: 0 = next launch is T = [P S], 1 = S' = [I + T P^T]
   std::vector<int64_t> ones;  // model sizes known on the host, ones[k] for k <= known
   int64_t iters = 0;
-  int cnt_index = -1;       // index into the round counter array of the last counted product
+  int tile = 64;            // output tile of its products (Np is a multiple of it)
   bool admit_count = false; // ones[1] pending from the ingest counter
 };
 
@@ -69,9 +71,9 @@ struct dl_batch {
   size_t pool_bytes = 0;
   std::map<size_t, size_t> free_list;  // offset -> size
   std::vector<Req> req;
-  GroupDesc* d_desc = nullptr;  // device descriptors
-  GroupDesc* h_desc = nullptr;  // pinned host descriptors
-  unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max]
+  GroupDesc* d_desc = nullptr;  // device descriptors: 64-tile list [max], 128-tile list [max]
+  GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
+  unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max], by slot
   unsigned long long* h_cnt = nullptr;
   int max_active = 0;
   int grid = 1024;
@@ -110,7 +112,10 @@ void pool_free(dl_batch* b, size_t off, size_t bytes) {
   }
 }
 
-int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+// Requests up to n = 256 use 64 x 64 tiles; larger ones 128 x 128 tiles.
+constexpr int64_t kSmallMax = 256;
+int tile_for(int64_t n) { return n <= kSmallMax ? 64 : 128; }
+int64_t pad_to(int64_t n, int t) { return (n + t - 1) / t * t; }
 
 size_t request_bytes(int kind, int64_t Np) {
   const size_t m = (size_t)Np * Np;
@@ -154,9 +159,9 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   }
   b->pool_bytes = pool_bytes;
   b->free_list[0] = pool_bytes;
-  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
   if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
@@ -203,7 +208,8 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
       break;
     }
   if (slot < 0) return bfail(DL_EAGAIN, "no free request slot");
-  const int64_t Np = pad64(n);
+  const int tile = tile_for(n);
+  const int64_t Np = pad_to(n, tile);
   const size_t bytes = request_bytes(kind, Np);
   size_t off = 0;
   if (!pool_alloc(b, bytes, &off)) return bfail(DL_EAGAIN, "pool memory exhausted");
@@ -214,6 +220,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   r.kind = kind;
   r.n = n;
   r.Np = Np;
+  r.tile = tile;
   r.tag = tag;
   r.off = off;
   r.bytes = bytes;
@@ -287,20 +294,20 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
   if (!b) return bfail(DL_EINVAL, "NULL batch");
   hipStream_t s = (hipStream_t)stream;
   BHIP(hipSetDevice(b->device));
-  // build this round's work list
-  int na = 0, tiles = 0;
-  const int T = group_tile();
+  // build this round's two work lists (64 x 64 and 128 x 128 tiles); the
+  // counters of a request's product are at d_cnt[slot]
+  int na[2] = {0, 0}, tiles[2] = {0, 0};
   std::vector<int> slots;
   for (int i = 0; i < b->max_active; ++i) {
     Req& r = b->req[i];
     if (!r.used || r.done) continue;
-    GroupDesc& g = b->h_desc[na];
+    const int li = r.tile == 64 ? 0 : 1;
+    GroupDesc& g = b->h_desc[li * b->max_active + na[li]];
     std::memset(&g, 0, sizeof g);
     g.Np = (int)r.Np;
     g.n_valid = (int)r.n;
-    g.tile_start = tiles;
+    g.tile_start = tiles[li];
     g.cnt = nullptr;
-    r.cnt_index = -1;
     if (r.kind == 0) {
       const int64_t t = r.computed + 1;  // iterate produced by this round
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
@@ -309,8 +316,7 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
       g.add = (const int8_t*)r.add;
       g.out = r.b[2 * cur];
       g.outT = r.b[2 * cur + 1];
-      g.cnt = b->d_cnt + na;
-      r.cnt_index = na;
+      g.cnt = b->d_cnt + i;
     } else if (r.phase == 0) {
       const int64_t t = r.computed + 1;
       const int prev = (int)((t - 1) & 1);
@@ -324,44 +330,49 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
       g.Y = r.b[0];
       g.add_identity = 1;
       g.out = r.b[1 + cur];
-      g.cnt = b->d_cnt + na;
-      r.cnt_index = na;
+      g.cnt = b->d_cnt + i;
     }
-    tiles += (int)((r.Np / T) * (r.Np / T));
+    tiles[li] += (int)((r.Np / r.tile) * (r.Np / r.tile));
     slots.push_back(i);
-    ++na;
+    ++na[li];
   }
-  if (na > 0) {
-    BHIP(launch_ring_clear(b->d_cnt, nullptr, 0, na, 0, s));
-    BHIP(hipMemcpyAsync(b->d_desc, b->h_desc, sizeof(GroupDesc) * na, hipMemcpyHostToDevice, s));
-    BHIP(launch_group_step(b->d_desc, na, tiles, std::min(b->grid, tiles), s));
+  const int nact = na[0] + na[1];
+  if (nact > 0) {
+    BHIP(hipMemsetAsync(b->d_cnt, 0, sizeof(unsigned long long) * b->max_active, s));
+    for (int li = 0; li < 2; ++li) {
+      if (!na[li]) continue;
+      GroupDesc* hd = b->h_desc + li * b->max_active;
+      GroupDesc* dd = b->d_desc + li * b->max_active;
+      BHIP(hipMemcpyAsync(dd, hd, sizeof(GroupDesc) * na[li], hipMemcpyHostToDevice, s));
+      BHIP(launch_group_step(li == 0 ? 64 : 128, dd, na[li], tiles[li], std::min(b->grid, tiles[li]), s));
+    }
   }
   BHIP(hipMemcpyAsync(b->h_cnt, b->d_cnt, sizeof(unsigned long long) * 2 * b->max_active, hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
   int finished = 0;
-  for (int a = 0; a < na; ++a) {
-    Req& r = b->req[slots[a]];
+  for (int sl : slots) {
+    Req& r = b->req[sl];
     if (r.admit_count) {
-      r.ones.push_back((int64_t)b->h_cnt[b->max_active + slots[a]]);  // ones[1] = |A|
+      r.ones.push_back((int64_t)b->h_cnt[b->max_active + sl]);  // ones[1] = |A|
       r.admit_count = false;
     }
     if (r.kind == 0) {
       r.computed += 1;
-      r.ones.push_back((int64_t)b->h_cnt[r.cnt_index]);
+      r.ones.push_back((int64_t)b->h_cnt[sl]);
     } else if (r.phase == 0) {
       r.phase = 1;
     } else {
       r.computed += 1;
       r.phase = 0;
-      r.ones.push_back((int64_t)b->h_cnt[r.cnt_index]);
+      r.ones.push_back((int64_t)b->h_cnt[sl]);
     }
     settle(r);
     if (r.done) {
-      b->finished.push_back(slots[a]);
+      b->finished.push_back(sl);
       ++finished;
     }
   }
-  if (active_out) *active_out = na - finished;
+  if (active_out) *active_out = nact - finished;
   if (finished_out) *finished_out = finished;
   return DL_OK;
 }
