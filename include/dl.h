@@ -206,8 +206,8 @@ int64_t dl_padded_size(int64_t n, int kind, int prec);
 /* ---------------------------------------------------------------- batching
  * Many independent fixpoints over uneven n, resident in one device pool and
  * advanced together: every dl_batch_step is one round of grouped launches
- * (64 x 64 output tiles for requests with n <= 256, 128 x 128 tiles for the
- * others) that moves each unfinished request forward by one product (a
+ * (64 x 64 output tiles for requests with n <= 256, 128 x 128 up to 1024,
+ * 256 x 256 above) that moves each unfinished request forward by one product (a
  * closure request by one
  * repeated-squaring step R' = min1(A + R R), Sec. 8; a same-generation
  * request by one of the two products T = min1(P S), S' = min1(I + T P^T),
@@ -220,7 +220,7 @@ typedef struct dl_batch dl_batch;
 
 /* pool_bytes of device memory hold the admitted requests (a request of n
  * constants takes 5 Np^2 bytes for closure, 4 Np^2 for same generation,
- * Np = n rounded up to 64 for n <= 256, else to 128); max_active (<= 4096)
+ * Np = n rounded up to 64 for n <= 256, to 128 up to 1024, else to 256); max_active (<= 4096)
  * bounds the requests admitted and not yet fetched. */
 int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** batch);
 int dl_batch_destroy(dl_batch* batch);

@@ -509,6 +509,9 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   }
 }
 
+__global__ void k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles);
+size_t group_dma_lds();
+
 hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
   if (nreq <= 0 || total_tiles <= 0) return hipSuccess;
   if (tile == 64) {
@@ -517,6 +520,8 @@ hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int tota
   } else if (tile == 128) {
     typedef NTKernel<128, 128, 64, 64, 64, OpI8, 2, 1> K;
     hipLaunchKernelGGL(k_group_step<128>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+  } else if (tile == 256) {
+    hipLaunchKernelGGL(k_group_dma, dim3(grid), dim3(1024), group_dma_lds(), s, desc, nreq, total_tiles);
   } else {
     return hipErrorInvalidValue;
   }
@@ -698,20 +703,15 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   return cnt;
 }
 
+// One BM x BN output tile (tm, tn) of the direct-to-LDS product; the whole
+// workgroup calls it.  smem holds the LDS ring (and the epilogue tile).
 template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
-__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
-__attribute__((amdgpu_waves_per_eu(1, ((BM / WM) * (BN / WN) + 3) / 4 > 2 ? ((BM / WM) * (BN / WN) + 3) / 4 : 2)))
-k_nt_dma(NTParams p) {
+__device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, uint8_t* smem) {
   typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  if (step_is_done(p)) return;
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
   const int row0 = tm * BM, col0 = tn * BN;
   const int64_t ldb = p.ld * K::NIB / 2;
   const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
@@ -872,6 +872,51 @@ k_nt_dma(NTParams p) {
   }
 }
 
+template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
+__global__ void __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__attribute__((amdgpu_waves_per_eu(1, ((BM / WM) * (BN / WN) + 3) / 4 > 2 ? ((BM / WM) * (BN / WN) + 3) / 4 : 2)))
+k_nt_dma(NTParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
+  nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem);
+}
+
+// Grouped serving step with the direct-to-LDS 256 x 256 tiles (requests with
+// Np a multiple of 256): one workgroup per CU walks the concatenated tile
+// lists as k_group_step does.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  for (int item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+    int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].tile_start <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const GroupDesc& g = desc[lo];
+    const int local = item - g.tile_start;
+    const int tiles_n = g.Np / 256;
+    NTParams p{};
+    p.X = g.X;
+    p.Y = g.Y;
+    p.ld = g.Np;
+    p.Np = g.Np;
+    p.add = g.add;
+    p.add_identity = g.add_identity;
+    p.n_valid = g.n_valid;
+    p.out = g.out;
+    p.outT = g.outT;
+    p.ones = g.cnt;
+    p.count = g.cnt != nullptr;
+    p.step = 0;
+    __syncthreads();  // the previous tile's epilogue is done with LDS
+    nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, local / tiles_n, local % tiles_n, smem);
+  }
+}
+
 template <class Op, int BM, int BN, int WM, int WN, int KB, int NSTAGE>
 static hipError_t launch_dma(const NTParams& p, hipStream_t s) {
   typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
@@ -948,8 +993,13 @@ static TileCfg cfg_of(int cfg) {
   }
 }
 
+size_t group_dma_lds() { return DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES; }
+
 hipError_t bool_kernels_init() {
   hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_group_dma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)group_dma_lds())) != hipSuccess)
+    return e;
   if ((e = init_op<OpI8>()) != hipSuccess) return e;
   if ((e = init_op<OpF32>()) != hipSuccess) return e;
   if ((e = init_op<OpBF16>()) != hipSuccess) return e;

@@ -104,7 +104,7 @@ hipError_t bool_kernels_init();
 // 1 fp32, 2 bf16, 3 fp8, 4 fp4, 5 fp64 on the current device; `sink` must hold
 // 256 ints (never written).
 hipError_t measure_peak(int kind, int* sink, double* ops_per_s, hipStream_t s);
-// tile: 64 or 128 (every request of the list has Np a multiple of it)
+// tile: 64, 128 or 256 (every request of the list has Np a multiple of it)
 hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
 
 }  // namespace dl

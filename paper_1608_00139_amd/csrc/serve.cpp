@@ -4,12 +4,13 @@
 //
 // A request is admitted with dl_batch_submit or dl_batch_submit_edges (its
 // relation is normalised into pool buffers, padded to a multiple of 64 for
-// n <= 256, else of 128).  Each dl_batch_step is one round: every unfinished
-// request advances by one product -- a closure request by one squaring step
-// R' = [A + R R], a same-generation request by one of the two products of its
-// step (T = [P S], then S' = [I + T P^T]) -- in two persistent launches, one
-// over the concatenated 64 x 64 tile lists of the small requests and one over
-// the 128 x 128 tile lists of the others.  The round ends
+// n <= 256, of 128 up to 1024, else of 256).  Each dl_batch_step is one round:
+// every unfinished request advances by one product -- a closure request by one
+// squaring step R' = [A + R R], a same-generation request by one of the two
+// products of its step (T = [P S], then S' = [I + T P^T]) -- in up to three
+// persistent launches over the concatenated tile lists of the requests of
+// each tile size (64 x 64, 128 x 128, and the 256 x 256 direct-to-LDS tiles).
+// The round ends
 // with one read-back of the per-request model sizes; a request whose model
 // size repeats is finished (its iteration count follows the same convention
 // as dl_tc/dl_sg) and can be fetched, which frees its slot and pool memory.
@@ -71,12 +72,13 @@ struct dl_batch {
   size_t pool_bytes = 0;
   std::map<size_t, size_t> free_list;  // offset -> size
   std::vector<Req> req;
-  GroupDesc* d_desc = nullptr;  // device descriptors: 64-tile list [max], 128-tile list [max]
+  GroupDesc* d_desc = nullptr;  // device descriptors: 64-, 128- and 256-tile lists [max] each
   GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
   unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max], by slot
   unsigned long long* h_cnt = nullptr;
   int max_active = 0;
-  int grid = 1024;
+  int grid = 1024;  // persistent workgroups of the 64 and 128 tile launches
+  int cus = 256;
   std::vector<int> finished;  // slots finished and not yet polled
 };
 
@@ -112,9 +114,11 @@ void pool_free(dl_batch* b, size_t off, size_t bytes) {
   }
 }
 
-// Requests up to n = 256 use 64 x 64 tiles; larger ones 128 x 128 tiles.
-constexpr int64_t kSmallMax = 256;
-int tile_for(int64_t n) { return n <= kSmallMax ? 64 : 128; }
+// Output tiles by request size: 64 x 64 up to n = 256, 128 x 128 up to
+// n = 1024, 256 x 256 (the direct-to-LDS kernel) above.
+int tile_for(int64_t n) { return n <= 256 ? 64 : (n <= 1024 ? 128 : 256); }
+int list_of(int tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : 2); }
+constexpr int kLists = 3;
 int64_t pad_to(int64_t n, int t) { return (n + t - 1) / t * t; }
 
 size_t request_bytes(int kind, int64_t Np) {
@@ -159,9 +163,9 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   }
   b->pool_bytes = pool_bytes;
   b->free_list[0] = pool_bytes;
-  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * kLists * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * kLists * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
   if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
@@ -173,6 +177,7 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
   b->grid = cus * 4;
+  b->cus = cus;
   *out = b;
   return DL_OK;
 }
@@ -294,14 +299,14 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
   if (!b) return bfail(DL_EINVAL, "NULL batch");
   hipStream_t s = (hipStream_t)stream;
   BHIP(hipSetDevice(b->device));
-  // build this round's two work lists (64 x 64 and 128 x 128 tiles); the
-  // counters of a request's product are at d_cnt[slot]
-  int na[2] = {0, 0}, tiles[2] = {0, 0};
+  // build this round's work lists (64, 128 and 256 tiles); the counters of a
+  // request's product are at d_cnt[slot]
+  int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};
   std::vector<int> slots;
   for (int i = 0; i < b->max_active; ++i) {
     Req& r = b->req[i];
     if (!r.used || r.done) continue;
-    const int li = r.tile == 64 ? 0 : 1;
+    const int li = list_of(r.tile);
     GroupDesc& g = b->h_desc[li * b->max_active + na[li]];
     std::memset(&g, 0, sizeof g);
     g.Np = (int)r.Np;
@@ -336,15 +341,16 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
     slots.push_back(i);
     ++na[li];
   }
-  const int nact = na[0] + na[1];
+  const int nact = na[0] + na[1] + na[2];
   if (nact > 0) {
     BHIP(hipMemsetAsync(b->d_cnt, 0, sizeof(unsigned long long) * b->max_active, s));
-    for (int li = 0; li < 2; ++li) {
+    for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
       if (!na[li]) continue;
       GroupDesc* hd = b->h_desc + li * b->max_active;
       GroupDesc* dd = b->d_desc + li * b->max_active;
       BHIP(hipMemcpyAsync(dd, hd, sizeof(GroupDesc) * na[li], hipMemcpyHostToDevice, s));
-      BHIP(launch_group_step(li == 0 ? 64 : 128, dd, na[li], tiles[li], std::min(b->grid, tiles[li]), s));
+      const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
+      BHIP(launch_group_step(64 << li, dd, na[li], tiles[li], std::min(grid, tiles[li]), s));
     }
   }
   BHIP(hipMemcpyAsync(b->h_cnt, b->d_cnt, sizeof(unsigned long long) * 2 * b->max_active, hipMemcpyDeviceToHost, s));

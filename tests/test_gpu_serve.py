@@ -152,3 +152,25 @@ def test_edge_list_admission(dl):
     assert np.array_equal(fin[7][0], ref) and fin[7][2] == int(ref.sum())
     assert fin[8][1] == 1 and fin[8][2] == 0 and not fin[8][0].any()
     b.close()
+
+
+def test_large_requests_all_tile_sizes(dl):
+    """A mix spanning the three tile sizes (n up to 1600: 64, 128 and 256 x 256
+    grouped tiles in one round), dense and edge-list admission, against the oracle."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    reqs = dlgen.serving_stream(14, seed=21, rate=0.0, n_lo=100, n_hi=1600)
+    assert any(r.n > 1024 for r in reqs) and any(r.n <= 256 for r in reqs)
+
+    def edges_of(r):
+        return torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda()
+
+    announce("serve large", [r.n for r in reqs])
+    for mk in (edges_of, _make_input):
+        stats, results = run_stream(reqs, mk, pool_bytes=1 << 31, max_active=8, keep_results=True)
+        for r in reqs:
+            got, iters = results[r.rid]
+            assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
+            assert iters == _alone(dl, r)[1], (r.rid, r.kind, r.n)
