@@ -60,6 +60,9 @@ def main() -> int:
                     help="run three plain 1 GiB device copies (traffic-counter calibration) and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
                     help="per-launch HBM traffic of the step kernel from rocprofv3 --pmc CSVs and exit")
+    ap.add_argument("--mfma-summary", metavar="CSV",
+                    help="matrix-core busy fraction and clock of the step kernel and of the register-only "
+                         "int8 MFMA loop from a rocprofv3 --pmc CSV and exit")
     ap.add_argument("--programs-only", action="store_true",
                     help="run only the layered program workloads (both methods) and print their JSON")
     args = ap.parse_args()
@@ -75,6 +78,8 @@ def main() -> int:
         return trace_summary(args.trace_summary)
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
+    if args.mfma_summary:
+        return mfma_summary(args.mfma_summary)
     if args.copy_calibration:
         return copy_calibration()
     if args.eps_only:
@@ -591,6 +596,59 @@ def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
     print(f"traffic_bytes_per_launch: {fetch + write:.0f}")
     print(f"algorithmic_bytes_per_launch: {algo}  (X, Y, addend read; out, out^T written; int8)")
     print(f"traffic_over_algorithmic: {(fetch + write) / algo:.3f}")
+    return 0
+
+
+def mfma_summary(csv_path: str) -> int:
+    """Matrix-core activity per launch from SQ_INSTS_VALU_MFMA_MOPS_I8,
+    SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE.
+
+    MOPS_I8 counts int8 MFMA operations in units of 512, so a full step
+    launch must read 2 Np^3 / 512.  GRBM_GUI_ACTIVE is summed over the XCDs
+    and the busy cycles over every SIMD: busy fraction = busy / (GUI_ACTIVE /
+    XCDs * SIMDs), clock = GUI_ACTIVE / XCDs / duration.  Step launches that
+    returned early are excluded by a cut at 10% of the largest MOPS value.
+    The device's XCD and SIMD counts come from k_agent_info.csv beside the
+    counter file (8 and 1024 if it is absent).
+    """
+    import csv
+    import os
+
+    xcds, simds = 8, 1024
+    info = os.path.join(os.path.dirname(csv_path), "k_agent_info.csv")
+    if os.path.exists(info):
+        for r in csv.DictReader(open(info)):
+            if r.get("Agent_Type") == "GPU":
+                xcds, simds = int(r["Num_Xcc"]), int(r["Simd_Count"])
+    disp = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = disp.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
+                                               "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    groups = {"step": lambda k: "k_nt_dma" in k and "OpI8" in k,
+              "peak": lambda k: "k_mfma_peak<0>" in k}
+    print("# int8 matrix-core activity (rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_I8 SQ_VALU_MFMA_BUSY_CYCLES "
+          "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE)")
+    print(f"# device: {xcds} XCDs, {simds} SIMDs")
+    for label, pred in groups.items():
+        ds = [d for d in disp.values() if pred(d["name"])]
+        if not ds:
+            continue
+        top = max(d["SQ_INSTS_VALU_MFMA_MOPS_I8"] for d in ds)
+        ds = [d for d in ds if d["SQ_INSTS_VALU_MFMA_MOPS_I8"] >= 0.1 * top]
+        k = len(ds)
+        ops = sum(d["SQ_INSTS_VALU_MFMA_MOPS_I8"] for d in ds) / k * 512
+        us = sum(d["ns"] for d in ds) / k / 1e3
+        ghz = sum(d["GRBM_GUI_ACTIVE"] / xcds / d["ns"] for d in ds) / k
+        busy = sum(d["SQ_VALU_MFMA_BUSY_CYCLES"] / (d["GRBM_GUI_ACTIVE"] / xcds * simds) for d in ds) / k
+        name = ds[0]["name"].split("(")[0].replace("void ", "")
+        print(f"{label}: {name}")
+        print(f"  launches: {k}")
+        print(f"  int8_ops_per_launch: {ops:.4e}" + (f"  (2 Np^3 = {2.0 * N ** 3:.4e})" if label == "step" else ""))
+        print(f"  duration_us: {us:.1f}")
+        print(f"  clock_ghz: {ghz:.3f}")
+        print(f"  mfma_busy_fraction: {busy:.3f}")
+        print(f"  int8_tops: {ops / (us * 1e-6) / 1e12:.0f}")
     return 0
 
 
