@@ -63,6 +63,9 @@ def main() -> int:
     ap.add_argument("--mfma-summary", metavar="CSV",
                     help="matrix-core busy fraction and clock of the step kernel and of the register-only "
                          "int8 MFMA loop from a rocprofv3 --pmc CSV and exit")
+    ap.add_argument("--counter-summary", metavar="CSV",
+                    help="per-launch averages of every counter in a rocprofv3 --pmc CSV for the step kernel, "
+                         "per CU cycle, and exit")
     ap.add_argument("--programs-only", action="store_true",
                     help="run only the layered program workloads (both methods) and print their JSON")
     args = ap.parse_args()
@@ -80,6 +83,8 @@ def main() -> int:
         return pmc_summary(*args.pmc_summary)
     if args.mfma_summary:
         return mfma_summary(args.mfma_summary)
+    if args.counter_summary:
+        return counter_summary(args.counter_summary)
     if args.copy_calibration:
         return copy_calibration()
     if args.eps_only:
@@ -109,11 +114,12 @@ def main() -> int:
     outs = [torch.empty((N, N), dtype=torch.uint8, device="cuda") for _ in graphs]
     torch.cuda.synchronize()
 
+    devs = [g["dev"] for g in graphs]
+
     def step():
-        its = []
-        for g, out in zip(graphs, outs):
-            _, it = dl.dl_tc(g["dev"], method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=out, ctx=ctx)
-            its.append(it)
+        # one batched call: two fixpoints in flight, so one's counter
+        # read-back overlaps the other's products
+        _, its = dl.dl_tc_batch(devs, method=dl.DL_TC_SQUARE, prec=dl.DL_I8, outs=outs, ctx=ctx)
         return its
 
     log(f"warmup {args.warmup}")
@@ -184,7 +190,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "i8",
         "data": "synthetic (seeded ER graphs, dense 0/1 int8 in HBM)",
-        "config": {"workload": "TC to fixpoint, int8 repeated squaring, N=8192 ER p in {1/N,4/N,0.01} x seeds {0,1,2}",
+        "config": {"workload": "TC to fixpoint, int8 repeated squaring, N=8192 ER p in {1/N,4/N,0.01} x seeds {0,1,2}, nine fixpoints per step in one batched call",
                    "n": N, "graphs": len(graphs), "iters": iters, "products_per_step": sum(products)},
         "frac_of_int8_peak": round(value / INT8_PEAK_TOPS, 4),
         "roofline": {"bound": "mfma", "kernel": "k_nt_dma<256,256,64,64,128,OpI8,2>",
@@ -649,6 +655,41 @@ def mfma_summary(csv_path: str) -> int:
         print(f"  clock_ghz: {ghz:.3f}")
         print(f"  mfma_busy_fraction: {busy:.3f}")
         print(f"  int8_tops: {ops / (us * 1e-6) / 1e12:.0f}")
+    return 0
+
+
+def counter_summary(csv_path: str) -> int:
+    """Averages over the step kernel's full launches (duration above 10% of
+    the longest) of each counter in a rocprofv3 --pmc CSV, also divided by
+    the kernel's CU cycles (GRBM_GUI_ACTIVE / XCDs x CUs; the CSV must hold
+    GRBM_GUI_ACTIVE).  SQ_WAVE_CYCLES counts in units of four cycles on this
+    device (sixteen resident waves read four per CU cycle)."""
+    import csv
+    import os
+
+    xcds, cus = 8, 256
+    info = os.path.join(os.path.dirname(csv_path), "k_agent_info.csv")
+    if os.path.exists(info):
+        for r in csv.DictReader(open(info)):
+            if r.get("Agent_Type") == "GPU":
+                xcds, cus = int(r["Num_Xcc"]), int(r["Cu_Count"])
+    disp = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = disp.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
+                                               "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    ds = [d for d in disp.values() if "k_nt_dma" in d["name"] and "OpI8" in d["name"]]
+    top = max(d["ns"] for d in ds)
+    ds = [d for d in ds if d["ns"] >= 0.1 * top]
+    keys = sorted(k for k in ds[0] if k not in ("name", "ns"))
+    avg = {k: sum(d[k] for d in ds) / len(ds) for k in keys}
+    cyc = avg["GRBM_GUI_ACTIVE"] / xcds
+    ns = sum(d["ns"] for d in ds) / len(ds)
+    print(f"kernel: {ds[0]['name'].split('(')[0].replace('void ', '')}")
+    print(f"launches: {len(ds)}  duration_us: {ns / 1e3:.1f}  cycles: {cyc:.0f}  clock_ghz: {cyc / ns:.3f}")
+    print(f"# {'counter':<34} {'per_launch':>16} {'per_CU_cycle':>13}")
+    for k in keys:
+        print(f"  {k:<34} {avg[k]:16.0f} {avg[k] / (cyc * cus):13.4f}")
     return 0
 
 

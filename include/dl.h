@@ -107,6 +107,18 @@ int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* 
                 int method, int prec, int32_t max_steps, int64_t* ones, int32_t* steps,
                 int32_t* converged, void* stream);
 
+/* Transitive closure of `count` relations of one size (Sec. 3, as dl_tc):
+ * A[g] and R[g] (g < count) are device uint8 matrices [n x lda] and
+ * [n x ldr], passed as host arrays of `count` device pointers; iters[g]
+ * (host int32) receives each fixpoint's iteration count.  The fixpoints run
+ * two at a time on `stream`, so the host's counter read-back of one overlaps
+ * the products of the other; the device workspace is twice that of dl_tc
+ * (one at a time if the budget allows only one).  Results are identical to
+ * `count` dl_tc calls.  No R[g] may overlap any A[h] or another R[h]
+ * (DL_EINVAL); count = 0 does nothing. */
+int dl_tc_batch(dl_ctx* ctx, int32_t count, int64_t n, const uint8_t* const* A, int64_t lda,
+                uint8_t* const* R, int64_t ldr, int method, int prec, int32_t* iters, void* stream);
+
 /* Same generation (Sec. 7.2): least S with S = min1(I + P S P^T), where P is
  * the r1 relation (device uint8 [n x ldp]) and I encodes diag(x, x) for
  * every constant.  Each step runs two products, T = min1(P S) and

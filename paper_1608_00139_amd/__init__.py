@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
-    "dl_tc", "dl_tc_steps", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
+    "dl_tc", "dl_tc_steps", "dl_tc_batch", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
     "dl_padded_size", "Batch", "DL_EAGAIN", "dl_solve_linear", "dl_solve_two_sided", "Program",
     "DL_EVAL_ITERATION", "DL_EVAL_MATRIX", "dl_measure_peak",
 ]
@@ -66,6 +66,8 @@ def load() -> ctypes.CDLL:
         "dl_tc": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, pi32, vp], ctypes.c_int),
         "dl_tc_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, i32, pi64, pi32, pi32, vp],
                         ctypes.c_int),
+        "dl_tc_batch": ([vp, i32, i64, ctypes.POINTER(vp), i64, ctypes.POINTER(vp), i64, ctypes.c_int, ctypes.c_int,
+                         pi32, vp], ctypes.c_int),
         "dl_sg": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, pi32, vp], ctypes.c_int),
         "dl_sg_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, pi64, pi32, pi32, vp], ctypes.c_int),
         "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
@@ -194,6 +196,34 @@ def dl_tc(A: torch.Tensor, method: int = DL_TC_SQUARE, prec=DL_I8, out: torch.Te
     _check(load().dl_tc(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()), ldr,
                         int(method), _prec(prec), ctypes.byref(it), _stream_ptr(stream)))
     return R, int(it.value)
+
+
+def dl_tc_batch(As: list, method: int = DL_TC_SQUARE, prec=DL_I8, outs: list | None = None,
+                ctx: Context | None = None, stream=None) -> tuple[list, list]:
+    """Transitive closures of several relations of one size (uint8 n x n on
+    the device, one common row stride), two fixpoints in flight:
+    (list of R, list of iters)."""
+    if not As:
+        return [], []
+    dims = [_mat(a, "A") for a in As]
+    n, lda = dims[0]
+    if any(d != (n, lda) for d in dims):
+        raise ValueError("every relation must have the same size and row stride")
+    Rs = outs if outs is not None else [torch.empty((n, n), dtype=torch.uint8, device=a.device) for a in As]
+    if len(Rs) != len(As):
+        raise ValueError("one output per input")
+    rdims = [_mat(r, "R") for r in Rs]
+    ldr = rdims[0][1]
+    if any(d != (n, ldr) for d in rdims):
+        raise ValueError("every output must be n x n with one common row stride")
+    k = len(As)
+    a_arr = (ctypes.c_void_p * k)(*[a.data_ptr() for a in As])
+    r_arr = (ctypes.c_void_p * k)(*[r.data_ptr() for r in Rs])
+    its = (ctypes.c_int32 * k)()
+    c = _ctx(ctx)
+    _check(load().dl_tc_batch(c.handle, k, n, a_arr, lda, r_arr, ldr, int(method), _prec(prec), its,
+                              _stream_ptr(stream)))
+    return Rs, [int(its[g]) for g in range(k)]
 
 
 @dataclass

@@ -93,22 +93,23 @@ int set_device(dl_ctx* c) {
   return DL_OK;
 }
 
-// Timed launch bracket (events only when timing is on).
+// Timed launch bracket (events only when timing is on).  Several brackets
+// may share the context's event pool through one `used` counter.
 struct Timer {
   dl_ctx* c;
   hipStream_t s;
+  size_t* used;
   std::vector<std::pair<int, int>> marks;  // (class, event index)
-  size_t used = 0;
   int begin(int cls) {
     if (!c->timing) return -1;
-    if (used >= c->events.size()) {
+    if (*used >= c->events.size()) {
       EventPair ep;
       if (hipEventCreate(&ep.a) != hipSuccess || hipEventCreate(&ep.b) != hipSuccess) return -1;
       c->events.push_back(ep);
     }
-    (void)hipEventRecord(c->events[used].a, s);
-    marks.push_back({cls, (int)used});
-    return (int)used++;
+    (void)hipEventRecord(c->events[*used].a, s);
+    marks.push_back({cls, (int)*used});
+    return (int)(*used)++;
   }
   void end(int idx) {
     if (idx >= 0) (void)hipEventRecord(c->events[idx].b, s);
@@ -132,166 +133,298 @@ struct Timer {
 
 enum Mode { M_PLAIN = 0, M_SQUARE = 1, M_SG = 2 };
 
-// Runs a fixpoint: ingest, step chunks with device-side early exit, emit.
-int run_fixpoint(dl_ctx* c, int mode, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R,
-                 int64_t ldr, int prec, int32_t max_steps, int64_t* ones_out, int32_t* steps_out,
-                 int32_t* converged_out, hipStream_t s) {
+// Workspace of one fixpoint: [add int8][op0][op1][op2][op3].
+size_t fix_ws_bytes(int prec, int64_t Np) { return (size_t)Np * Np + 4 * (size_t)mat_bytes(prec, Np) + 256; }
+
+// Device and pinned host state of one fixpoint in flight.
+struct FixSlot {
+  uint8_t* ws = nullptr;
+  unsigned long long* ring = nullptr;    // device ring of model sizes
+  int* conv = nullptr;                   // device convergence step
+  unsigned long long* h_ring = nullptr;  // pinned copies read after `ev`
+  int* h_conv = nullptr;
+  hipEvent_t ev = nullptr;
+};
+
+// One fixpoint: ingest, chunks of step launches with device-side early exit,
+// emit.  After each chunk the ring and the convergence step are copied to
+// pinned memory and the slot's event is recorded; advance() reads them once
+// that event has completed and enqueues the next chunk or the emit.  Nothing
+// here waits on the device, so a driver can keep several fixpoints in flight
+// on one stream and read one back while the device runs another's products.
+class Fix {
+ public:
+  Fix(dl_ctx* c, const FixSlot& sl, size_t* ev_used, int mode, int64_t n, const uint8_t* A, int64_t lda,
+      uint8_t* R, int64_t ldr, int prec, int32_t max_steps, hipStream_t s)
+      : c_(c), sl_(sl), mode_(mode), n_(n), A_(A), lda_(lda), R_(R), ldr_(ldr), prec_(prec),
+        max_steps_(max_steps), s_(s), tm_{c, s, ev_used, {}} {}
+
+  bool done() const { return done_; }
+  const FixSlot& slot() const { return sl_; }
+
+  // Ingest and the first chunk, or straight to the emit when max_steps <= 1
+  // needs no product.
+  int start() {
+    Np_ = padded_size_for(prec_, n_);
+    cfg_ = choose_nt_config(prec_, Np_);
+    const size_t mat8 = (size_t)Np_ * Np_;
+    const size_t matT = (size_t)mat_bytes(prec_, Np_);
+    int8_t* ADD = (int8_t*)sl_.ws;
+    uint8_t* op[4];
+    for (int i = 0; i < 4; ++i) op[i] = sl_.ws + mat8 + i * matT;
+    DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
+    if (mode_ == M_PLAIN) {
+      // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
+      Yop_ = op[0];
+      S_[0] = op[1];
+      S_[1] = op[2];
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, ADD, Yop_, S_[1], sl_.ring + 1, s_));
+    } else if (mode_ == M_SQUARE) {
+      // R^(1) = A with its transpose; addend A
+      S_[0] = op[0];
+      ST_[0] = op[1];
+      S_[1] = op[2];
+      ST_[1] = op[3];
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, ADD, nullptr, S_[1], ST_[1], sl_.ring + 1, s_));
+    } else {
+      // P in operand precision; S^(1) = I; intermediate T
+      Yop_ = op[0];
+      S_[0] = op[1];
+      S_[1] = op[2];
+      Tmp_ = op[3];
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, nullptr, nullptr, s_));
+      DL_HIP(launch_identity(prec_, S_[1], (int)Np_, (int)n_, s_));
+      DL_HIP(launch_ring_set(sl_.ring, 1, (unsigned long long)n_, s_));
+    }
+    add_ = ADD;
+    const TileCfg tc = nt_config(prec_, cfg_);
+    p_.ld = Np_;
+    p_.Np = (int)Np_;
+    p_.n_valid = (int)n_;
+    p_.ones = sl_.ring;
+    p_.conv = sl_.conv;
+    p_.tiles_m = (int)(Np_ / tc.bm);
+    p_.tiles_n = (int)(Np_ / tc.bn);
+    computed_ = max_steps_ >= 1 ? 1 : 0;
+    if (max_steps_ == 1) return readback(1);  // step 1 came from ingest; one read-back settles it
+    if (max_steps_ >= 2) return chunk();
+    return emit();
+  }
+
+  // The slot's event has completed: take the counts of the last chunk.
+  int advance() {
+    const int cv = sl_.h_conv[0];
+    const int64_t upto = pending_;
+    int64_t last = upto;
+    if (cv != kNotConverged) last = std::min<int64_t>(last, cv);
+    const int64_t first = (int64_t)ones_.size() - 1;  // slot 1 may be unread yet
+    if ((int64_t)ones_.size() < last + 1) ones_.resize(last + 1, 0);
+    for (int64_t k = std::max<int64_t>(1, first); k <= last; ++k) ones_[k] = (int64_t)sl_.h_ring[k % kRing];
+    if (cv != kNotConverged) {
+      iters_ = cv;
+    } else if (upto >= 1 && ones_[upto] == ones_[upto - 1]) {
+      iters_ = upto;
+    }
+    computed_ = (iters_ >= 0) ? iters_ : upto;
+    if (iters_ < 0 && s0_ <= max_steps_) return chunk();
+    return emit();
+  }
+
+  // After the stream has been synchronised: timing and the caller's outputs.
+  void finish(int64_t* ones_out, int32_t* steps_out, int32_t* converged_out) {
+    const int64_t last = computed_;
+    if (c_->timing) {
+      // launches that did work: every product of steps 2 .. computed
+      const int per = (mode_ == M_SG) ? 2 : 1;
+      tm_.collect(0, (last >= 2 ? (last - 1) : 0) * per);
+    }
+    if (ones_out) {
+      for (int64_t k = 0; k <= last; ++k) ones_out[k] = k < (int64_t)ones_.size() ? ones_[k] : 0;
+      if (last == 0) ones_out[0] = 0;
+    }
+    if (steps_out) *steps_out = (int32_t)last;
+    if (converged_out) *converged_out = iters_ >= 0 ? 1 : 0;
+  }
+
+ private:
+  // Chunk sizes: squaring needs 2 + log2(D) steps (at most 18 for n <=
+  // 65536): a first chunk of 6 covers D <= 16, then 4, 8, ...; launches
+  // after the fixpoint return at once but still cost a few microseconds
+  // each.  The plain and same-generation series start at 4 and double.
+  int chunk() {
+    if (chunk_ == 0) chunk_ = mode_ == M_SQUARE ? 6 : 4;
+    const int cnt = (int)std::min<int64_t>(chunk_, (int64_t)max_steps_ - s0_ + 1);
+    DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, (int)s0_, cnt, 0, s_));
+    for (int64_t t = s0_; t < s0_ + cnt; ++t) {
+      const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
+      NTParams& p = p_;
+      p.step = (int)t;
+      if (mode_ == M_PLAIN) {
+        p.X = S_[prev]; p.Y = Yop_; p.add = add_; p.add_identity = 0;
+        p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
+        int ev = tm_.begin(0);
+        DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
+        tm_.end(ev);
+      } else if (mode_ == M_SQUARE) {
+        p.X = S_[prev]; p.Y = ST_[prev]; p.add = add_; p.add_identity = 0;
+        p.out = S_[cur]; p.outT = ST_[cur]; p.count = 1; p.check = 1;
+        int ev = tm_.begin(0);
+        DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
+        tm_.end(ev);
+      } else {
+        p.X = Yop_; p.Y = S_[prev]; p.add = nullptr; p.add_identity = 0;
+        p.out = Tmp_; p.outT = nullptr; p.count = 0; p.check = 1;
+        int ev = tm_.begin(0);
+        DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
+        tm_.end(ev);
+        p.X = Tmp_; p.Y = Yop_; p.add = nullptr; p.add_identity = 1;
+        p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
+        ev = tm_.begin(0);
+        DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
+        tm_.end(ev);
+      }
+    }
+    const int64_t upto = s0_ + cnt - 1;
+    s0_ += cnt;
+    chunk_ = (mode_ == M_SQUARE && s0_ == 8) ? 4 : std::min(chunk_ * 2, 256);
+    return readback(upto);
+  }
+
+  // Copy the ring and the convergence step to pinned memory after a chunk.
+  // The ring holds the last kRing steps, more than one chunk, so every step
+  // of the chunk just run is still present when the copy is read.
+  int readback(int64_t upto) {
+    DL_HIP(hipMemcpyAsync(sl_.h_ring, sl_.ring, kRing * sizeof(unsigned long long), hipMemcpyDeviceToHost, s_));
+    DL_HIP(hipMemcpyAsync(sl_.h_conv, sl_.conv, sizeof(int), hipMemcpyDeviceToHost, s_));
+    DL_HIP(hipEventRecord(sl_.ev, s_));
+    pending_ = upto;
+    return DL_OK;
+  }
+
+  // The last iterate computed is R^(computed), in buffer computed % 2.
+  int emit() {
+    const int64_t last = computed_;
+    if (last == 0) {
+      DL_HIP(hipMemset2DAsync(R_, (size_t)ldr_, 0, (size_t)n_, (size_t)n_, s_));
+    } else {
+      const void* src = S_[last & 1];
+      DL_HIP(launch_emit(prec_, src, (int)Np_, mode_ == M_PLAIN ? 1 : 0, (int)n_, R_, ldr_, s_));
+    }
+    done_ = true;
+    return DL_OK;
+  }
+
+  dl_ctx* c_;
+  FixSlot sl_;
+  int mode_;
+  int64_t n_;
+  const uint8_t* A_;
+  int64_t lda_;
+  uint8_t* R_;
+  int64_t ldr_;
+  int prec_;
+  int32_t max_steps_;
+  hipStream_t s_;
+  Timer tm_;
+  int64_t Np_ = 0;
+  int cfg_ = 0;
+  NTParams p_{};
+  const int8_t* add_ = nullptr;
+  void *Yop_ = nullptr, *S_[2] = {nullptr, nullptr}, *ST_[2] = {nullptr, nullptr}, *Tmp_ = nullptr;
+  std::vector<int64_t> ones_ = std::vector<int64_t>(2, 0);
+  int64_t iters_ = -1;  // set when the repeat is seen
+  int64_t computed_ = 0;
+  int64_t s0_ = 2;
+  int64_t pending_ = 0;
+  int chunk_ = 0;
+  bool done_ = false;
+};
+
+// Runs `count` fixpoints of one size, mode and precision on stream s, with
+// up to two in flight: while the host reads one's counters back, the device
+// runs the other's products.  Per-fixpoint outputs are indexed by g;
+// ones_out (model sizes per step) is taken for count == 1 only.
+int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* const* A, int64_t lda,
+                  uint8_t* const* R, int64_t ldr, int prec, int32_t max_steps, int64_t* ones_out,
+                  int32_t* steps_out, int32_t* converged_out, hipStream_t s) {
   if (prec < P_I8 || prec > P_FP4) return fail(DL_EINVAL, "unknown precision");
   if (max_steps < 0) return fail(DL_EINVAL, "max_steps < 0");
+  if (count <= 0) return DL_OK;
   int rc = set_device(c);
   if (rc) return rc;
   if (n == 0) {
-    if (ones_out) ones_out[0] = 0;
-    if (ones_out && max_steps >= 1) ones_out[1] = 0;
-    if (steps_out) *steps_out = max_steps >= 1 ? 1 : 0;
-    if (converged_out) *converged_out = max_steps >= 1 ? 1 : 0;
+    for (int g = 0; g < count; ++g) {
+      if (ones_out && g == 0) {
+        ones_out[0] = 0;
+        if (max_steps >= 1) ones_out[1] = 0;
+      }
+      if (steps_out) steps_out[g] = max_steps >= 1 ? 1 : 0;
+      if (converged_out) converged_out[g] = max_steps >= 1 ? 1 : 0;
+    }
     return DL_OK;
   }
   const int64_t Np = padded_size_for(prec, n);
-  const int cfg = choose_nt_config(prec, Np);
-  const size_t mat8 = (size_t)Np * Np;
-  const size_t matT = (size_t)mat_bytes(prec, Np);
-  // layout: [add int8][op0][op1][op2][op3]
-  size_t need = mat8 + 4 * matT + 256;
-  if ((rc = ensure_ws(c, need))) return rc;
-  uint8_t* base = (uint8_t*)c->ws;
-  int8_t* ADD = (int8_t*)base;
-  uint8_t* op[4];
-  for (int i = 0; i < 4; ++i) op[i] = base + mat8 + i * matT;
-
-  Timer tm{c, s, {}, 0};
-  DL_HIP(launch_ring_clear(c->ring, c->conv, 0, 2, 1, s));
-  void *Yop = nullptr, *S[2] = {nullptr, nullptr}, *ST[2] = {nullptr, nullptr}, *Tmp = nullptr;
-  if (mode == M_PLAIN) {
-    // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
-    Yop = op[0];
-    S[0] = op[1];
-    S[1] = op[2];
-    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, nullptr, ADD, Yop, S[1], c->ring + 1, s));
-  } else if (mode == M_SQUARE) {
-    // R^(1) = A with its transpose; addend A
-    S[0] = op[0];
-    ST[0] = op[1];
-    S[1] = op[2];
-    ST[1] = op[3];
-    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, ADD, nullptr, S[1], ST[1], c->ring + 1, s));
-  } else {
-    // P in operand precision; S^(1) = I; intermediate T
-    Yop = op[0];
-    S[0] = op[1];
-    S[1] = op[2];
-    Tmp = op[3];
-    DL_HIP(launch_ingest(prec, A, lda, (int)n, (int)Np, nullptr, nullptr, Yop, nullptr, nullptr, s));
-    DL_HIP(launch_identity(prec, S[1], (int)Np, (int)n, s));
-    DL_HIP(launch_ring_set(c->ring, 1, (unsigned long long)n, s));
+  const size_t need = fix_ws_bytes(prec, Np);
+  int nslots = count >= 2 ? kFixSlots : 1;
+  if (nslots > 1 && c->budget && need * nslots > c->budget) nslots = 1;  // one at a time within the budget
+  if ((rc = ensure_ws(c, need * nslots))) return rc;
+  FixSlot slots[kFixSlots];
+  for (int i = 0; i < nslots; ++i) {
+    if (!c->slot_ev[i]) DL_HIP(hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming));
+    slots[i].ws = (uint8_t*)c->ws + need * i;
+    slots[i].ring = c->ring + (size_t)kRing * i;
+    slots[i].conv = c->conv + 4 * i;
+    slots[i].h_ring = c->h_ring + (size_t)kRing * i;
+    slots[i].h_conv = c->h_conv + 4 * i;
+    slots[i].ev = c->slot_ev[i];
   }
-
-  const TileCfg tc = nt_config(prec, cfg);
-  NTParams p{};
-  p.ld = Np;
-  p.Np = (int)Np;
-  p.n_valid = (int)n;
-  p.ones = c->ring;
-  p.conv = c->conv;
-  p.tiles_m = (int)(Np / tc.bm);
-  p.tiles_n = (int)(Np / tc.bn);
-
-  std::vector<int64_t> ones_hist(2, 0);
-  int64_t iters = -1;  // set when the repeat is seen
-  int64_t computed = max_steps >= 1 ? 1 : 0;
-  // chunk sizes: squaring needs 2 + log2(D) steps (at most 18 for n <= 65536):
-  // a first chunk of 6 covers D <= 16, then 4, 8, ...; launches after the
-  // fixpoint return at once but still cost a few microseconds each.  The
-  // plain and same-generation series start at 4 and double.
-  int chunk = mode == M_SQUARE ? 6 : 4;
-  int64_t s0 = 2;
-  int steps_launched = 0;
-
-  // Copy the ring and the convergence state to the host after a chunk.  The
-  // ring holds the last kRing steps, more than one chunk, so every step of
-  // the chunk just run is still present.
-  auto readback = [&](int64_t upto) -> int {
-    DL_HIP(hipMemcpyAsync(c->h_ring, c->ring, kRing * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    DL_HIP(hipMemcpyAsync(c->h_conv, c->conv, sizeof(int), hipMemcpyDeviceToHost, s));
-    DL_HIP(hipStreamSynchronize(s));
-    const int cv = c->h_conv[0];
-    int64_t last = upto;
-    if (cv != kNotConverged) last = std::min<int64_t>(last, cv);
-    const int64_t first = (int64_t)ones_hist.size() - 1;  // slot 1 may be unread yet
-    if ((int64_t)ones_hist.size() < last + 1) ones_hist.resize(last + 1, 0);
-    for (int64_t k = std::max<int64_t>(1, first); k <= last; ++k) ones_hist[k] = (int64_t)c->h_ring[k % kRing];
-    if (cv != kNotConverged) {
-      iters = cv;
-    } else if (upto >= 1 && ones_hist[upto] == ones_hist[upto - 1]) {
-      iters = upto;
-    }
-    computed = (iters >= 0) ? iters : upto;
+  size_t ev_used = 0;
+  std::vector<Fix> jobs;
+  jobs.reserve(count);
+  std::vector<int> inflight;  // indices into jobs, oldest first
+  int next = 0;
+  auto launch = [&](const FixSlot& sl) -> int {
+    const int g = next++;
+    jobs.emplace_back(c, sl, &ev_used, mode, n, A[g], lda, R[g], ldr, prec, max_steps, s);
+    int r = jobs.back().start();
+    if (r) return r;
+    if (!jobs.back().done()) inflight.push_back(g);
     return DL_OK;
   };
-
-  if (max_steps >= 1) {
-    // step 1 was produced by ingest; a single read-back settles max_steps == 1
-    if (max_steps == 1) {
-      if ((rc = readback(1))) return rc;
+  for (int i = 0; i < nslots && next < count; ++i)
+    if ((rc = launch(slots[i]))) break;
+  // a fixpoint that needed no read-back has freed its slot already
+  while (!rc && next < count && (int)inflight.size() < nslots) {
+    const FixSlot* freed = nullptr;
+    for (int i = 0; i < nslots && !freed; ++i) {
+      bool busy = false;
+      for (int g : inflight) busy = busy || jobs[g].slot().ws == slots[i].ws;
+      if (!busy) freed = &slots[i];
     }
-    while (iters < 0 && s0 <= max_steps) {
-      const int cnt = (int)std::min<int64_t>(chunk, (int64_t)max_steps - s0 + 1);
-      DL_HIP(launch_ring_clear(c->ring, c->conv, (int)s0, cnt, 0, s));
-      for (int64_t t = s0; t < s0 + cnt; ++t) {
-        const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
-        p.step = (int)t;
-        if (mode == M_PLAIN) {
-          p.X = S[prev]; p.Y = Yop; p.add = ADD; p.add_identity = 0;
-          p.out = S[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
-          int ev = tm.begin(0);
-          DL_HIP(launch_nt_step(prec, cfg, p, s));
-          tm.end(ev);
-        } else if (mode == M_SQUARE) {
-          p.X = S[prev]; p.Y = ST[prev]; p.add = ADD; p.add_identity = 0;
-          p.out = S[cur]; p.outT = ST[cur]; p.count = 1; p.check = 1;
-          int ev = tm.begin(0);
-          DL_HIP(launch_nt_step(prec, cfg, p, s));
-          tm.end(ev);
-        } else {
-          p.X = Yop; p.Y = S[prev]; p.add = nullptr; p.add_identity = 0;
-          p.out = Tmp; p.outT = nullptr; p.count = 0; p.check = 1;
-          int ev = tm.begin(0);
-          DL_HIP(launch_nt_step(prec, cfg, p, s));
-          tm.end(ev);
-          p.X = Tmp; p.Y = Yop; p.add = nullptr; p.add_identity = 1;
-          p.out = S[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
-          ev = tm.begin(0);
-          DL_HIP(launch_nt_step(prec, cfg, p, s));
-          tm.end(ev);
-        }
-        ++steps_launched;
-      }
-      if ((rc = readback(s0 + cnt - 1))) return rc;
-      s0 += cnt;
-      chunk = (mode == M_SQUARE && s0 == 8) ? 4 : std::min(chunk * 2, 256);
+    rc = launch(*freed);
+  }
+  while (!rc && !inflight.empty()) {
+    const int g = inflight.front();
+    inflight.erase(inflight.begin());
+    hipError_t e = hipEventSynchronize(jobs[g].slot().ev);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "hipEventSynchronize(read-back)");
+      break;
+    }
+    if ((rc = jobs[g].advance())) break;
+    if (!jobs[g].done()) {
+      inflight.push_back(g);
+    } else if (next < count) {
+      // the emit just enqueued is ordered before the next ingest into this slot
+      if ((rc = launch(jobs[g].slot()))) break;
     }
   }
-
-  // the last iterate computed is R^(computed), in buffer computed % 2
-  const int64_t last = computed;
-  if (last == 0) {
-    DL_HIP(hipMemset2DAsync(R, (size_t)ldr, 0, (size_t)n, (size_t)n, s));
-  } else {
-    const void* src = S[last & 1];
-    DL_HIP(launch_emit(prec, src, (int)Np, mode == M_PLAIN ? 1 : 0, (int)n, R, ldr, s));
-  }
-  DL_HIP(hipStreamSynchronize(s));
-  if (c->timing) {
-    // launches that did work: every product of steps 2 .. computed
-    const int per = (mode == M_SG) ? 2 : 1;
-    tm.collect(0, (last >= 2 ? (last - 1) : 0) * per);
-  }
-  if (ones_out) {
-    for (int64_t k = 0; k <= last; ++k) ones_out[k] = k < (int64_t)ones_hist.size() ? ones_hist[k] : 0;
-    if (last == 0) ones_out[0] = 0;
-  }
-  if (steps_out) *steps_out = (int32_t)last;
-  if (converged_out) *converged_out = iters >= 0 ? 1 : 0;
+  hipError_t e = hipStreamSynchronize(s);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int g = 0; g < count; ++g)
+    jobs[g].finish(g == 0 ? ones_out : nullptr, steps_out ? steps_out + g : nullptr,
+                   converged_out ? converged_out + g : nullptr);
   return DL_OK;
 }
 
@@ -316,15 +449,16 @@ int dl_create(dl_ctx** out, int device, size_t budget) {
   };
   if ((e = hipSetDevice(device)) != hipSuccess) return cleanup(hip_fail(e, "hipSetDevice"));
   if ((e = bool_kernels_init()) != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
-  if ((e = hipMalloc(&c->ring, kRing * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = hipMalloc(&c->ring, kFixSlots * kRing * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(ring)"));
   if ((e = hipMalloc(&c->conv, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(conv)"));
   c->dscratch = c->conv + 16;
-  if ((e = hipHostMalloc(&c->h_ring, kRing * sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&c->h_ring, kFixSlots * kRing * sizeof(unsigned long long), hipHostMallocDefault)) !=
+      hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(ring)"));
   if ((e = hipHostMalloc(&c->h_conv, 64 * sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(conv)"));
-  if ((e = hipMemset(c->ring, 0, kRing * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = hipMemset(c->ring, 0, kFixSlots * kRing * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemset(ring)"));
   if ((e = hipMemset(c->conv, 0, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMemset(conv)"));
   if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
@@ -345,6 +479,8 @@ int dl_destroy(dl_ctx* c) {
     (void)hipEventDestroy(ep.a);
     (void)hipEventDestroy(ep.b);
   }
+  for (auto& ev : c->slot_ev)
+    if (ev) (void)hipEventDestroy(ev);
   dl::eps_release(&c->eps);
   delete c;
   return DL_OK;
@@ -356,8 +492,8 @@ int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* 
   int rc = check_common(ctx, n, A, lda, R, ldr);
   if (rc) return rc;
   if (method != DL_TC_PLAIN && method != DL_TC_SQUARE) return fail(DL_EINVAL, "unknown method");
-  return run_fixpoint(ctx, method == DL_TC_PLAIN ? M_PLAIN : M_SQUARE, n, A, lda, R, ldr, prec, max_steps,
-                      ones, steps, converged, (hipStream_t)stream);
+  return run_fixpoints(ctx, method == DL_TC_PLAIN ? M_PLAIN : M_SQUARE, 1, n, &A, lda, &R, ldr, prec, max_steps,
+                       ones, steps, converged, (hipStream_t)stream);
 }
 
 int dl_tc(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr, int method,
@@ -373,11 +509,41 @@ int dl_tc(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int
   return DL_OK;
 }
 
+int dl_tc_batch(dl_ctx* ctx, int32_t count, int64_t n, const uint8_t* const* A, int64_t lda, uint8_t* const* R,
+                int64_t ldr, int method, int prec, int32_t* iters, void* stream) {
+  if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  if (count < 0) return fail(DL_EINVAL, "count < 0");
+  if (count == 0) return DL_OK;
+  if (!A || !R || !iters) return fail(DL_EINVAL, "NULL array argument");
+  if (method != DL_TC_PLAIN && method != DL_TC_SQUARE) return fail(DL_EINVAL, "unknown method");
+  for (int g = 0; g < count; ++g) {
+    int rc = check_common(ctx, n, A[g], lda, R[g], ldr);
+    if (rc) return rc;
+  }
+  if (n > 0) {
+    const size_t ra = mat_span(n, ldr), aa = mat_span(n, lda);
+    for (int g = 0; g < count; ++g)
+      for (int h = 0; h < count; ++h) {
+        if (h != g && overlaps(R[g], ra, A[h], aa)) return fail(DL_EINVAL, "an output overlaps another input");
+        if (h > g && overlaps(R[g], ra, R[h], ra)) return fail(DL_EINVAL, "two outputs overlap");
+      }
+  }
+  // plain: iters <= D + 1 <= n + 1; squaring: iters <= 2 + ceil(log2 n)
+  const int64_t cap = method == DL_TC_SQUARE ? 3 + 64 : n + 2;
+  std::vector<int32_t> conv(count, 0);
+  int rc = run_fixpoints(ctx, method == DL_TC_PLAIN ? M_PLAIN : M_SQUARE, count, n, A, lda, R, ldr, prec,
+                         (int32_t)std::min<int64_t>(cap, INT_MAX), nullptr, iters, conv.data(), (hipStream_t)stream);
+  if (rc) return rc;
+  for (int g = 0; g < count; ++g)
+    if (!conv[g]) return fail(DL_ENOCONV, "step cap reached before the fixpoint");
+  return DL_OK;
+}
+
 int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds, int prec,
                 int32_t max_steps, int64_t* ones, int32_t* steps, int32_t* converged, void* stream) {
   int rc = check_common(ctx, n, P, ldp, S, lds);
   if (rc) return rc;
-  return run_fixpoint(ctx, M_SG, n, P, ldp, S, lds, prec, max_steps, ones, steps, converged,
+  return run_fixpoints(ctx, M_SG, 1, n, &P, ldp, &S, lds, prec, max_steps, ones, steps, converged,
                       (hipStream_t)stream);
 }
 

@@ -145,6 +145,65 @@ def test_zero_size_and_errors(dl):
     assert ei.value.status == 1
 
 
+@pytest.mark.parametrize("count", [1, 2, 5])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("prec", ["i8", "f32"])
+def test_batch_matches_oracle(dl, count, method, prec):
+    """dl_tc_batch: every model and iteration count equal to the oracle's,
+    with an empty and a complete relation among random ones."""
+    n = 300
+    inputs = []
+    for g in range(count):
+        if g == 1:
+            a = np.zeros((n, n), np.uint8)
+        elif g == 3:
+            a = np.ones((n, n), np.uint8)
+        else:
+            a = dlgen.to_dense(n, dlgen.er_edges(n, (1.0 + g) / n, 10 + g))
+        inputs.append(a)
+    announce("tc batch", count, method, prec)
+    rs, its = dl.dl_tc_batch([dev(a) for a in inputs], method=method, prec=prec)
+    assert len(rs) == count and len(its) == count
+    for g, a in enumerate(inputs):
+        ref, _, it_ref, _ = oracle.tc_seminaive(a)
+        assert np.array_equal(host(rs[g]), ref), f"graph {g}"
+        if method == dl.DL_TC_PLAIN:
+            assert its[g] == it_ref, f"graph {g}"
+        else:
+            _, hist = oracle.bfs(a, want_matrix=False)
+            assert its[g] == oracle.square_schedule_from_hist(hist)[0], f"graph {g}"
+
+
+def test_batch_one_slot_budget_and_errors(dl):
+    """A workspace budget that holds one fixpoint runs the batch one at a
+    time with the same results; zero counts, zero sizes and overlapping
+    buffers."""
+    import torch
+
+    n = 300
+    inputs = [dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, s)) for s in range(3)]
+    ctx = dl.Context(workspace_budget=2 << 20)  # Np = 512: one fixpoint needs 1.3 MB
+    announce("tc batch one slot")
+    rs, its = dl.dl_tc_batch([dev(a) for a in inputs], ctx=ctx)
+    for g, a in enumerate(inputs):
+        assert np.array_equal(host(rs[g]), oracle.tc_seminaive(a)[0])
+    assert dl.dl_tc_batch([]) == ([], [])
+    z = [torch.zeros((0, 0), dtype=torch.uint8, device="cuda") for _ in range(3)]
+    _, its0 = dl.dl_tc_batch(z)
+    assert its0 == [1, 1, 1]
+    a0, a1 = dev(inputs[0]), dev(inputs[1])
+    out = torch.empty_like(a0)
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc_batch([a0, a1], outs=[out, out])  # two outputs overlap
+    assert ei.value.status == 1
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc_batch([a0, a1], outs=[a1, out])  # an output overlaps another input
+    assert ei.value.status == 1
+    with pytest.raises(dl.DLError) as ei:
+        dl.dl_tc_batch([a0, a1], method=7)
+    assert ei.value.status == 1
+
+
 def test_config_plain_fp32_n512(dl):
     """Plain FP32 iteration, n = 512, ER p = 2/n, seeds 0..2."""
     n = 512
@@ -160,6 +219,25 @@ def test_config_n8192_int8_square(dl, pname, p):
     for seed in range(3):
         a = dlgen.to_dense(n, dlgen.er_edges(n, p, seed))
         _check_closure(dl, a, dl.DL_TC_SQUARE, "i8", f"cfg8192 p={pname} seed={seed}")
+
+
+def test_config_n8192_batch(dl):
+    """The nine n = 8192 ER graphs as one dl_tc_batch call (the launch the
+    benchmark times): each model and count equal to the single-call path,
+    which the tests above hold to the oracle at this size."""
+    import torch
+
+    n = 8192
+    inputs = [dlgen.to_dense(n, dlgen.er_edges(n, p, seed))
+              for p in (1.0 / n, 4.0 / n, 0.01) for seed in range(3)]
+    announce("tc batch n8192 x9")
+    devs = [dev(a) for a in inputs]
+    rs, its = dl.dl_tc_batch(devs, method=dl.DL_TC_SQUARE, prec="i8")
+    for g, d in enumerate(devs):
+        r1, it1 = dl.dl_tc(d, method=dl.DL_TC_SQUARE, prec="i8")
+        assert its[g] == it1, f"graph {g}"
+        assert torch.equal(rs[g], r1), f"graph {g}"
+    del rs, devs
 
 
 @pytest.mark.parametrize("prec", ["fp4", "fp8", "bf16"])
