@@ -36,6 +36,9 @@ N = 8192
 PROBS = (("1/N", 1.0 / N), ("4/N", 4.0 / N), ("0.01", 0.01))
 SEEDS = (0, 1, 2)
 INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 MFMA, 5.0 POP/s
+# int8 step kernel of each tile configuration (dl_tune numbering)
+STEP_KERNELS = {0: "k_nt_dma<256,256,64,64,128,OpI8,2>", 1: "k_nt_step<128,128,64,64,64,OpI8,2,1>",
+                2: "k_nt_step<64,64,32,32,64,OpI8,2,1>", 3: "k_nt_dma<256,256,64,64,128,OpI8x32,2>"}
 FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 matrix
 
 
@@ -122,6 +125,10 @@ def main() -> int:
         _, its = dl.dl_tc_batch(devs, method=dl.DL_TC_SQUARE, prec=dl.DL_I8, outs=outs, ctx=ctx)
         return its
 
+    # tile configuration of the step kernel chosen by the library's autotuner
+    tile_cfg, tile_ms, tile_cand = ctx.tune("i8", N, candidates=True)
+    log(f"autotuner: cfg {tile_cfg} ({tile_ms:.4f} ms), candidates {tile_cand}")
+
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -193,13 +200,15 @@ def main() -> int:
         "config": {"workload": "TC to fixpoint, int8 repeated squaring, N=8192 ER p in {1/N,4/N,0.01} x seeds {0,1,2}, nine fixpoints per step in one batched call",
                    "n": N, "graphs": len(graphs), "iters": iters, "products_per_step": sum(products)},
         "frac_of_int8_peak": round(value / INT8_PEAK_TOPS, 4),
-        "roofline": {"bound": "mfma", "kernel": "k_nt_dma<256,256,64,64,128,OpI8,2>",
+        "roofline": {"bound": "mfma", "kernel": STEP_KERNELS[tile_cfg],
                      "achieved": round(achieved, 1), "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": measured_traffic(STEP_KERNELS[tile_cfg]),
                      "launches": launches, "avg_kernel_ms": round(avg_kernel_ms, 4),
                      "ops_per_launch": 2.0 * N ** 3,
                      "measured_mfma_peak": round(measured_peak, 1),
-                     "frac_of_measured_peak": round(achieved / measured_peak, 4)},
+                     "frac_of_measured_peak": round(achieved / measured_peak, 4),
+                     "autotuner": {"cfg": tile_cfg, "ms": round(tile_ms, 4),
+                                   "candidates_ms": [round(x, 4) for x in tile_cand]}},
         "per_graph": per_graph,
         "extras": extras,
         "serving": serving,
@@ -220,6 +229,19 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
         r = fn()
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
+
+    # tile autotuner: every configuration's time per product launch by size
+    # (its own context, so the entries do not steer the runs below)
+    tctx = dl.Context(0)
+    tune = []
+    for prec_name in ("i8", "f32"):
+        for n in (512, 1024, 2048, 4096, 8192):
+            log(f"autotune {prec_name} n={n}")
+            cfg, ms, cand = tctx.tune(prec_name, n, candidates=True)
+            tune.append({"prec": prec_name, "n": n, "cfg": cfg, "ms": round(ms, 4),
+                         "candidates_ms": [round(x, 4) for x in cand]})
+    tctx.close()
+    res["autotune"] = tune
 
     # plain FP32 fixpoint (the "Iteration" baseline) and speed-up of int8 squaring
     plain = []
@@ -519,14 +541,17 @@ def source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel: str):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary, or None if the kernel source changed since it was taken."""
+    summary, or None if it covers another kernel or the kernel source
+    changed since it was taken."""
     try:
         fields = dict(line.split(":", 1) for line in open(TRAFFIC_PROFILE) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != source_hash():
+        return None
+    if fields.get("kernel", "").strip() != kernel:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -579,8 +604,10 @@ def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
         cut = 0.1 * max(vals)
         return [v for v in vals if v >= cut]
 
-    is_step = lambda k: "k_nt_dma" in k and "OpI8" in k
+    is_step = lambda k: "k_nt_dma" in k and ("OpI8," in k or "OpI8x32," in k)
     is_copy = lambda k: "copy" in k.lower() or "elementwise" in k
+    names = {r["Kernel_Name"] for r in csv.DictReader(open(fetch_csv)) if is_step(r["Kernel_Name"])}
+    kernel = STEP_KERNELS[3] if any("OpI8x32" in k for k in names) else STEP_KERNELS[0]
     f = per_kernel(fetch_csv, is_step)
     w = per_kernel(write_csv, is_step)
     cf = per_kernel(cal_fetch_csv, is_copy)
@@ -592,7 +619,7 @@ def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
     write = sum(w) / len(w) * wfac * 1024
     algo = 3 * N * N + 2 * N * N
     print("# HBM traffic per launch of the int8 step kernel at N=8192 (rocprofv3 --pmc)")
-    print(f"kernel: k_nt_dma<256,256,64,64,128,OpI8,2>")
+    print(f"kernel: {kernel}")
     print(f"kernel_source_sha256: {source_hash()}")
     print(f"launches_counted: fetch={len(f)} write={len(w)}")
     print(f"calibration_fetch_factor: {ffac:.4f}")
@@ -631,7 +658,7 @@ def mfma_summary(csv_path: str) -> int:
         d = disp.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
                                                "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
         d[r["Counter_Name"]] = float(r["Counter_Value"])
-    groups = {"step": lambda k: "k_nt_dma" in k and "OpI8" in k,
+    groups = {"step": lambda k: "k_nt_dma" in k and ("OpI8," in k or "OpI8x32," in k),
               "peak": lambda k: "k_mfma_peak<0>" in k}
     print("# int8 matrix-core activity (rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_I8 SQ_VALU_MFMA_BUSY_CYCLES "
           "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE)")
@@ -678,7 +705,7 @@ def counter_summary(csv_path: str) -> int:
         d = disp.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
                                                "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
         d[r["Counter_Name"]] = float(r["Counter_Value"])
-    ds = [d for d in disp.values() if "k_nt_dma" in d["name"] and "OpI8" in d["name"]]
+    ds = [d for d in disp.values() if "k_nt_dma" in d["name"] and ("OpI8," in d["name"] or "OpI8x32," in d["name"])]
     top = max(d["ns"] for d in ds)
     ds = [d for d in ds if d["ns"] >= 0.1 * top]
     keys = sorted(k for k in ds[0] if k not in ("name", "ns"))

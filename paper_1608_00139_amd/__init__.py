@@ -74,6 +74,9 @@ def load() -> ctypes.CDLL:
         "dl_eps_bound": ([vp, i64, vp, i64, ctypes.POINTER(dbl), vp], ctypes.c_int),
         "dl_sg_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
         "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "dl_tune": ([vp, ctypes.c_int, i64, pi32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), vp], ctypes.c_int),
+        "dl_tune_set": ([vp, ctypes.c_int, i64, i32], ctypes.c_int),
+        "dl_tune_get": ([vp, pi32, pi64, pi32, ctypes.POINTER(dbl), i32, pi32], ctypes.c_int),
         "dl_kernel_stats": ([vp, ctypes.c_int, pi64, ctypes.POINTER(dbl), ctypes.c_int], ctypes.c_int),
         "dl_padded_size": ([i64, ctypes.c_int, ctypes.c_int], i64),
         "dl_batch_create": ([vp, ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
@@ -167,6 +170,76 @@ class Context:
         ms = ctypes.c_double()
         _check(load().dl_kernel_stats(self.handle, kernel_class, ctypes.byref(n), ctypes.byref(ms), int(reset)))
         return int(n.value), float(ms.value)
+
+    # -- tile autotuner (dl_tune*) --
+    def tune(self, prec, n: int, stream=None, candidates: bool = False):
+        """Time every tile configuration for (prec, n) and keep the fastest:
+        (configuration, ms per product launch), plus the list of every
+        candidate's ms when ``candidates`` is true."""
+        cfg = ctypes.c_int32()
+        ms = ctypes.c_double()
+        cand = (ctypes.c_double * 4)()
+        _check(load().dl_tune(self.handle, _prec(prec), int(n), ctypes.byref(cfg), ctypes.byref(ms), cand,
+                              _stream_ptr(stream)))
+        if candidates:
+            k = 4 if _prec(prec) == DL_I8 else 3
+            return int(cfg.value), float(ms.value), [float(cand[i]) for i in range(k)]
+        return int(cfg.value), float(ms.value)
+
+    def set_tuning(self, prec, n: int, cfg: int) -> None:
+        """Fix the tile configuration for (prec, n); cfg = -1 removes it."""
+        _check(load().dl_tune_set(self.handle, _prec(prec), int(n), int(cfg)))
+
+    def tuning(self) -> list[dict]:
+        """The context's tuned entries: precision name, padded size, cfg, ms."""
+        count = ctypes.c_int32()
+        _check(load().dl_tune_get(self.handle, None, None, None, None, 0, ctypes.byref(count)))
+        k = count.value
+        pr, npad = (ctypes.c_int32 * max(k, 1))(), (ctypes.c_int64 * max(k, 1))()
+        cf, ms = (ctypes.c_int32 * max(k, 1))(), (ctypes.c_double * max(k, 1))()
+        _check(load().dl_tune_get(self.handle, pr, npad, cf, ms, k, ctypes.byref(count)))
+        names = {v: key for key, v in PRECISIONS.items()}
+        return [{"prec": names[pr[i]], "np": int(npad[i]), "cfg": int(cf[i]), "ms": float(ms[i])}
+                for i in range(k)]
+
+    def save_tuning(self, path: str) -> None:
+        with open(path, "w") as f:
+            f.write(tuning_to_json(self.tuning(), torch.cuda.get_device_name(self.device)))
+
+    def load_tuning(self, path: str) -> list[dict]:
+        """Apply the entries of a file written by save_tuning; returns them."""
+        with open(path) as f:
+            entries = tuning_from_json(f.read())
+        for e in entries:
+            self.set_tuning(e["prec"], e["np"], e["cfg"])
+        return entries
+
+
+TUNING_FORMAT = "dl-tuning-1"
+
+
+def tuning_to_json(entries: list, device: str) -> str:
+    """Tuning entries as a JSON document (format, device name, entries)."""
+    import json
+
+    rows = [{"prec": e["prec"], "np": int(e["np"]), "cfg": int(e["cfg"]), "ms": float(e.get("ms", 0.0))}
+            for e in entries]
+    return json.dumps({"format": TUNING_FORMAT, "device": device, "entries": rows}, indent=1)
+
+
+def tuning_from_json(text: str) -> list:
+    """Entries of a document written by tuning_to_json, validated."""
+    import json
+
+    doc = json.loads(text)
+    if doc.get("format") != TUNING_FORMAT:
+        raise ValueError("not a tuning document")
+    out = []
+    for e in doc["entries"]:
+        if e["prec"] not in PRECISIONS or int(e["np"]) <= 0 or int(e["cfg"]) < 0:
+            raise ValueError(f"bad tuning entry {e}")
+        out.append({"prec": e["prec"], "np": int(e["np"]), "cfg": int(e["cfg"]), "ms": float(e.get("ms", 0.0))})
+    return out
 
 
 _DEFAULT: dict[int, Context] = {}

@@ -933,9 +933,10 @@ static hipError_t set_lds_attr_dma() {
 }
 
 // ----------------------------------------------------------------- configurations
-// cfg 0: 256x256 tile, 8 waves of 128x64 (large n)
-// cfg 1: 128x128 tile, 4 waves of 64x64  (medium n)
-// cfg 2: 64x64 tile,   4 waves of 32x32  (small n)
+// cfg 0: 256x256 tile, 16 waves of 64x64, direct-to-LDS slices (large n)
+// cfg 1: 128x128 tile, 4 waves of 64x64, register-staged  (medium n)
+// cfg 2: 64x64 tile,   4 waves of 32x32, register-staged  (small n)
+// cfg 3: int8 only, cfg 0 with the 32 x 32 x 32 MFMA instead of 16 x 16 x 64
 
 template <class Op, int BM, int BN, int WM, int WN, int KB, int SWZ = (KB == 64 ? 2 : 1), int PREF = 1>
 static hipError_t launch_cfg(const NTParams& p, hipStream_t s) {
@@ -969,6 +970,9 @@ static hipError_t launch_op(int cfg, const NTParams& p, hipStream_t s) {
   constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   switch (cfg) {
     case 0: return launch_dma<Op, 256, 256, 64, 64, BigCfg<Op>::KB, BigCfg<Op>::NS>(p, s);
+    case 3:
+      if constexpr (Op::kPrec == P_I8) return launch_dma<OpI8x32, 256, 256, 64, 64, 128, 2>(p, s);
+      return hipErrorInvalidValue;
     case 1: return launch_cfg<Op, 128, 128, 64, 64, KSMALL>(p, s);
     default: return launch_cfg<Op, 64, 64, 32, 32, KSMALL>(p, s);
   }
@@ -979,6 +983,8 @@ static hipError_t init_op() {
   constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   hipError_t e;
   if ((e = set_lds_attr_dma<Op, 256, 256, 64, 64, BigCfg<Op>::KB, BigCfg<Op>::NS>()) != hipSuccess) return e;
+  if constexpr (Op::kPrec == P_I8)
+    if ((e = set_lds_attr_dma<OpI8x32, 256, 256, 64, 64, 128, 2>()) != hipSuccess) return e;
   if ((e = set_lds_attr<Op, 128, 128, 64, 64, KSMALL>()) != hipSuccess) return e;
   return set_lds_attr<Op, 64, 64, 32, 32, KSMALL>();
 }
@@ -988,6 +994,7 @@ static TileCfg cfg_of(int cfg) {
   constexpr int KSMALL = (Op::CPL == 2) ? 128 : 64;
   switch (cfg) {
     case 0: { typedef typename BigCfg<Op>::K K; return {256, 256, BigCfg<Op>::KB, K::NT, K::LDS_BYTES}; }
+    case 3: { typedef DmaKernel<256, 256, 64, 64, 128, OpI8x32, 2> K; return {256, 256, 128, K::NT, K::LDS_BYTES}; }
     case 1: { typedef NTKernel<128, 128, 64, 64, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {128, 128, KSMALL, K::NT, K::LDS_BYTES}; }
     default: { typedef NTKernel<64, 64, 32, 32, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {64, 64, KSMALL, K::NT, K::LDS_BYTES}; }
   }
@@ -1035,6 +1042,8 @@ int64_t padded_size_for(int prec, int64_t n) {
   const int64_t q = 256;
   return n <= 0 ? 0 : ((n + q - 1) / q) * q;
 }
+
+int nt_config_count(int prec) { return prec == P_I8 ? 4 : 3; }
 
 int choose_nt_config(int prec, int64_t np) {
   (void)prec;

@@ -76,6 +76,8 @@ struct TileCfg {
 hipError_t launch_nt_step(int prec, int cfg_id, const NTParams& p, hipStream_t s);
 TileCfg nt_config(int prec, int cfg_id);
 int choose_nt_config(int prec, int64_t n);
+int nt_config_count(int prec);  // valid cfg ids are 0 .. count - 1
+hipError_t launch_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed, hipStream_t s);
 int64_t padded_size_for(int prec, int64_t n);
 
 hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,

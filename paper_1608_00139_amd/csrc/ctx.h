@@ -18,6 +18,15 @@ struct EventPair {
   hipEvent_t a, b;
 };
 
+// A tile configuration chosen for (precision, padded size) by the autotuner
+// or set by the caller; ms is the measured time of one product (0 if set).
+struct TuneEntry {
+  int prec;
+  int64_t np;
+  int cfg;
+  double ms;
+};
+
 struct dl_ctx {
   int device = 0;
   size_t budget = 0;
@@ -34,8 +43,12 @@ struct dl_ctx {
   double ms[3] = {0, 0, 0};
   std::vector<EventPair> events;
   dl::EpsWorkspace eps;  // workspace of the epsilon solve
+  std::vector<TuneEntry> tuned;  // tile configurations that override the size rule
 };
 
 namespace dl {
 void set_last_error(const std::string& m);
+// Tile configuration of the product kernels for (prec, Np): the tuned entry
+// if there is one, else the size rule of choose_nt_config.
+int pick_config(const dl_ctx* c, int prec, int64_t np);
 }  // namespace dl

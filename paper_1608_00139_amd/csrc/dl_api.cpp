@@ -42,6 +42,12 @@ int hip_fail(hipError_t e, const char* what) {
 
 namespace dl {
 void set_last_error(const std::string& m) { g_last_error = m; }
+
+int pick_config(const dl_ctx* c, int prec, int64_t np) {
+  for (const auto& t : c->tuned)
+    if (t.prec == prec && t.np == np) return t.cfg;
+  return choose_nt_config(prec, np);
+}
 }  // namespace dl
 
 
@@ -166,7 +172,7 @@ class Fix {
   // needs no product.
   int start() {
     Np_ = padded_size_for(prec_, n_);
-    cfg_ = choose_nt_config(prec_, Np_);
+    cfg_ = pick_config(c_, prec_, Np_);
     const size_t mat8 = (size_t)Np_ * Np_;
     const size_t matT = (size_t)mat_bytes(prec_, Np_);
     int8_t* ADD = (int8_t*)sl_.ws;
@@ -536,6 +542,131 @@ int dl_tc_batch(dl_ctx* ctx, int32_t count, int64_t n, const uint8_t* const* A, 
   if (rc) return rc;
   for (int g = 0; g < count; ++g)
     if (!conv[g]) return fail(DL_ENOCONV, "step cap reached before the fixpoint");
+  return DL_OK;
+}
+
+int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, double* cand_ms, void* stream) {
+  if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  if (prec < P_I8 || prec > P_FP4) return fail(DL_EINVAL, "unknown precision");
+  if (n <= 0 || n > (1 << 16)) return fail(DL_EINVAL, "n must be in 1 .. 65536");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t Np = padded_size_for(prec, n);
+  const size_t mat8 = (size_t)Np * Np, matT = (size_t)mat_bytes(prec, Np);
+  // [add int8][X][Y][out][outT][raw int8]: the operands of one squaring step
+  if ((rc = ensure_ws(ctx, fix_ws_bytes(prec, Np) + mat8))) return rc;
+  uint8_t* base = (uint8_t*)ctx->ws;
+  int8_t* ADD = (int8_t*)base;
+  uint8_t* op[4];
+  for (int i = 0; i < 4; ++i) op[i] = base + mat8 + i * matT;
+  uint8_t* raw = base + mat8 + 4 * matT;
+  DL_HIP(launch_hash_bool(raw, Np, (int)n, (int)Np, 0x5eedu, s));
+  DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, ADD, nullptr, op[0], op[1], nullptr, s));
+  NTParams p{};
+  p.X = op[0];
+  p.Y = op[1];
+  p.add = ADD;
+  p.out = op[2];
+  p.outT = op[3];
+  p.ld = Np;
+  p.Np = (int)Np;
+  p.n_valid = (int)n;
+  p.ones = ctx->ring;
+  p.conv = nullptr;  // never returns early
+  p.step = 2;
+  p.count = 1;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  DL_HIP(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    (void)hipEventDestroy(ea);
+    return fail(DL_EHIP, "hipEventCreate");
+  }
+  // average time of `reps` launches of configuration cfg
+  auto timed = [&](int cfg, int reps, double* ms) -> hipError_t {
+    hipError_t e = hipEventRecord(ea, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_nt_step(prec, cfg, p, s);
+    if (e == hipSuccess) e = hipEventRecord(eb, s);
+    if (e == hipSuccess) e = hipEventSynchronize(eb);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ea, eb);
+    *ms = (double)t / reps;
+    return e;
+  };
+  int best = -1;
+  double best_ms = 0.0, def_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  hipError_t e = hipSuccess;
+  for (int cfg = 0; cfg < nt_config_count(prec) && e == hipSuccess; ++cfg) {
+    const TileCfg tc = nt_config(prec, cfg);
+    p.tiles_m = (int)(Np / tc.bm);
+    p.tiles_n = (int)(Np / tc.bn);
+    double first = 0.0, ms = 0.0;
+    if ((e = timed(cfg, 1, &first)) != hipSuccess) break;  // warm-up (code load, clocks)
+    if ((e = timed(cfg, 1, &first)) != hipSuccess) break;
+    // about 5 ms of launches per candidate, 3 .. 50 of them
+    const int reps = (int)std::min(50.0, std::max(3.0, 5.0 / std::max(first, 1e-3)));
+    if ((e = timed(cfg, reps, &ms)) != hipSuccess) break;
+    if (cand_ms) cand_ms[cfg] = ms;
+    def_ms[cfg] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = cfg;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "autotune launches");
+  // keep the size rule's choice unless another configuration beats it by
+  // more than 3% (timing noise would otherwise flip near-ties between runs)
+  const int def = choose_nt_config(prec, Np);
+  if (def != best && def_ms[def] <= 1.03 * best_ms) {
+    best = def;
+    best_ms = def_ms[def];
+  }
+  bool found = false;
+  for (auto& t : ctx->tuned)
+    if (t.prec == prec && t.np == Np) {
+      t.cfg = best;
+      t.ms = best_ms;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back({prec, Np, best, best_ms});
+  if (cfg_out) *cfg_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return DL_OK;
+}
+
+int dl_tune_set(dl_ctx* ctx, int prec, int64_t n, int32_t cfg) {
+  if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  if (prec < P_I8 || prec > P_FP4) return fail(DL_EINVAL, "unknown precision");
+  if (n <= 0 || n > (1 << 16)) return fail(DL_EINVAL, "n must be in 1 .. 65536");
+  if (cfg < -1 || cfg >= nt_config_count(prec)) return fail(DL_EINVAL, "no such tile configuration");
+  const int64_t Np = padded_size_for(prec, n);
+  for (size_t i = 0; i < ctx->tuned.size(); ++i)
+    if (ctx->tuned[i].prec == prec && ctx->tuned[i].np == Np) {
+      if (cfg < 0) {
+        ctx->tuned.erase(ctx->tuned.begin() + i);
+      } else {
+        ctx->tuned[i].cfg = cfg;
+        ctx->tuned[i].ms = 0.0;
+      }
+      return DL_OK;
+    }
+  if (cfg >= 0) ctx->tuned.push_back({prec, Np, cfg, 0.0});
+  return DL_OK;
+}
+
+int dl_tune_get(dl_ctx* ctx, int32_t* prec, int64_t* np, int32_t* cfg, double* ms, int32_t cap, int32_t* count) {
+  if (!ctx || !count || cap < 0) return fail(DL_EINVAL, "bad arguments");
+  const int32_t k = (int32_t)std::min<size_t>((size_t)cap, ctx->tuned.size());
+  for (int32_t i = 0; i < k; ++i) {
+    const TuneEntry& t = ctx->tuned[i];
+    if (prec) prec[i] = t.prec;
+    if (np) np[i] = t.np;
+    if (cfg) cfg[i] = t.cfg;
+    if (ms) ms[i] = t.ms;
+  }
+  *count = (int32_t)ctx->tuned.size();
   return DL_OK;
 }
 

@@ -1,7 +1,8 @@
 // prog_kernels.hip -- elementwise kernels on int8 0/1 matrices (Np x Np,
 // row-major, zero padded): disjunction of relations, complement for negated
 // atoms (Sec. 8), transposed copies for converse atoms, the column-sum norm,
-// and the edge-list scatter that admits serving requests.
+// the edge-list scatter that admits serving requests, and the pseudo-random
+// relation the tile autotuner times its candidates on.
 #include "common.h"
 
 namespace dl {
@@ -122,6 +123,29 @@ hipError_t launch_scatter_edges(const int32_t* edges, int64_t m, int n, int Np, 
   const int64_t blocks = (m + 255) / 256;
   hipLaunchKernelGGL(k_scatter_edges, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, s, edges, m, n,
                      Np, M, M2, MT, ones);
+  return hipGetLastError();
+}
+
+// M[i][j] = a pseudo-random bit (density 1/2) for i, j < n, 0 in the padding
+// up to Np; bits from the "lowbias32" integer hash (C. Wellons) of the
+// element index mixed with the seed.
+__global__ void __launch_bounds__(256) k_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)Np * Np) return;
+  const int i = (int)(idx / Np), j = (int)(idx % Np);
+  unsigned x = (unsigned)idx ^ (seed * 0x9e3779b9u);
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  M[(int64_t)i * ld + j] = (i < n && j < n) ? (uint8_t)((x >> 7) & 1u) : (uint8_t)0;
+}
+
+hipError_t launch_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed, hipStream_t s) {
+  const int64_t total = (int64_t)Np * Np;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_bool, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, ld, n, Np, seed);
   return hipGetLastError();
 }
 

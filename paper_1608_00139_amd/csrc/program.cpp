@@ -893,7 +893,7 @@ int dl_program_run(dl_program* g, int method, void* stream) {
   }
   r.Np = padded_size_for(P_I8, g->n);
   g->Np = r.Np;
-  r.cfg = choose_nt_config(P_I8, r.Np);
+  r.cfg = pick_config(g->ctx, P_I8, r.Np);
   r.tc = nt_config(P_I8, r.cfg);
   int rc = DL_OK;
   for (size_t p = 0; p < g->names.size() && !rc; ++p) {

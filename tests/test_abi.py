@@ -57,3 +57,17 @@ def test_product_path_has_no_fallback():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "liboracle" not in src, f
+
+
+def test_tuning_document_round_trip():
+    """The autotuner's JSON document: entries survive a round trip; other
+    documents and bad entries are rejected (host logic only)."""
+    import paper_1608_00139_amd as m
+
+    entries = [{"prec": "i8", "np": 8192, "cfg": 0, "ms": 0.43}, {"prec": "f32", "np": 512, "cfg": 2, "ms": 0.0}]
+    text = m.tuning_to_json(entries, "gfx950 test")
+    assert m.tuning_from_json(text) == entries
+    with pytest.raises(ValueError):
+        m.tuning_from_json('{"format": "other", "entries": []}')
+    with pytest.raises(ValueError):
+        m.tuning_from_json(m.tuning_to_json([{"prec": "f99", "np": 512, "cfg": 0}], "x"))

@@ -204,6 +204,69 @@ def test_batch_one_slot_budget_and_errors(dl):
     assert ei.value.status == 1
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_forced_tile_configs(dl, prec):
+    """Every tile configuration, forced through dl_tune_set, gives the
+    oracle's model and count for both methods on sizes that span several
+    tiles of each configuration and end in a ragged tile; same generation on
+    each configuration too."""
+    ctx = dl.Context()
+    ncfg = 4 if prec == "i8" else 3
+    sizes = (300, 700, 2000) if prec == "i8" else (300, 700)
+    for n in sizes:
+        a = dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, 5))
+        ref, _, it_plain, _ = oracle.tc_seminaive(a)
+        _, hist = oracle.bfs(a, want_matrix=False)
+        it_sq = oracle.square_schedule_from_hist(hist)[0]
+        p = dlgen.to_dense(n, dlgen.forest_edges(n, 6))
+        sg_ref, _, sg_it, _ = oracle.sg_seminaive(p)
+        for cfg in range(ncfg):
+            ctx.set_tuning(prec, n, cfg)
+            for method, it_ref in ((dl.DL_TC_PLAIN, it_plain), (dl.DL_TC_SQUARE, it_sq)):
+                announce("forced cfg", prec, n, cfg, method)
+                r, it = dl.dl_tc(dev(a), method=method, prec=prec, ctx=ctx)
+                assert np.array_equal(host(r), ref), f"n={n} cfg={cfg} method={method}"
+                assert it == it_ref
+            announce("forced cfg sg", prec, n, cfg)
+            sgr, sit = dl.dl_sg(dev(p), prec=prec, ctx=ctx)
+            assert np.array_equal(host(sgr), sg_ref), f"sg n={n} cfg={cfg}"
+            assert sit == sg_it
+    ctx.close()
+
+
+def test_autotune(dl, tmp_path):
+    """dl_tune picks a valid configuration and records it; fixpoints after
+    tuning match the oracle; entries survive a save / load round trip into a
+    fresh context; bad configurations are rejected."""
+    ctx = dl.Context()
+    n = 1000
+    announce("autotune i8", n)
+    cfg, ms = ctx.tune("i8", n)
+    assert 0 <= cfg < 4 and ms > 0
+    ent = ctx.tuning()
+    assert ent == [{"prec": "i8", "np": 1024, "cfg": cfg, "ms": ms}]
+    a = dlgen.to_dense(n, dlgen.er_edges(n, 3.0 / n, 9))
+    r, _ = dl.dl_tc(dev(a), ctx=ctx)
+    assert np.array_equal(host(r), oracle.tc_seminaive(a)[0])
+    announce("autotune f32", 512)
+    cfg2, _ = ctx.tune("f32", 512)
+    assert 0 <= cfg2 < 3
+    path = str(tmp_path / "tuning.json")
+    ctx.save_tuning(path)
+    fresh = dl.Context()
+    loaded = fresh.load_tuning(path)
+    assert {(e["prec"], e["np"], e["cfg"]) for e in loaded} == {("i8", 1024, cfg), ("f32", 512, cfg2)}
+    assert {(e["prec"], e["np"], e["cfg"]) for e in fresh.tuning()} == {("i8", 1024, cfg), ("f32", 512, cfg2)}
+    with pytest.raises(dl.DLError):
+        fresh.set_tuning("f32", 512, 3)  # the 32 x 32 x 32 configuration is int8 only
+    with pytest.raises(dl.DLError):
+        fresh.set_tuning("i8", 512, 4)
+    fresh.set_tuning("i8", 1000, -1)
+    assert [(e["prec"], e["np"]) for e in fresh.tuning()] == [("f32", 512)]
+    ctx.close()
+    fresh.close()
+
+
 def test_config_plain_fp32_n512(dl):
     """Plain FP32 iteration, n = 512, ER p = 2/n, seeds 0..2."""
     n = 512
