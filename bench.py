@@ -69,6 +69,8 @@ def main() -> int:
     ap.add_argument("--counter-summary", metavar="CSV",
                     help="per-launch averages of every counter in a rocprofv3 --pmc CSV for the step kernel, "
                          "per CU cycle, and exit")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving workload (--serve-requests of them) and print its JSON")
     ap.add_argument("--programs-only", action="store_true",
                     help="run only the layered program workloads (both methods) and print their JSON")
     args = ap.parse_args()
@@ -79,6 +81,14 @@ def main() -> int:
 
         torch.cuda.set_device(0)
         print(json.dumps(run_programs(dl, dl.Context(0), torch)))
+        return 0
+    if args.serving_only:
+        import torch
+
+        import paper_1608_00139_amd as dl
+
+        torch.cuda.set_device(0)
+        print(json.dumps(run_serving(dl, torch, args.serve_requests)))
         return 0
     if args.trace_summary:
         return trace_summary(args.trace_summary)

@@ -272,10 +272,13 @@ int dl_batch_submit(dl_batch* batch, int kind, int64_t n, const uint8_t* A, int6
 
 /* Admit a request given as an edge list: edges is a device int32 array of m
  * pairs (i, j), row-major [m x 2], meaning r(e_i, e_j); pairs outside
- * [0, n) are skipped and repeated pairs count once.  The relation is built
- * directly in the request's pool buffers (one clear and one scatter launch,
- * no dense n x n input).  Otherwise as dl_batch_submit; the caller may
- * reuse edges after the stream reaches this point. */
+ * [0, n) are skipped and repeated pairs count once.  The call only reserves
+ * the slot and pool memory (no device work, `stream` is unused): the next
+ * dl_batch_step builds the relations of every request admitted this way
+ * since the previous round directly in their pool buffers, with one clear
+ * and one scatter launch for all of them on the step's stream, ahead of
+ * their first product.  edges must therefore stay valid and unchanged until
+ * that dl_batch_step has returned.  Otherwise as dl_batch_submit. */
 int dl_batch_submit_edges(dl_batch* batch, int kind, int64_t n, const int32_t* edges, int64_t m, int64_t tag,
                           int32_t* slot, void* stream);
 

@@ -537,6 +537,7 @@ class Batch:
         self._tags = (ctypes.c_int64 * self._cap)()
         self._slots = (ctypes.c_int32 * self._cap)()
         self._iters = (ctypes.c_int32 * self._cap)()
+        self._pending_edges: list = []
 
     def close(self) -> None:
         if self._h:
@@ -575,12 +576,17 @@ class Batch:
         if rc == DL_EAGAIN:
             return None
         _check(rc)
+        # the library reads the edges in the next dl_batch_step: keep them alive
+        self._pending_edges.append(edges)
         return int(slot.value)
 
     def dl_batch_step(self) -> tuple[int, int]:
         active = ctypes.c_int32()
         fin = ctypes.c_int32()
-        _check(load().dl_batch_step(self._h, ctypes.byref(active), ctypes.byref(fin), _stream_ptr(self.stream)))
+        try:
+            _check(load().dl_batch_step(self._h, ctypes.byref(active), ctypes.byref(fin), _stream_ptr(self.stream)))
+        finally:
+            self._pending_edges.clear()
         return int(active.value), int(fin.value)
 
     def dl_batch_poll(self) -> list[tuple[int, int, int]]:

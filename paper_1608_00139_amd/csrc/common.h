@@ -67,6 +67,27 @@ struct GroupDesc {
   int tile_start;  // first work-list index of this request
 };
 
+// One request of a grouped admission (serving): clear its buffers, write the
+// identity where same generation needs S^(1) = I, zero its admission counter,
+// then scatter its edge list.  clear_start / edge_start are running totals
+// (16-byte units, edges) over the requests before it.
+struct AdmitDesc {
+  int8_t* base;            // start of the region to clear
+  long long clear_units;   // 16-byte units to clear from base
+  long long clear_start;
+  long long ident_off;     // byte offset from base of an Np x Np identity block, -1 if none
+  int8_t* M;               // scatter targets (see k_scatter_edges); M2 / MT may be null
+  int8_t* M2;
+  int8_t* MT;
+  unsigned long long* ones;  // distinct edges counter (may be null), zeroed by the clear
+  const int32_t* edges;
+  long long m;
+  long long edge_start;
+  int n;
+  int Np;
+};
+hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, long long total_edges, hipStream_t s);
+
 // Launch helpers implemented in bool_kernels.hip.
 struct TileCfg {
   int bm, bn, kb, threads;

@@ -126,6 +126,93 @@ hipError_t launch_scatter_edges(const int32_t* edges, int64_t m, int n, int Np, 
   return hipGetLastError();
 }
 
+// ---- grouped admission of serving requests (two launches per round)
+// Last request whose running total start(d) is <= x.
+template <class F>
+__device__ inline int find_req(int nreq, long long x, F start) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start(mid) <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Clear every request's region in 16-byte units; units inside the identity
+// block get the diagonal bytes (i, i) for i < n; the thread that clears a
+// request's first unit zeroes its counter.
+__global__ void __launch_bounds__(256) k_admit_clear(const AdmitDesc* __restrict__ d, int nreq, long long total) {
+  for (long long u = (long long)blockIdx.x * 256 + threadIdx.x; u < total; u += (long long)gridDim.x * 256) {
+    const int q = find_req(nreq, u, [&](int i) { return d[i].clear_start; });
+    const long long local = u - d[q].clear_start;
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (d[q].ident_off >= 0) {
+      const long long o = local * 16 - d[q].ident_off;
+      const long long np = d[q].Np;
+      if (o >= 0 && o < np * np) {
+        const long long i = o / np, j0 = o % np;
+        if (i < d[q].n && i >= j0 && i < j0 + 16) {
+          const int t = (int)(i - j0);
+          v[t >> 2] |= 1u << (8 * (t & 3));
+        }
+      }
+    }
+    *(u32x4*)(d[q].base + local * 16) = v;
+    if (local == 0 && d[q].ones) *d[q].ones = 0ull;
+  }
+}
+
+// Scatter every request's edges (as k_scatter_edges).  A wave whose lanes all
+// hold edges of one request adds its distinct-edge count with one atomic.
+__global__ void __launch_bounds__(256) k_admit_scatter(const AdmitDesc* __restrict__ d, int nreq, long long total) {
+  for (long long e0 = (long long)blockIdx.x * 256; e0 < total; e0 += (long long)gridDim.x * 256) {
+    const long long e = e0 + threadIdx.x;
+    int q = -1, c = 0;
+    if (e < total) {
+      q = find_req(nreq, e, [&](int i) { return d[i].edge_start; });
+      const AdmitDesc& a = d[q];
+      const long long k = e - a.edge_start;
+      const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
+      if (i >= 0 && j >= 0 && i < a.n && j < a.n) {
+        const int64_t off = (int64_t)i * a.Np + j;
+        unsigned* w = (unsigned*)(a.M + (off & ~(int64_t)3));
+        const unsigned bit = 1u << (8 * (off & 3));
+        if (!(atomicOr(w, bit) & bit)) c = 1;
+        if (a.M2) a.M2[off] = 1;
+        if (a.MT) a.MT[(int64_t)j * a.Np + i] = 1;
+      }
+    }
+    const int q0 = __shfl(q, 0, 64);
+    if (__all(q == q0)) {
+      int t = c;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      if ((threadIdx.x & 63) == 0 && t && q0 >= 0 && d[q0].ones) atomicAdd(d[q0].ones, (unsigned long long)t);
+    } else if (c && d[q].ones) {
+      atomicAdd(d[q].ones, 1ull);
+    }
+  }
+}
+
+hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, long long total_edges, hipStream_t s) {
+  if (nreq <= 0) return hipSuccess;
+  if (total_units > 0) {
+    const long long blocks = (total_units + 255) / 256;
+    hipLaunchKernelGGL(k_admit_clear, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, d, nreq,
+                       total_units);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (total_edges > 0) {
+    const long long blocks = (total_edges + 255) / 256;
+    hipLaunchKernelGGL(k_admit_scatter, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256), 0, s, d, nreq,
+                       total_edges);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
 // M[i][j] = a pseudo-random bit (density 1/2) for i, j < n, 0 in the padding
 // up to Np; bits from the "lowbias32" integer hash (C. Wellons) of the
 // element index mixed with the seed.

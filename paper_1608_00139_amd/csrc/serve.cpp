@@ -76,6 +76,9 @@ struct dl_batch {
   GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
   unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max], by slot
   unsigned long long* h_cnt = nullptr;
+  AdmitDesc* d_adm = nullptr;   // grouped admission descriptors [max]
+  AdmitDesc* h_adm = nullptr;   // pinned host copy
+  std::vector<AdmitDesc> pend;  // edge-list requests admitted since the last round
   int max_active = 0;
   int grid = 1024;  // persistent workgroups of the 64 and 128 tile launches
   int cus = 256;
@@ -173,6 +176,11 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
     return fail_destroy(bfail(DL_ENOMEM, "pinned counter allocation failed"));
   if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_EHIP, "counter clear"));
+  if ((e = hipMalloc(&b->d_adm, sizeof(AdmitDesc) * max_active)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "admission descriptor allocation failed"));
+  if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * max_active, hipHostMallocDefault)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "pinned admission descriptor allocation failed"));
+  b->pend.reserve(max_active);
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
@@ -191,6 +199,8 @@ int dl_batch_destroy(dl_batch* b) {
   if (b->h_desc) (void)hipHostFree(b->h_desc);
   if (b->d_cnt) (void)hipFree(b->d_cnt);
   if (b->h_cnt) (void)hipHostFree(b->h_cnt);
+  if (b->d_adm) (void)hipFree(b->d_adm);
+  if (b->h_adm) (void)hipHostFree(b->h_adm);
   delete b;
   return DL_OK;
 }
@@ -200,9 +210,12 @@ int dl_batch_destroy(dl_batch* b) {
 namespace {
 
 // Admission shared by both submit calls: a slot, pool memory, the request's
-// buffers; `fill` writes the relation into them.
+// buffers; `fill` writes the relation into them.  A deferred admission leaves
+// every device write to `fill` (which queues a grouped-admission descriptor
+// that also zeroes the counter and writes S^(1) = I).
 template <class Fill>
-int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipStream_t s, Fill fill) {
+int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipStream_t s, bool deferred,
+          Fill fill) {
   if (!b || !slot_out) return bfail(DL_EINVAL, "NULL argument");
   if (kind != 0 && kind != 1) return bfail(DL_EINVAL, "kind must be 0 (closure) or 1 (same generation)");
   if (n <= 0 || n > 16384) return bfail(DL_EINVAL, "bad relation size (1 <= n <= 16384)");
@@ -236,7 +249,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   if (kind == 0) {
     r.add = base;
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * (1 + i);  // R0, R0T, R1, R1T
-    BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
+    if (!deferred) BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
     // addend A, R^(1) = A, R^(1)T = A^T
     int rc = fill(n, Np, (int8_t*)r.add, (int8_t*)r.b[2], (int8_t*)r.b[3], adm);
     if (rc) {
@@ -254,7 +267,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
       r = Req();
       return rc;
     }
-    BHIP(launch_identity(P_I8, r.b[2], (int)Np, (int)n, s));
+    if (!deferred) BHIP(launch_identity(P_I8, r.b[2], (int)Np, (int)n, s));
     r.computed = 1;
     r.ones.push_back(n);  // S^(1) = I: one fact diag(x, x) per constant
   }
@@ -270,7 +283,7 @@ int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t 
                     void* stream) {
   if (!A || lda < n) return bfail(DL_EINVAL, "bad relation (A NULL or lda < n)");
   hipStream_t s = (hipStream_t)stream;
-  return admit(b, kind, n, tag, slot_out, s,
+  return admit(b, kind, n, tag, slot_out, s, false,
                [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
                  // closure: M = addend, M2 = R^(1), MT = R^(1)T; same generation: M = P
                  if (M2)
@@ -284,13 +297,25 @@ int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t 
 int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges, int64_t m, int64_t tag,
                           int32_t* slot_out, void* stream) {
   if (m < 0 || (m > 0 && !edges)) return bfail(DL_EINVAL, "bad edge list");
-  hipStream_t s = (hipStream_t)stream;
-  return admit(b, kind, n, tag, slot_out, s,
+  (void)stream;  // the device work runs in the next dl_batch_step, on its stream
+  return admit(b, kind, n, tag, slot_out, nullptr, true,
                [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
-                 const size_t mb = (size_t)Np * Np;
-                 // the request's buffers are contiguous: clear them in one call
-                 BHIP(hipMemsetAsync(M, 0, (kind == 0 ? 5 : 1) * mb, s));
-                 BHIP(launch_scatter_edges(edges, m, (int)nn, (int)Np, M, M2, MT, ones, s));
+                 const long long mb = (long long)Np * Np;
+                 // the request's buffers are contiguous from M: closure clears
+                 // A, R0, R0T, R1, R1T; same generation P, S0 and S1 = I
+                 AdmitDesc a{};
+                 a.base = M;
+                 a.clear_units = (kind == 0 ? 5 : 3) * mb / 16;
+                 a.ident_off = kind == 0 ? -1 : 2 * mb;
+                 a.M = M;
+                 a.M2 = M2;
+                 a.MT = MT;
+                 a.ones = ones;
+                 a.edges = edges;
+                 a.m = m;
+                 a.n = (int)nn;
+                 a.Np = (int)Np;
+                 b->pend.push_back(a);
                  return DL_OK;
                });
 }
@@ -299,6 +324,23 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
   if (!b) return bfail(DL_EINVAL, "NULL batch");
   hipStream_t s = (hipStream_t)stream;
   BHIP(hipSetDevice(b->device));
+  // edge-list requests admitted since the last round: one clear and one
+  // scatter launch for all of them, ahead of their first product
+  if (!b->pend.empty()) {
+    const int na = (int)b->pend.size();
+    long long units = 0, edges = 0;
+    for (int i = 0; i < na; ++i) {
+      AdmitDesc& a = b->pend[i];
+      a.clear_start = units;
+      a.edge_start = edges;
+      units += a.clear_units;
+      edges += a.m;
+      b->h_adm[i] = a;
+    }
+    b->pend.clear();
+    BHIP(hipMemcpyAsync(b->d_adm, b->h_adm, sizeof(AdmitDesc) * na, hipMemcpyHostToDevice, s));
+    BHIP(launch_admit(b->d_adm, na, units, edges, s));
+  }
   // build this round's work lists (64, 128 and 256 tiles); the counters of a
   // request's product are at d_cnt[slot]
   int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};

@@ -154,6 +154,57 @@ def test_edge_list_admission(dl):
     b.close()
 
 
+def test_grouped_admission_many_small(dl):
+    """Forty edge-list requests admitted before one round (one grouped clear
+    and scatter for all of them): sizes 1..90, empty lists, repeated and
+    out-of-range pairs, lists that end inside a wave of the scatter; every
+    model, count of distinct pairs and iteration count equals the oracle's."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    b = dl.Batch(pool_bytes=1 << 28, max_active=64)
+    cases = {}
+    for tag in range(40):
+        n = int(rng.integers(1, 91))
+        kind = dl.Batch.TC if tag % 3 else dl.Batch.SG
+        m = 0 if tag % 7 == 0 else int(rng.integers(1, 3 * n + 2))
+        if kind == dl.Batch.SG:
+            par = dlgen.forest_parents(n, tag)
+            e = np.stack([np.nonzero(par >= 0)[0], par[par >= 0]], axis=1).astype(np.int32)[: m]
+        else:
+            e = rng.integers(-2, n + 2, size=(m, 2)).astype(np.int32)
+        a = np.zeros((n, n), np.uint8)
+        ok = (e[:, 0] >= 0) & (e[:, 1] >= 0) & (e[:, 0] < n) & (e[:, 1] < n) if len(e) else np.zeros(0, bool)
+        a[e[ok, 0], e[ok, 1]] = 1
+        slot = b.dl_batch_submit_edges(kind, n, torch.from_numpy(e.reshape(-1, 2)).cuda(), tag)
+        assert slot is not None
+        cases[tag] = (kind, n, a)
+    announce("serve grouped admission", len(cases))
+    fin = {}
+    for _ in range(200):
+        b.dl_batch_step()
+        for tag, sl, iters in b.dl_batch_poll():
+            n = cases[tag][1]
+            out = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+            ones = b.dl_batch_fetch(sl, out)
+            fin[tag] = (host(out), iters, ones)
+        if len(fin) == len(cases):
+            break
+    assert len(fin) == len(cases)
+    for tag, (kind, n, a) in cases.items():
+        if kind == dl.Batch.TC:
+            ref, _, _, _ = oracle.tc_seminaive(a)
+            _, hist = oracle.bfs(a, want_matrix=False)
+            it_ref = oracle.square_schedule_from_hist(hist)[0]
+        else:
+            ref, _, it_ref, _ = oracle.sg_seminaive(a)
+        got, iters, ones = fin[tag]
+        assert np.array_equal(got, ref), (tag, kind, n)
+        assert iters == it_ref, (tag, kind, n)
+        assert ones == int(ref.sum()), (tag, kind, n)
+    b.close()
+
+
 def test_large_requests_all_tile_sizes(dl):
     """A mix spanning the three tile sizes (n up to 1600: 64, 128 and 256 x 256
     grouped tiles in one round), dense and edge-list admission, against the oracle."""
