@@ -491,14 +491,14 @@ def run_serving(dl, torch, count: int, seed: int = 0):
     log(f"serving: closed-loop burst of {burst_n}")
     mk = prepare(burst)
     warm = dlgen.serving_stream(64, seed + 1, rate=0.0)
-    run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512)
-    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512)
+    run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512, lookahead=1)
+    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512, lookahead=1)
     sat = sb.summary()
     rate = 0.8 * sat["req_per_s"]
     stream = dlgen.serving_stream(count, seed, rate=rate)
     log(f"serving: Poisson stream of {count} at {rate:.0f} req/s")
     mk = prepare(stream)
-    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512)
+    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512, lookahead=1)
     ops = 0.0
     for c in st.completions:
         per_step = 2.0 if c.kind == 1 else 1.0
@@ -507,7 +507,8 @@ def run_serving(dl, torch, count: int, seed: int = 0):
     out.update({"offered_rate": round(rate, 1), "saturation": sat,
                 "eff_tops_padded": round(ops / st.wall / 1e12, 2),
                 "workload": f"{count} requests, 70% TC (ER p=3/n) / 30% SG (forest), n log-uniform [64, 2048], "
-                            f"Poisson arrivals at 0.8x the closed-loop saturation rate, int8 grouped steps"})
+                            f"Poisson arrivals at 0.8x the closed-loop saturation rate, int8 grouped steps, "
+                            f"one round of look-ahead"})
     return out
 
 

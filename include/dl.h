@@ -284,8 +284,19 @@ int dl_batch_submit_edges(dl_batch* batch, int kind, int64_t n, const int32_t* e
 
 /* One round (blocks until its model sizes are read back).  *active receives
  * the number of requests still running, *finished the number that finished
- * in this round. */
+ * in this round.  With one round of look-ahead, the call enqueues the next
+ * round and then waits for the round the previous call enqueued, so *finished
+ * counts the requests found finished in that older round and the host work
+ * between calls overlaps the device's products; every result is the same. */
 int dl_batch_step(dl_batch* batch, int32_t* active, int32_t* finished, void* stream);
+
+/* Rounds of look-ahead of dl_batch_step: 0 (the default: each call runs and
+ * reads back one round) or 1 (each call enqueues one round and reads back
+ * the previous one; a request that finishes in a round has its next product
+ * computed and discarded, and pool memory freed by dl_batch_fetch returns to
+ * the pool after the round in flight completes).  Setting 0 while a round is
+ * in flight is DL_EINVAL: call dl_batch_step until *active is 0 first. */
+int dl_batch_set_lookahead(dl_batch* batch, int32_t rounds);
 
 /* Up to cap finished requests since the last poll: their tags, slots and
  * iteration counts (the dl_tc / dl_sg convention). */

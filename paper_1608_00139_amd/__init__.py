@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
         "dl_batch_submit": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
         "dl_batch_submit_edges": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
         "dl_batch_step": ([vp, pi32, pi32, vp], ctypes.c_int),
+        "dl_batch_set_lookahead": ([vp, i32], ctypes.c_int),
         "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
         "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
         "dl_batch_info": ([vp, pi32, pi32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -526,13 +527,16 @@ class Batch:
 
     TC, SG = 0, 1
 
-    def __init__(self, pool_bytes: int, max_active: int = 256, ctx: Context | None = None, stream=None):
+    def __init__(self, pool_bytes: int, max_active: int = 256, ctx: Context | None = None, stream=None,
+                 lookahead: int = 0):
         lib = load()
         self.ctx = _ctx(ctx)
         self.stream = stream
         self._h = ctypes.c_void_p()
         _check(lib.dl_batch_create(self.ctx.handle, self.ctx.device, int(pool_bytes), int(max_active),
                                    ctypes.byref(self._h)))
+        if lookahead:
+            _check(lib.dl_batch_set_lookahead(self._h, int(lookahead)))
         self._cap = int(max_active)
         self._tags = (ctypes.c_int64 * self._cap)()
         self._slots = (ctypes.c_int32 * self._cap)()

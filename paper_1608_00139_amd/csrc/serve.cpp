@@ -16,6 +16,18 @@
 // as dl_tc/dl_sg) and can be fetched, which frees its slot and pool memory.
 // Requests can be submitted between any two rounds, so batching is
 // continuous at the granularity of one product.
+//
+// With one round of look-ahead (dl_batch_set_lookahead), a dl_batch_step
+// enqueues the next round before it waits for the one already on the device,
+// so the host's bookkeeping between rounds overlaps the device's products.
+// The next round is built before the current one's model sizes are known: a
+// request that finishes in round k has its round k + 1 product computed and
+// ignored (it writes only the buffer that does not hold the model).  Each
+// round has its own counter, descriptor and read-back set (two sets
+// alternate); a round's entries carry the request's admission number, so a
+// slot fetched and reused meanwhile is not confused with its previous
+// request; pool memory released by dl_batch_fetch returns to the pool only
+// after the round that may still read it has completed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,6 +73,25 @@ struct Req {
   int64_t iters = 0;
   int tile = 64;            // output tile of its products (Np is a multiple of it)
   bool admit_count = false; // ones[1] pending from the ingest counter
+  uint64_t gen = 0;         // admission number
+  int64_t icomp = 0;        // issue state: iterate the next product builds on ...
+  int iphase = 0;           // ... and (same generation) which of its two products
+};
+
+// One request's product in a round, as recorded when the round was issued.
+struct RoundItem {
+  int slot;
+  uint64_t gen;
+  int kind;
+  int phase;     // same generation: 0 = T = [P S], 1 = S' = [I + T P^T]
+  int64_t t;     // iterate this product belongs to
+  bool admit;    // this round also reads the request's admission counter
+};
+
+struct Round {
+  std::vector<RoundItem> items;
+  int set = 0;  // counter / descriptor / read-back set
+  bool live = false;
 };
 
 }  // namespace
@@ -72,13 +103,20 @@ struct dl_batch {
   size_t pool_bytes = 0;
   std::map<size_t, size_t> free_list;  // offset -> size
   std::vector<Req> req;
-  GroupDesc* d_desc = nullptr;  // device descriptors: 64-, 128- and 256-tile lists [max] each
+  // two sets (alternating rounds) of everything a round reads or writes:
+  GroupDesc* d_desc = nullptr;  // device descriptors: 64-, 128- and 256-tile lists [max] each, per set
   GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
-  unsigned long long* d_cnt = nullptr;  // round counters [max] + admission counters [max], by slot
-  unsigned long long* h_cnt = nullptr;
-  AdmitDesc* d_adm = nullptr;   // grouped admission descriptors [max]
+  unsigned long long* d_cnt = nullptr;  // round counters [max] per set, then admission counters [max]
+  unsigned long long* h_cnt = nullptr;  // per set: round counters [max], admission counters [max]
+  AdmitDesc* d_adm = nullptr;   // grouped admission descriptors [max] per set
   AdmitDesc* h_adm = nullptr;   // pinned host copy
+  hipEvent_t ev[2] = {nullptr, nullptr};  // end of each set's read-back
   std::vector<AdmitDesc> pend;  // edge-list requests admitted since the last round
+  int lookahead = 0;
+  int64_t rounds_issued = 0;
+  Round inflight;               // issued, not yet read (look-ahead only)
+  uint64_t next_gen = 1;
+  std::vector<std::pair<size_t, size_t>> retire;  // pool regions freed once `inflight` completes
   int max_active = 0;
   int grid = 1024;  // persistent workgroups of the 64 and 128 tile launches
   int cus = 256;
@@ -166,20 +204,24 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   }
   b->pool_bytes = pool_bytes;
   b->free_list[0] = pool_bytes;
-  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * kLists * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * kLists * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * kLists * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * kLists * max_active, hipHostMallocDefault)) !=
+      hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
-  if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 3 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
-  if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 4 * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned counter allocation failed"));
-  if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 2 * max_active)) != hipSuccess)
+  if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 3 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_EHIP, "counter clear"));
-  if ((e = hipMalloc(&b->d_adm, sizeof(AdmitDesc) * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_adm, sizeof(AdmitDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "admission descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned admission descriptor allocation failed"));
+  for (auto& ev : b->ev)
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return fail_destroy(bfail(DL_EHIP, "event creation failed"));
   b->pend.reserve(max_active);
   int cus = 256;
   hipDeviceProp_t prop;
@@ -201,6 +243,8 @@ int dl_batch_destroy(dl_batch* b) {
   if (b->h_cnt) (void)hipHostFree(b->h_cnt);
   if (b->d_adm) (void)hipFree(b->d_adm);
   if (b->h_adm) (void)hipHostFree(b->h_adm);
+  for (auto& ev : b->ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
   return DL_OK;
 }
@@ -245,7 +289,8 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   uint8_t* base = b->pool + off;
   const size_t m = (size_t)Np * Np;
   r.ones.push_back(0);
-  unsigned long long* adm = b->d_cnt + b->max_active + slot;
+  r.gen = b->next_gen++;
+  unsigned long long* adm = b->d_cnt + 2 * b->max_active + slot;
   if (kind == 0) {
     r.add = base;
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * (1 + i);  // R0, R0T, R1, R1T
@@ -257,7 +302,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
       r = Req();
       return rc;
     }
-    r.computed = 1;
+    r.computed = r.icomp = 1;
     r.admit_count = true;
   } else {
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // P, S0, S1, T
@@ -268,7 +313,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
       return rc;
     }
     if (!deferred) BHIP(launch_identity(P_I8, r.b[2], (int)Np, (int)n, s));
-    r.computed = 1;
+    r.computed = r.icomp = 1;
     r.ones.push_back(n);  // S^(1) = I: one fact diag(x, x) per constant
   }
   *slot_out = slot;
@@ -320,14 +365,25 @@ int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges
                });
 }
 
-int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void* stream) {
-  if (!b) return bfail(DL_EINVAL, "NULL batch");
-  hipStream_t s = (hipStream_t)stream;
-  BHIP(hipSetDevice(b->device));
+}  // extern "C"
+
+namespace {
+
+// Enqueue one round on s: the grouped admission of pending edge-list
+// requests, then one product for every unfinished request (as far as the
+// host knows), then the read-back of the round's counters into its set.
+// rd is left not live when there was nothing to run.
+int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
+  rd.items.clear();
+  rd.live = false;
+  const int set = (int)(b->rounds_issued & 1);
+  const int M = b->max_active;
   // edge-list requests admitted since the last round: one clear and one
   // scatter launch for all of them, ahead of their first product
   if (!b->pend.empty()) {
     const int na = (int)b->pend.size();
+    AdmitDesc* ha = b->h_adm + (size_t)set * M;
+    AdmitDesc* da = b->d_adm + (size_t)set * M;
     long long units = 0, edges = 0;
     for (int i = 0; i < na; ++i) {
       AdmitDesc& a = b->pend[i];
@@ -335,92 +391,144 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
       a.edge_start = edges;
       units += a.clear_units;
       edges += a.m;
-      b->h_adm[i] = a;
+      ha[i] = a;
     }
     b->pend.clear();
-    BHIP(hipMemcpyAsync(b->d_adm, b->h_adm, sizeof(AdmitDesc) * na, hipMemcpyHostToDevice, s));
-    BHIP(launch_admit(b->d_adm, na, units, edges, s));
+    BHIP(hipMemcpyAsync(da, ha, sizeof(AdmitDesc) * na, hipMemcpyHostToDevice, s));
+    BHIP(launch_admit(da, na, units, edges, s));
   }
-  // build this round's work lists (64, 128 and 256 tiles); the counters of a
-  // request's product are at d_cnt[slot]
+  // this round's work lists (64, 128 and 256 tiles); the counters of a
+  // request's product are at d_cnt[set][slot]
+  unsigned long long* cnt = b->d_cnt + (size_t)set * M;
+  GroupDesc* hset = b->h_desc + (size_t)set * kLists * M;
+  GroupDesc* dset = b->d_desc + (size_t)set * kLists * M;
   int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};
-  std::vector<int> slots;
-  for (int i = 0; i < b->max_active; ++i) {
+  for (int i = 0; i < M; ++i) {
     Req& r = b->req[i];
     if (!r.used || r.done) continue;
     const int li = list_of(r.tile);
-    GroupDesc& g = b->h_desc[li * b->max_active + na[li]];
+    GroupDesc& g = hset[li * M + na[li]];
     std::memset(&g, 0, sizeof g);
     g.Np = (int)r.Np;
     g.n_valid = (int)r.n;
     g.tile_start = tiles[li];
     g.cnt = nullptr;
+    RoundItem it{i, r.gen, r.kind, r.iphase, r.icomp + 1, r.admit_count};
+    r.admit_count = false;
+    const int64_t t = r.icomp + 1;  // iterate this product belongs to
     if (r.kind == 0) {
-      const int64_t t = r.computed + 1;  // iterate produced by this round
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       g.X = r.b[2 * prev];
       g.Y = r.b[2 * prev + 1];
       g.add = (const int8_t*)r.add;
       g.out = r.b[2 * cur];
       g.outT = r.b[2 * cur + 1];
-      g.cnt = b->d_cnt + i;
-    } else if (r.phase == 0) {
-      const int64_t t = r.computed + 1;
+      g.cnt = cnt + i;
+      r.icomp = t;
+    } else if (r.iphase == 0) {
       const int prev = (int)((t - 1) & 1);
       g.X = r.b[0];
       g.Y = r.b[1 + prev];
       g.out = r.b[3];
+      r.iphase = 1;
     } else {
-      const int64_t t = r.computed + 1;
       const int cur = (int)(t & 1);
       g.X = r.b[3];
       g.Y = r.b[0];
       g.add_identity = 1;
       g.out = r.b[1 + cur];
-      g.cnt = b->d_cnt + i;
+      g.cnt = cnt + i;
+      r.icomp = t;
+      r.iphase = 0;
     }
     tiles[li] += (int)((r.Np / r.tile) * (r.Np / r.tile));
-    slots.push_back(i);
+    rd.items.push_back(it);
     ++na[li];
   }
-  const int nact = na[0] + na[1] + na[2];
-  if (nact > 0) {
-    BHIP(hipMemsetAsync(b->d_cnt, 0, sizeof(unsigned long long) * b->max_active, s));
-    for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
-      if (!na[li]) continue;
-      GroupDesc* hd = b->h_desc + li * b->max_active;
-      GroupDesc* dd = b->d_desc + li * b->max_active;
-      BHIP(hipMemcpyAsync(dd, hd, sizeof(GroupDesc) * na[li], hipMemcpyHostToDevice, s));
-      const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
-      BHIP(launch_group_step(64 << li, dd, na[li], tiles[li], std::min(grid, tiles[li]), s));
-    }
+  if (rd.items.empty()) return DL_OK;
+  BHIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * M, s));
+  for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
+    if (!na[li]) continue;
+    BHIP(hipMemcpyAsync(dset + li * M, hset + li * M, sizeof(GroupDesc) * na[li], hipMemcpyHostToDevice, s));
+    const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
+    BHIP(launch_group_step(64 << li, dset + li * M, na[li], tiles[li], std::min(grid, tiles[li]), s));
   }
-  BHIP(hipMemcpyAsync(b->h_cnt, b->d_cnt, sizeof(unsigned long long) * 2 * b->max_active, hipMemcpyDeviceToHost, s));
-  BHIP(hipStreamSynchronize(s));
-  int finished = 0;
-  for (int sl : slots) {
-    Req& r = b->req[sl];
-    if (r.admit_count) {
-      r.ones.push_back((int64_t)b->h_cnt[b->max_active + sl]);  // ones[1] = |A|
-      r.admit_count = false;
-    }
-    if (r.kind == 0) {
-      r.computed += 1;
-      r.ones.push_back((int64_t)b->h_cnt[sl]);
-    } else if (r.phase == 0) {
+  unsigned long long* hc = b->h_cnt + (size_t)set * 2 * M;
+  BHIP(hipMemcpyAsync(hc, cnt, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(hc + M, b->d_cnt + 2 * (size_t)M, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost, s));
+  BHIP(hipEventRecord(b->ev[set], s));
+  rd.set = set;
+  rd.live = true;
+  ++b->rounds_issued;
+  return DL_OK;
+}
+
+// Wait for a round's read-back and take its model sizes; entries of requests
+// already finished or fetched (and their slots reused) are skipped.
+int complete_round(dl_batch* b, Round& rd, int* finished) {
+  if (!rd.live) return DL_OK;
+  BHIP(hipEventSynchronize(b->ev[rd.set]));
+  rd.live = false;
+  const int M = b->max_active;
+  const unsigned long long* hc = b->h_cnt + (size_t)rd.set * 2 * M;
+  for (const RoundItem& it : rd.items) {
+    Req& r = b->req[it.slot];
+    if (!r.used || r.gen != it.gen || r.done) continue;
+    if (it.admit) r.ones.push_back((int64_t)hc[M + it.slot]);  // ones[1] = |A|
+    if (it.kind == 0) {
+      r.computed = it.t;
+      r.ones.push_back((int64_t)hc[it.slot]);
+    } else if (it.phase == 0) {
       r.phase = 1;
     } else {
-      r.computed += 1;
+      r.computed = it.t;
       r.phase = 0;
-      r.ones.push_back((int64_t)b->h_cnt[sl]);
+      r.ones.push_back((int64_t)hc[it.slot]);
     }
     settle(r);
     if (r.done) {
-      b->finished.push_back(sl);
-      ++finished;
+      b->finished.push_back(it.slot);
+      ++*finished;
     }
   }
-  if (active_out) *active_out = nact - finished;
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dl_batch_set_lookahead(dl_batch* b, int32_t rounds) {
+  if (!b) return bfail(DL_EINVAL, "NULL batch");
+  if (rounds != 0 && rounds != 1) return bfail(DL_EINVAL, "look-ahead must be 0 or 1 rounds");
+  if (rounds == 0 && b->inflight.live) return bfail(DL_EINVAL, "a round is in flight: step until none is");
+  b->lookahead = rounds;
+  return DL_OK;
+}
+
+int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void* stream) {
+  if (!b) return bfail(DL_EINVAL, "NULL batch");
+  hipStream_t s = (hipStream_t)stream;
+  BHIP(hipSetDevice(b->device));
+  int finished = 0, rc = DL_OK;
+  Round next;
+  if ((rc = issue_round(b, s, next))) return rc;
+  if (b->lookahead == 0) {
+    rc = complete_round(b, next, &finished);
+  } else {
+    // wait for the round issued by the previous call while `next` runs
+    rc = complete_round(b, b->inflight, &finished);
+    b->inflight = std::move(next);
+  }
+  if (rc) return rc;
+  // pool memory fetched while an older round was in flight is free now
+  if (!b->inflight.live) {
+    for (auto& pr : b->retire) pool_free(b, pr.first, pr.second);
+    b->retire.clear();
+  }
+  int active = 0;
+  for (int i = 0; i < b->max_active; ++i) active += b->req[i].used && !b->req[i].done;
+  if (active_out) *active_out = active;
   if (finished_out) *finished_out = finished;
   return DL_OK;
 }
@@ -454,7 +562,10 @@ int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* 
     BHIP(hipStreamSynchronize(s));
   }
   if (ones_out) *ones_out = r.ones[r.iters];
-  pool_free(b, r.off, r.bytes);
+  if (b->inflight.live)
+    b->retire.emplace_back(r.off, r.bytes);  // the round in flight may still read it
+  else
+    pool_free(b, r.off, r.bytes);
   r = Req();
   return DL_OK;
 }

@@ -57,14 +57,15 @@ class StreamStats:
 
 
 def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool = False,
-               batch: Batch | None = None) -> tuple[StreamStats, dict]:
+               batch: Batch | None = None, lookahead: int = 0) -> tuple[StreamStats, dict]:
     """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
 
     make_input(req) returns the request's relation as a uint8 device tensor
-    (dense n x n) or as a device int32 [m, 2] edge list.
+    (dense n x n) or as a device int32 [m, 2] edge list.  lookahead = 1 lets
+    each round's host work overlap the next round on the device.
     Returns the statistics and, if keep_results, {rid: (model tensor, iters)}.
     """
-    b = batch or Batch(pool_bytes, max_active)
+    b = batch or Batch(pool_bytes, max_active, lookahead=lookahead)
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting: deque = deque()
     inflight = {}  # slot -> (req, admitted time)
@@ -80,10 +81,18 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
             req = waiting[0]
             kind = Batch.TC if req.kind == "tc" else Batch.SG
             rel = make_input(req)
-            if rel.dtype == torch.int32:
-                slot = b.dl_batch_submit_edges(kind, req.n, rel, req.rid)
-            else:
-                slot = b.dl_batch_submit(kind, rel, req.rid)
+
+            def submit():
+                if rel.dtype == torch.int32:
+                    return b.dl_batch_submit_edges(kind, req.n, rel, req.rid)
+                return b.dl_batch_submit(kind, rel, req.rid)
+
+            slot = submit()
+            if slot is None and not inflight:
+                # with look-ahead, memory of fetched requests returns to the
+                # pool once the round in flight completes
+                b.dl_batch_step()
+                slot = submit()
             if slot is None:
                 if not inflight:
                     raise RuntimeError(f"request {req.rid} (n={req.n}) does not fit an empty pool")

@@ -36,14 +36,16 @@ def _oracle(req):
     return oracle.tc_seminaive(a)[0] if req.kind == "tc" else oracle.sg_seminaive(a)[0]
 
 
-def test_mixed_stream_alone_vs_mix(dl):
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_mixed_stream_alone_vs_mix(dl, lookahead):
     from paper_1608_00139_amd.serve import run_stream
 
     reqs = dlgen.serving_stream(40, seed=5, rate=0.0, n_lo=64, n_hi=700)
     # pool for about a third of the stream: forces waits and continuous admission
     pool = sum(5 * ((r.n + 63) // 64 * 64) ** 2 for r in reqs) // 3
-    announce("serve mix", len(reqs), pool)
-    stats, results = run_stream(reqs, _make_input, pool_bytes=pool, max_active=64, keep_results=True)
+    announce("serve mix", len(reqs), pool, lookahead)
+    stats, results = run_stream(reqs, _make_input, pool_bytes=pool, max_active=64, keep_results=True,
+                                lookahead=lookahead)
     assert len(stats.completions) == len(reqs)
     assert stats.eagain > 0
     for r in reqs:
@@ -54,19 +56,26 @@ def test_mixed_stream_alone_vs_mix(dl):
         assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
 
 
-def test_submit_between_rounds(dl):
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_submit_between_rounds(dl, lookahead):
+    """Two new requests every other round into four slots, so finished slots
+    are fetched and reused while (with look-ahead) a round is in flight."""
     reqs = dlgen.serving_stream(12, seed=9, rate=0.0, n_lo=64, n_hi=400)
-    b = dl.Batch(pool_bytes=1 << 28, max_active=16)
+    b = dl.Batch(pool_bytes=1 << 28, max_active=4, lookahead=lookahead)
     done = {}
     queue = list(reqs)
-    announce("serve interleaved")
+    announce("serve interleaved", lookahead)
     rounds = 0
     while queue or len(done) < len(reqs):
-        if queue and rounds % 2 == 0:  # two new requests every other round
-            for r in queue[:2]:
+        if queue and rounds % 2 == 0:  # up to two new requests every other round
+            for _ in range(2):
+                if not queue:
+                    break
+                r = queue[0]
                 slot = b.dl_batch_submit(b.TC if r.kind == "tc" else b.SG, _make_input(r), r.rid)
-                assert slot is not None
-            queue = queue[2:]
+                if slot is None:
+                    break
+                queue = queue[1:]
         b.dl_batch_step()
         rounds += 1
         for tag, slot, iters in b.dl_batch_poll():
@@ -109,7 +118,8 @@ def test_edge_requests(dl):
         b.dl_batch_fetch(3)  # never used slot
 
 
-def test_edge_list_admission(dl):
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_edge_list_admission(dl, lookahead):
     """Requests admitted as device edge lists give the same models and
     iteration counts as dense admission and the oracle; repeated pairs count
     once, pairs outside [0, n) are skipped, an empty list is the empty relation."""
@@ -125,8 +135,9 @@ def test_edge_list_admission(dl):
         extra = [e[: min(len(e), 5)], np.array([[r.n, 0], [0, r.n], [-1, 3], [2, -5]], np.int32)]
         return torch.from_numpy(np.concatenate([e] + extra)).cuda()
 
-    announce("serve edges", len(reqs))
-    stats, results = run_stream(reqs, edges_of, pool_bytes=1 << 30, max_active=16, keep_results=True)
+    announce("serve edges", len(reqs), lookahead)
+    stats, results = run_stream(reqs, edges_of, pool_bytes=1 << 30, max_active=16, keep_results=True,
+                                lookahead=lookahead)
     _, dense = run_stream(reqs, _make_input, pool_bytes=1 << 30, max_active=16, keep_results=True)
     for r in reqs:
         got, iters = results[r.rid]
@@ -134,7 +145,7 @@ def test_edge_list_admission(dl):
         assert iters == dense[r.rid][1]
         assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
     # model sizes: ones[1] (the relation itself) counts distinct pairs
-    b = dl.Batch(pool_bytes=1 << 26, max_active=4)
+    b = dl.Batch(pool_bytes=1 << 26, max_active=4, lookahead=lookahead)
     n = 100
     e = np.array([[1, 2], [2, 3], [1, 2], [1, 2], [3, 1], [99, 0]], np.int32)
     slot = b.dl_batch_submit_edges(dl.Batch.TC, n, torch.from_numpy(e).cuda(), 7)
@@ -154,7 +165,8 @@ def test_edge_list_admission(dl):
     b.close()
 
 
-def test_grouped_admission_many_small(dl):
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_grouped_admission_many_small(dl, lookahead):
     """Forty edge-list requests admitted before one round (one grouped clear
     and scatter for all of them): sizes 1..90, empty lists, repeated and
     out-of-range pairs, lists that end inside a wave of the scatter; every
@@ -162,7 +174,7 @@ def test_grouped_admission_many_small(dl):
     import torch
 
     rng = np.random.default_rng(5)
-    b = dl.Batch(pool_bytes=1 << 28, max_active=64)
+    b = dl.Batch(pool_bytes=1 << 28, max_active=64, lookahead=lookahead)
     cases = {}
     for tag in range(40):
         n = int(rng.integers(1, 91))
@@ -179,7 +191,7 @@ def test_grouped_admission_many_small(dl):
         slot = b.dl_batch_submit_edges(kind, n, torch.from_numpy(e.reshape(-1, 2)).cuda(), tag)
         assert slot is not None
         cases[tag] = (kind, n, a)
-    announce("serve grouped admission", len(cases))
+    announce("serve grouped admission", len(cases), lookahead)
     fin = {}
     for _ in range(200):
         b.dl_batch_step()
@@ -205,7 +217,35 @@ def test_grouped_admission_many_small(dl):
     b.close()
 
 
-def test_large_requests_all_tile_sizes(dl):
+def test_lookahead_switch(dl):
+    """Look-ahead can be turned off only when no round is in flight; values
+    other than 0 and 1 are rejected."""
+    b = dl.Batch(pool_bytes=1 << 26, max_active=4)
+    lib = dl.load()
+    assert lib.dl_batch_set_lookahead(b._h, 2) == 1
+    assert lib.dl_batch_set_lookahead(b._h, 1) == 0
+    a = dev(np.eye(64, k=1, dtype=np.uint8))
+    slot = b.dl_batch_submit(b.TC, a, 0)
+    assert slot is not None
+    announce("serve lookahead switch")
+    b.dl_batch_step()  # round 1 in flight
+    assert lib.dl_batch_set_lookahead(b._h, 0) == 1
+    iters = None
+    for _ in range(20):
+        active, _ = b.dl_batch_step()
+        for tag, sl, it in b.dl_batch_poll():
+            iters = it
+            b.dl_batch_fetch(sl)
+        if active == 0 and iters is not None:
+            break
+    b.dl_batch_step()  # drains the round issued before the last completion
+    assert lib.dl_batch_set_lookahead(b._h, 0) == 0
+    assert iters == dl.dl_tc(a, method=dl.DL_TC_SQUARE)[1]
+    b.close()
+
+
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_large_requests_all_tile_sizes(dl, lookahead):
     """A mix spanning the three tile sizes (n up to 1600: 64, 128 and 256 x 256
     grouped tiles in one round), dense and edge-list admission, against the oracle."""
     import torch
@@ -218,9 +258,10 @@ def test_large_requests_all_tile_sizes(dl):
     def edges_of(r):
         return torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda()
 
-    announce("serve large", [r.n for r in reqs])
+    announce("serve large", [r.n for r in reqs], lookahead)
     for mk in (edges_of, _make_input):
-        stats, results = run_stream(reqs, mk, pool_bytes=1 << 31, max_active=8, keep_results=True)
+        stats, results = run_stream(reqs, mk, pool_bytes=1 << 31, max_active=8, keep_results=True,
+                                    lookahead=lookahead)
         for r in reqs:
             got, iters = results[r.rid]
             assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
