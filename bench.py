@@ -38,7 +38,8 @@ SEEDS = (0, 1, 2)
 INT8_PEAK_TOPS = 5000.0     # MI355X dense int8 MFMA, 5.0 POP/s
 # int8 step kernel of each tile configuration (dl_tune numbering)
 STEP_KERNELS = {0: "k_nt_dma<256,256,64,64,128,OpI8,2>", 1: "k_nt_step<128,128,64,64,64,OpI8,2,1>",
-                2: "k_nt_step<64,64,32,32,64,OpI8,2,1>", 3: "k_nt_dma<256,256,64,64,128,OpI8x32,2>"}
+                2: "k_nt_step<64,64,32,32,64,OpI8,2,1>", 3: "k_nt_dma<256,256,64,64,128,OpI8x32,2>",
+                4: "k_nt_small<OpI8>"}
 FP32_PEAK_TFLOPS = 157.3    # MI355X fp32 matrix
 
 

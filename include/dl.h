@@ -216,18 +216,21 @@ int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream);
  *   1  128 x 128 tile, 4 waves of 64 x 64, register-staged loads
  *   2  64 x 64 tile, 4 waves of 32 x 32, register-staged loads
  *   3  (DL_I8 only) configuration 0 on the 32 x 32 x 32 int8 MFMA
- * Without an entry the library picks by size (0 when (Np/256)^2 >= 256
- * tiles, 1 when (Np/128)^2 >= 128, else 2; Np = dl_padded_size).
+ *   4  32 x 32 tile, 4 waves of 16 x 16, the whole K extent of its rows in
+ *      LDS (operand rows of at most 2 KB: Np <= 2048 / element bytes)
+ * Without an entry the library picks by size (4 when Np = 256, or DL_F32
+ * at Np = 512; else 0 when (Np/256)^2 >= 256 tiles, 1 when (Np/128)^2 >=
+ * 128, else 2; Np = dl_padded_size).
  * dl_tune times one squaring-step launch of every configuration on a
  * pseudo-random 0/1 relation of size n in precision prec (a few ms each, on
  * `stream`, blocking), records the fastest for (prec, Np) in the context
  * (the size rule's choice when it is within 3% of the fastest) and
- * returns it in *cfg and its time per launch in *ms; cand_ms (host, one
- * double per configuration: 4 for DL_I8, 3 otherwise) receives every
- * candidate's time (any of the three may be NULL).
+ * returns it in *cfg and its time per launch in *ms; cand_ms (host, five
+ * doubles) receives every configuration's time, -1 for configurations that
+ * do not apply (any of the three may be NULL).
  * Entries apply to dl_tc*, dl_sg* and programs on this context.
  * dl_tune_set records cfg for (prec, Np) without timing (cfg = -1 removes
- * the entry); an unknown cfg is DL_EINVAL.  dl_tune_get copies up to cap
+ * the entry); a cfg that does not apply to (prec, n) is DL_EINVAL.  dl_tune_get copies up to cap
  * entries (precision, padded size, cfg, ms; ms = 0 for set entries) into the
  * host arrays (any may be NULL) and sets *count to the number of entries. */
 int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg, double* ms, double* cand_ms, void* stream);

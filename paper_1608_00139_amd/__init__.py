@@ -179,12 +179,11 @@ class Context:
         candidate's ms when ``candidates`` is true."""
         cfg = ctypes.c_int32()
         ms = ctypes.c_double()
-        cand = (ctypes.c_double * 4)()
+        cand = (ctypes.c_double * 5)()
         _check(load().dl_tune(self.handle, _prec(prec), int(n), ctypes.byref(cfg), ctypes.byref(ms), cand,
                               _stream_ptr(stream)))
         if candidates:
-            k = 4 if _prec(prec) == DL_I8 else 3
-            return int(cfg.value), float(ms.value), [float(cand[i]) for i in range(k)]
+            return int(cfg.value), float(ms.value), [float(cand[i]) for i in range(5)]
         return int(cfg.value), float(ms.value)
 
     def set_tuning(self, prec, n: int, cfg: int) -> None:

@@ -471,6 +471,132 @@ k_nt_step(NTParams p) {
                                              smem);
 }
 
+// ----------------------------------------------------------------- small relations
+// Whole-K tiles for small n: a 32 x 32 output tile per workgroup whose 32 rows
+// of X and 32 rows of Y are fetched completely into LDS at once
+// (global_load_lds_dwordx4, all issued before the first wait), so the product
+// waits on memory once instead of once per K slice.  Four waves each own a
+// 16 x 16 block of the tile and alternate two accumulators over K.  LDS: row
+// r (X rows 0..31, then Y rows) at r * ldb, its 16-byte chunk c stored at
+// c ^ (r & mask) (mask 15, or 7 when a row has fewer than 16 chunks), so the
+// 16 lanes that read one chunk of 16 rows hit distinct banks.  The epilogue
+// tile (32 x 48 bytes) follows the operands.
+constexpr int kSmallMaxLdb = 2048;  // largest row of operand bytes (LDS: 64 rows + epilogue)
+constexpr int kSmallEst = 48;
+
+size_t small_lds_bytes(int64_t ldb) { return (size_t)64 * ldb + 32 * kSmallEst; }
+
+template <class Op>
+__global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+  constexpr int NIB = elem_nibbles(Op::kPrec);
+  constexpr int KSTEP_CHUNKS = (64 / Op::FR) * Op::CPL;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
+  const int row0 = tm * 32, col0 = tn * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ldb = p.ld * NIB / 2;
+  const int kc = (int)(ldb / 16);
+  const int mask = (kc % 16 == 0) ? 15 : 7;
+  const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
+  const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
+  // 64 * kc chunks, 64 per DMA instruction: instruction i fills LDS chunks
+  // [64 i, 64 i + 64), lane L the chunk at position q = 64 i + L
+  for (int i = wave; i < kc; i += 4) {
+    const int q = 64 * i + lane;
+    const int r = q / kc, pos = q % kc;
+    const int c = pos ^ (r & mask);
+    const uint8_t* src = (r < 32 ? Xg + (int64_t)r * ldb : Yg + (int64_t)(r - 32) * ldb) + 16 * c;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)(smem + 1024 * i), 16, 0, 0);
+  }
+  __syncthreads();  // waits for every load of this workgroup (vmcnt(0)) and joins the waves
+
+  const int wm = wave >> 1, wn = wave & 1;
+  const int g = lane / Op::FR, rf = lane % Op::FR;
+  const int ra = 16 * wm + rf, rb = 32 + 16 * wn + rf;
+  const uint8_t* xa = smem + (int64_t)ra * ldb;
+  const uint8_t* yb = smem + (int64_t)rb * ldb;
+  typename Op::Acc acc0 = Op::zero(), acc1 = Op::zero();
+  const int ksteps = kc / KSTEP_CHUNKS;
+  for (int ks = 0; ks < ksteps; ks += 2) {
+    u32x4 a[Op::CPL], b[Op::CPL];
+#pragma unroll
+    for (int c = 0; c < Op::CPL; ++c) {
+      const int ch = ks * KSTEP_CHUNKS + g * Op::CPL + c;
+      a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
+      b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
+    }
+    acc0 = Op::mma(a, b, acc0);
+    if (ks + 1 < ksteps) {
+#pragma unroll
+      for (int c = 0; c < Op::CPL; ++c) {
+        const int ch = (ks + 1) * KSTEP_CHUNKS + g * Op::CPL + c;
+        a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
+        b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
+      }
+      acc1 = Op::mma(a, b, acc1);
+    }
+  }
+  // 0/1 block into the epilogue tile
+  uint8_t* et = smem + 64 * ldb;
+#pragma unroll
+  for (int v = 0; v < Op::NI; ++v) {
+    int r, c;
+    Op::coord(lane, v, r, c);
+    et[(16 * wm + r) * kSmallEst + 16 * wn + c] = (Op::nz(acc0, v) || Op::nz(acc1, v)) ? 1 : 0;
+  }
+  __syncthreads();
+  int cnt = 0;
+  uint8_t* outb = (uint8_t*)p.out;
+  if (tid < 64) {  // 32 rows x two 16-byte segments
+    const int r = tid >> 1, cs = tid & 1;
+    u32x4 v = *(const u32x4*)(et + r * kSmallEst + 16 * cs);
+    const int gr = row0 + r, gc = col0 + 16 * cs;
+    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
+      const int bq = gr - gc;
+      v[bq >> 2] |= 1u << (8 * (bq & 3));
+    }
+    cnt = popc16(v);
+    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * NIB / 2, v);
+    if (p.outT) *(u32x4*)(et + r * kSmallEst + 16 * cs) = v;
+  }
+  if (p.outT) {
+    __syncthreads();
+    if (tid < 64) {  // column c, rows 16 rs .. 16 rs + 15
+      const int c = tid & 31, rs = tid >> 5;
+      u32x4 v;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint8_t* e = et + (16 * rs + 4 * w) * kSmallEst + c;
+        v[w] = (unsigned)e[0] | ((unsigned)e[kSmallEst] << 8) | ((unsigned)e[2 * kSmallEst] << 16) |
+               ((unsigned)e[3 * kSmallEst] << 24);
+      }
+      store_bool16<Op::kPrec>((uint8_t*)p.outT + ((int64_t)(col0 + c) * p.ld + row0 + 16 * rs) * NIB / 2, v);
+    }
+  }
+  if (p.count && wave == 0) {
+    cnt = wave_sum(cnt);
+    if (lane == 0 && cnt) atomicAdd(p.ones + (p.step % kRing), (unsigned long long)cnt);
+  }
+}
+
+template <class Op>
+static hipError_t launch_small(const NTParams& p, hipStream_t s) {
+  const int64_t ldb = p.ld * elem_nibbles(Op::kPrec) / 2;
+  if (ldb > kSmallMaxLdb || ldb % 128 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nt_small<Op>, dim3(p.tiles_m * p.tiles_n), dim3(256), small_lds_bytes(ldb), s, p);
+  return hipGetLastError();
+}
+
+template <class Op>
+static hipError_t set_lds_attr_small() {
+  return hipFuncSetAttribute((const void*)k_nt_small<Op>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)small_lds_bytes(kSmallMaxLdb));
+}
+
 // ----------------------------------------------------------------- grouped step (serving)
 // One launch advances many independent fixpoints by one product each.  The
 // work list is the concatenation of every request's 64 x 64 output tiles;
@@ -937,6 +1063,7 @@ static hipError_t set_lds_attr_dma() {
 // cfg 1: 128x128 tile, 4 waves of 64x64, register-staged  (medium n)
 // cfg 2: 64x64 tile,   4 waves of 32x32, register-staged  (small n)
 // cfg 3: int8 only, cfg 0 with the 32 x 32 x 32 MFMA instead of 16 x 16 x 64
+// cfg 4: 32x32 tile, 4 waves of 16x16, whole K in LDS (rows of at most 2 KB)
 
 template <class Op, int BM, int BN, int WM, int WN, int KB, int SWZ = (KB == 64 ? 2 : 1), int PREF = 1>
 static hipError_t launch_cfg(const NTParams& p, hipStream_t s) {
@@ -973,6 +1100,7 @@ static hipError_t launch_op(int cfg, const NTParams& p, hipStream_t s) {
     case 3:
       if constexpr (Op::kPrec == P_I8) return launch_dma<OpI8x32, 256, 256, 64, 64, 128, 2>(p, s);
       return hipErrorInvalidValue;
+    case 4: return launch_small<Op>(p, s);
     case 1: return launch_cfg<Op, 128, 128, 64, 64, KSMALL>(p, s);
     default: return launch_cfg<Op, 64, 64, 32, 32, KSMALL>(p, s);
   }
@@ -985,6 +1113,7 @@ static hipError_t init_op() {
   if ((e = set_lds_attr_dma<Op, 256, 256, 64, 64, BigCfg<Op>::KB, BigCfg<Op>::NS>()) != hipSuccess) return e;
   if constexpr (Op::kPrec == P_I8)
     if ((e = set_lds_attr_dma<OpI8x32, 256, 256, 64, 64, 128, 2>()) != hipSuccess) return e;
+  if ((e = set_lds_attr_small<Op>()) != hipSuccess) return e;
   if ((e = set_lds_attr<Op, 128, 128, 64, 64, KSMALL>()) != hipSuccess) return e;
   return set_lds_attr<Op, 64, 64, 32, 32, KSMALL>();
 }
@@ -995,6 +1124,7 @@ static TileCfg cfg_of(int cfg) {
   switch (cfg) {
     case 0: { typedef typename BigCfg<Op>::K K; return {256, 256, BigCfg<Op>::KB, K::NT, K::LDS_BYTES}; }
     case 3: { typedef DmaKernel<256, 256, 64, 64, 128, OpI8x32, 2> K; return {256, 256, 128, K::NT, K::LDS_BYTES}; }
+    case 4: return {32, 32, kSmallMaxLdb, 256, small_lds_bytes(kSmallMaxLdb)};
     case 1: { typedef NTKernel<128, 128, 64, 64, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {128, 128, KSMALL, K::NT, K::LDS_BYTES}; }
     default: { typedef NTKernel<64, 64, 32, 32, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {64, 64, KSMALL, K::NT, K::LDS_BYTES}; }
   }
@@ -1043,11 +1173,24 @@ int64_t padded_size_for(int prec, int64_t n) {
   return n <= 0 ? 0 : ((n + q - 1) / q) * q;
 }
 
-int nt_config_count(int prec) { return prec == P_I8 ? 4 : 3; }
+int nt_config_count(int prec) {
+  (void)prec;
+  return 5;
+}
+
+bool nt_config_valid(int prec, int cfg, int64_t np) {
+  if (cfg < 0 || cfg >= nt_config_count(prec) || np <= 0 || np % 256) return false;
+  if (cfg == 3) return prec == P_I8;
+  if (cfg == 4) return np * elem_nibbles(prec) / 2 <= kSmallMaxLdb;
+  return true;
+}
 
 int choose_nt_config(int prec, int64_t np) {
-  (void)prec;
-  // enough workgroups to cover the 256 CUs before choosing the large tile
+  // whole-K 32 x 32 tiles at Np = 256 (and fp32 at 512, where each byte
+  // carries the most MFMA work); beyond that they move twice the operand
+  // bytes of 64 x 64 tiles and lose.  Then enough workgroups to cover the 256
+  // CUs before choosing the larger tiles (measured on MI355X).
+  if (np == 256 || (prec == P_F32 && np == 512)) return 4;
   if ((np / 256) * (np / 256) >= 256) return 0;
   if ((np / 128) * (np / 128) >= 128) return 1;
   return 2;

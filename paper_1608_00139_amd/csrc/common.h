@@ -97,7 +97,8 @@ struct TileCfg {
 hipError_t launch_nt_step(int prec, int cfg_id, const NTParams& p, hipStream_t s);
 TileCfg nt_config(int prec, int cfg_id);
 int choose_nt_config(int prec, int64_t n);
-int nt_config_count(int prec);  // valid cfg ids are 0 .. count - 1
+int nt_config_count(int prec);  // cfg ids are 0 .. count - 1
+bool nt_config_valid(int prec, int cfg, int64_t np);  // cfg usable at padded size np
 hipError_t launch_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed, hipStream_t s);
 int64_t padded_size_for(int prec, int64_t n);
 

@@ -594,9 +594,11 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
     return e;
   };
   int best = -1;
-  double best_ms = 0.0, def_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  double best_ms = 0.0, def_ms[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   hipError_t e = hipSuccess;
   for (int cfg = 0; cfg < nt_config_count(prec) && e == hipSuccess; ++cfg) {
+    if (cand_ms) cand_ms[cfg] = -1.0;
+    if (!nt_config_valid(prec, cfg, Np)) continue;
     const TileCfg tc = nt_config(prec, cfg);
     p.tiles_m = (int)(Np / tc.bm);
     p.tiles_n = (int)(Np / tc.bn);
@@ -640,8 +642,9 @@ int dl_tune_set(dl_ctx* ctx, int prec, int64_t n, int32_t cfg) {
   if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
   if (prec < P_I8 || prec > P_FP4) return fail(DL_EINVAL, "unknown precision");
   if (n <= 0 || n > (1 << 16)) return fail(DL_EINVAL, "n must be in 1 .. 65536");
-  if (cfg < -1 || cfg >= nt_config_count(prec)) return fail(DL_EINVAL, "no such tile configuration");
   const int64_t Np = padded_size_for(prec, n);
+  if (cfg < -1 || (cfg >= 0 && !nt_config_valid(prec, cfg, Np)))
+    return fail(DL_EINVAL, "no such tile configuration for this precision and size");
   for (size_t i = 0; i < ctx->tuned.size(); ++i)
     if (ctx->tuned[i].prec == prec && ctx->tuned[i].np == Np) {
       if (cfg < 0) {

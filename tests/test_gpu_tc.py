@@ -211,16 +211,18 @@ def test_forced_tile_configs(dl, prec):
     tiles of each configuration and end in a ragged tile; same generation on
     each configuration too."""
     ctx = dl.Context()
-    ncfg = 4 if prec == "i8" else 3
+    elem = {"i8": 1.0, "fp8": 1.0, "f32": 4.0, "bf16": 2.0, "fp4": 0.5}[prec]
     sizes = (300, 700, 2000) if prec == "i8" else (300, 700)
     for n in sizes:
+        np_ = (n + 255) // 256 * 256
+        cfgs = [0, 1, 2] + ([3] if prec == "i8" else []) + ([4] if np_ * elem <= 2048 else [])
         a = dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, 5))
         ref, _, it_plain, _ = oracle.tc_seminaive(a)
         _, hist = oracle.bfs(a, want_matrix=False)
         it_sq = oracle.square_schedule_from_hist(hist)[0]
         p = dlgen.to_dense(n, dlgen.forest_edges(n, 6))
         sg_ref, _, sg_it, _ = oracle.sg_seminaive(p)
-        for cfg in range(ncfg):
+        for cfg in cfgs:
             ctx.set_tuning(prec, n, cfg)
             for method, it_ref in ((dl.DL_TC_PLAIN, it_plain), (dl.DL_TC_SQUARE, it_sq)):
                 announce("forced cfg", prec, n, cfg, method)
@@ -242,15 +244,15 @@ def test_autotune(dl, tmp_path):
     n = 1000
     announce("autotune i8", n)
     cfg, ms = ctx.tune("i8", n)
-    assert 0 <= cfg < 4 and ms > 0
+    assert 0 <= cfg < 5 and ms > 0
     ent = ctx.tuning()
     assert ent == [{"prec": "i8", "np": 1024, "cfg": cfg, "ms": ms}]
     a = dlgen.to_dense(n, dlgen.er_edges(n, 3.0 / n, 9))
     r, _ = dl.dl_tc(dev(a), ctx=ctx)
     assert np.array_equal(host(r), oracle.tc_seminaive(a)[0])
     announce("autotune f32", 512)
-    cfg2, _ = ctx.tune("f32", 512)
-    assert 0 <= cfg2 < 3
+    cfg2, _, cand = ctx.tune("f32", 512, candidates=True)
+    assert 0 <= cfg2 < 5 and cand[3] == -1.0 and cand[cfg2] > 0  # the 32 x 32 x 32 form is int8 only
     path = str(tmp_path / "tuning.json")
     ctx.save_tuning(path)
     fresh = dl.Context()
@@ -260,7 +262,9 @@ def test_autotune(dl, tmp_path):
     with pytest.raises(dl.DLError):
         fresh.set_tuning("f32", 512, 3)  # the 32 x 32 x 32 configuration is int8 only
     with pytest.raises(dl.DLError):
-        fresh.set_tuning("i8", 512, 4)
+        fresh.set_tuning("i8", 512, 5)
+    with pytest.raises(dl.DLError):
+        fresh.set_tuning("f32", 1024, 4)  # 4 KB operand rows do not fit the whole-K tile
     fresh.set_tuning("i8", 1000, -1)
     assert [(e["prec"], e["np"]) for e in fresh.tuning()] == [("f32", 512)]
     ctx.close()
