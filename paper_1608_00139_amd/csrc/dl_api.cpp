@@ -734,8 +734,6 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
   }
   hipStream_t s = (hipStream_t)stream;
   std::string err;
-  const int64_t launches_before = ctx->launches[1];
-  (void)launches_before;
   double tmsum = 0.0;
   int64_t tcount = 0;
   hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, A, lda, A, lda, eps, R, ldr, X, ldx, s, ctx->timing,

@@ -42,7 +42,6 @@
 
 using namespace dl;
 
-extern "C" const char* dl_last_error(void);
 namespace dl {
 void set_last_error(const std::string& m);
 }
@@ -184,7 +183,6 @@ extern "C" {
 int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** out) {
   if (!out || pool_bytes == 0 || max_active <= 0 || max_active > kRing) return bfail(DL_EINVAL, "bad batch arguments");
   *out = nullptr;
-  (void)ctx;
   dl_batch* b = new (std::nothrow) dl_batch();
   if (!b) return bfail(DL_ENOMEM, "host allocation failed");
   b->ctx = ctx;
