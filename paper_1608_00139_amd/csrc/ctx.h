@@ -41,7 +41,9 @@ struct dl_ctx {
   bool timing = false;
   int64_t launches[3] = {0, 0, 0};
   double ms[3] = {0, 0, 0};
-  std::vector<EventPair> events;
+  std::vector<EventPair> events;    // pool of timing event pairs
+  size_t ev_cursor = 0;             // pairs [0, ev_cursor) hold launches not yet resolved
+  std::vector<std::pair<int, int>> pending;  // (class, pair index) to add to ms / launches
   dl::EpsWorkspace eps;  // workspace of the epsilon solve
   std::vector<TuneEntry> tuned;  // tile configurations that override the size rule
 };

@@ -99,39 +99,52 @@ int set_device(dl_ctx* c) {
   return DL_OK;
 }
 
-// Timed launch bracket (events only when timing is on).  Several brackets
-// may share the context's event pool through one `used` counter.
+// Timed launch bracket (events only when timing is on).  Brackets take pairs
+// from the context's pool in order; the launches that did work are queued in
+// ctx->pending and their times are read only when the statistics are asked
+// for (or the pool grows large), so a timed run does not wait on
+// elapsed-time queries between calls.
+constexpr size_t kMaxPendingEvents = 4096;
+
+void resolve_timing(dl_ctx* c) {
+  for (auto& m : c->pending) {
+    float t = 0.f;
+    const EventPair& ep = c->events[m.second];
+    if (hipEventSynchronize(ep.b) == hipSuccess && hipEventElapsedTime(&t, ep.a, ep.b) == hipSuccess) {
+      c->ms[m.first] += t;
+      c->launches[m.first] += 1;
+    }
+  }
+  c->pending.clear();
+  c->ev_cursor = 0;
+}
+
 struct Timer {
   dl_ctx* c;
   hipStream_t s;
-  size_t* used;
   std::vector<std::pair<int, int>> marks;  // (class, event index)
   int begin(int cls) {
     if (!c->timing) return -1;
-    if (*used >= c->events.size()) {
+    if (c->ev_cursor >= c->events.size()) {
       EventPair ep;
       if (hipEventCreate(&ep.a) != hipSuccess || hipEventCreate(&ep.b) != hipSuccess) return -1;
       c->events.push_back(ep);
     }
-    (void)hipEventRecord(c->events[*used].a, s);
-    marks.push_back({cls, (int)*used});
-    return (int)(*used)++;
+    const int idx = (int)c->ev_cursor++;
+    (void)hipEventRecord(c->events[idx].a, s);
+    marks.push_back({cls, idx});
+    return idx;
   }
   void end(int idx) {
     if (idx >= 0) (void)hipEventRecord(c->events[idx].b, s);
   }
-  // Accumulate the first `keep` marks of each class (launches that did work);
-  // call after the stream has been synchronised.
+  // Queue the first `keep` marks of class cls (launches that did work).
   void collect(int cls, int64_t keep) {
     int64_t taken = 0;
     for (auto& m : marks) {
       if (m.first != cls) continue;
       if (taken >= keep) break;
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, c->events[m.second].a, c->events[m.second].b) == hipSuccess) {
-        c->ms[cls] += t;
-        c->launches[cls] += 1;
-      }
+      c->pending.push_back(m);
       ++taken;
     }
   }
@@ -160,10 +173,10 @@ struct FixSlot {
 // on one stream and read one back while the device runs another's products.
 class Fix {
  public:
-  Fix(dl_ctx* c, const FixSlot& sl, size_t* ev_used, int mode, int64_t n, const uint8_t* A, int64_t lda,
-      uint8_t* R, int64_t ldr, int prec, int32_t max_steps, hipStream_t s)
+  Fix(dl_ctx* c, const FixSlot& sl, int mode, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
+      int prec, int32_t max_steps, hipStream_t s)
       : c_(c), sl_(sl), mode_(mode), n_(n), A_(A), lda_(lda), R_(R), ldr_(ldr), prec_(prec),
-        max_steps_(max_steps), s_(s), tm_{c, s, ev_used, {}} {}
+        max_steps_(max_steps), s_(s), tm_{c, s, {}} {}
 
   bool done() const { return done_; }
   const FixSlot& slot() const { return sl_; }
@@ -179,19 +192,27 @@ class Fix {
     uint8_t* op[4];
     for (int i = 0; i < 4; ++i) op[i] = sl_.ws + mat8 + i * matT;
     DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
+    // Addend: A (plain: A^T), or for int8 operands the previous iterate
+    // itself, which gives the same iterates: R^(k) = A + f(R^(k-1)) lies
+    // inside A + f(R^(k)) because f is monotone and R^(k-1) <= R^(k), and it
+    // contains A; so A + f(R^(k)) = R^(k) + f(R^(k)).  No separate addend is
+    // then written or read.
+    const bool self_add = prec_ == P_I8;
     if (mode_ == M_PLAIN) {
       // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
       Yop_ = op[0];
       S_[0] = op[1];
       S_[1] = op[2];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, ADD, Yop_, S_[1], sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, self_add ? nullptr : ADD, Yop_, S_[1],
+                           sl_.ring + 1, s_));
     } else if (mode_ == M_SQUARE) {
       // R^(1) = A with its transpose; addend A
       S_[0] = op[0];
       ST_[0] = op[1];
       S_[1] = op[2];
       ST_[1] = op[3];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, ADD, nullptr, S_[1], ST_[1], sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, self_add ? nullptr : ADD, nullptr, S_[1], ST_[1],
+                           sl_.ring + 1, s_));
     } else {
       // P in operand precision; S^(1) = I; intermediate T
       Yop_ = op[0];
@@ -202,7 +223,7 @@ class Fix {
       DL_HIP(launch_identity(prec_, S_[1], (int)Np_, (int)n_, s_));
       DL_HIP(launch_ring_set(sl_.ring, 1, (unsigned long long)n_, s_));
     }
-    add_ = ADD;
+    add_ = (mode_ != M_SG && !self_add) ? ADD : nullptr;
     const TileCfg tc = nt_config(prec_, cfg_);
     p_.ld = Np_;
     p_.Np = (int)Np_;
@@ -265,14 +286,15 @@ class Fix {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       NTParams& p = p_;
       p.step = (int)t;
+      const int8_t* add = add_ ? add_ : (const int8_t*)S_[prev];
       if (mode_ == M_PLAIN) {
-        p.X = S_[prev]; p.Y = Yop_; p.add = add_; p.add_identity = 0;
+        p.X = S_[prev]; p.Y = Yop_; p.add = add; p.add_identity = 0;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
         int ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
       } else if (mode_ == M_SQUARE) {
-        p.X = S_[prev]; p.Y = ST_[prev]; p.add = add_; p.add_identity = 0;
+        p.X = S_[prev]; p.Y = ST_[prev]; p.add = add; p.add_identity = 0;
         p.out = S_[cur]; p.outT = ST_[cur]; p.count = 1; p.check = 1;
         int ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
@@ -384,14 +406,13 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
     slots[i].h_conv = c->h_conv + 4 * i;
     slots[i].ev = c->slot_ev[i];
   }
-  size_t ev_used = 0;
   std::vector<Fix> jobs;
   jobs.reserve(count);
   std::vector<int> inflight;  // indices into jobs, oldest first
   int next = 0;
   auto launch = [&](const FixSlot& sl) -> int {
     const int g = next++;
-    jobs.emplace_back(c, sl, &ev_used, mode, n, A[g], lda, R[g], ldr, prec, max_steps, s);
+    jobs.emplace_back(c, sl, mode, n, A[g], lda, R[g], ldr, prec, max_steps, s);
     int r = jobs.back().start();
     if (r) return r;
     if (!jobs.back().done()) inflight.push_back(g);
@@ -431,6 +452,7 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
   for (int g = 0; g < count; ++g)
     jobs[g].finish(g == 0 ? ones_out : nullptr, steps_out ? steps_out + g : nullptr,
                    converged_out ? converged_out + g : nullptr);
+  if (c->ev_cursor > kMaxPendingEvents) resolve_timing(c);  // bound the event pool
   return DL_OK;
 }
 
@@ -870,6 +892,9 @@ int dl_set_timing(dl_ctx* ctx, int enable) {
 
 int dl_kernel_stats(dl_ctx* ctx, int cls, int64_t* launches, double* total_ms, int reset) {
   if (!ctx || cls < 0 || cls > 2) return fail(DL_EINVAL, "bad argument");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  resolve_timing(ctx);
   if (launches) *launches = ctx->launches[cls];
   if (total_ms) *total_ms = ctx->ms[cls];
   if (reset) {
