@@ -259,7 +259,7 @@ int64_t dl_padded_size(int64_t n, int kind, int prec);
 typedef struct dl_batch dl_batch;
 
 /* pool_bytes of device memory hold the admitted requests (a request of n
- * constants takes 5 Np^2 bytes for closure, 4 Np^2 for same generation,
+ * constants takes 4 Np^2 bytes, closure and same generation alike,
  * Np = n rounded up to 64 for n <= 256, to 128 up to 1024, else to 256); max_active (<= 4096)
  * bounds the requests admitted and not yet fetched. */
 int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, dl_batch** batch);

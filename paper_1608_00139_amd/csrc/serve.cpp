@@ -65,7 +65,7 @@ struct Req {
   int64_t n = 0, Np = 0;
   int64_t tag = 0;
   size_t off = 0, bytes = 0;  // pool region
-  uint8_t *add = nullptr, *b[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint8_t* b[4] = {nullptr, nullptr, nullptr, nullptr};
   int64_t computed = 0;     // highest iterate written on the device
   int phase = 0;            // same generation: 0 = next launch is T = [P S], 1 = S' = [I + T P^T]
   std::vector<int64_t> ones;  // model sizes known on the host, ones[k] for k <= known
@@ -163,7 +163,7 @@ int64_t pad_to(int64_t n, int t) { return (n + t - 1) / t * t; }
 
 size_t request_bytes(int kind, int64_t Np) {
   const size_t m = (size_t)Np * Np;
-  return kind == 0 ? 5 * m : 4 * m;  // closure: A + R, R^T (two each); SG: P, S (two), T
+  return 4 * m;  // closure: R, R^T (two each); SG: P, S (two), T
 }
 
 // Detect the first repeat in the known model sizes.
@@ -290,11 +290,11 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   r.gen = b->next_gen++;
   unsigned long long* adm = b->d_cnt + 2 * b->max_active + slot;
   if (kind == 0) {
-    r.add = base;
-    for (int i = 0; i < 4; ++i) r.b[i] = base + m * (1 + i);  // R0, R0T, R1, R1T
+    for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // R0, R0T, R1, R1T
     if (!deferred) BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
-    // addend A, R^(1) = A, R^(1)T = A^T
-    int rc = fill(n, Np, (int8_t*)r.add, (int8_t*)r.b[2], (int8_t*)r.b[3], adm);
+    // R^(1) = A and R^(1)T = A^T; each squaring step takes its previous
+    // iterate as the addend (R + R R = A + R R along the iteration)
+    int rc = fill(n, Np, (int8_t*)base, (int8_t*)r.b[2], (int8_t*)r.b[3], adm);
     if (rc) {
       pool_free(b, off, bytes);
       r = Req();
@@ -304,7 +304,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
     r.admit_count = true;
   } else {
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // P, S0, S1, T
-    int rc = fill(n, Np, (int8_t*)r.b[0], nullptr, nullptr, nullptr);
+    int rc = fill(n, Np, (int8_t*)base, (int8_t*)r.b[0], nullptr, nullptr);
     if (rc) {
       pool_free(b, off, bytes);
       r = Req();
@@ -327,12 +327,10 @@ int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t 
   if (!A || lda < n) return bfail(DL_EINVAL, "bad relation (A NULL or lda < n)");
   hipStream_t s = (hipStream_t)stream;
   return admit(b, kind, n, tag, slot_out, s, false,
-               [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
-                 // closure: M = addend, M2 = R^(1), MT = R^(1)T; same generation: M = P
-                 if (M2)
-                   BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, M, nullptr, M2, MT, ones, s));
-                 else
-                   BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, nullptr, nullptr, M, nullptr, nullptr, s));
+               [&](int64_t nn, int64_t Np, int8_t* base, int8_t* M, int8_t* MT, unsigned long long* ones) -> int {
+                 // closure: M = R^(1), MT = R^(1)T; same generation: M = P
+                 (void)base;
+                 BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, nullptr, nullptr, M, MT, ones, s));
                  return DL_OK;
                });
 }
@@ -342,16 +340,16 @@ int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges
   if (m < 0 || (m > 0 && !edges)) return bfail(DL_EINVAL, "bad edge list");
   (void)stream;  // the device work runs in the next dl_batch_step, on its stream
   return admit(b, kind, n, tag, slot_out, nullptr, true,
-               [&](int64_t nn, int64_t Np, int8_t* M, int8_t* M2, int8_t* MT, unsigned long long* ones) -> int {
+               [&](int64_t nn, int64_t Np, int8_t* base, int8_t* M, int8_t* MT, unsigned long long* ones) -> int {
                  const long long mb = (long long)Np * Np;
-                 // the request's buffers are contiguous from M: closure clears
-                 // A, R0, R0T, R1, R1T; same generation P, S0 and S1 = I
+                 // the request's buffers are contiguous from base: closure
+                 // clears R0, R0T, R1, R1T; same generation P, S0 and S1 = I
                  AdmitDesc a{};
-                 a.base = M;
-                 a.clear_units = (kind == 0 ? 5 : 3) * mb / 16;
+                 a.base = base;
+                 a.clear_units = (kind == 0 ? 4 : 3) * mb / 16;
                  a.ident_off = kind == 0 ? -1 : 2 * mb;
                  a.M = M;
-                 a.M2 = M2;
+                 a.M2 = nullptr;
                  a.MT = MT;
                  a.ones = ones;
                  a.edges = edges;
@@ -418,7 +416,7 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       g.X = r.b[2 * prev];
       g.Y = r.b[2 * prev + 1];
-      g.add = (const int8_t*)r.add;
+      g.add = (const int8_t*)r.b[2 * prev];  // the previous iterate is the addend
       g.out = r.b[2 * cur];
       g.outT = r.b[2 * cur + 1];
       g.cnt = cnt + i;
