@@ -223,6 +223,15 @@ class Fix {
       DL_HIP(launch_identity(prec_, S_[1], (int)Np_, (int)n_, s_));
       DL_HIP(launch_ring_set(sl_.ring, 1, (unsigned long long)n_, s_));
     }
+    // When the caller's R has exactly the layout of an int8 iterate (no
+    // padding, row stride Np, not transposed), it serves as iterate buffer
+    // S[0]: the confirming step writes an iterate equal to the one before
+    // it, so at a confirmed fixpoint both buffers hold the model and no
+    // emit is needed.
+    if (prec_ == P_I8 && mode_ != M_PLAIN && n_ == Np_ && ldr_ == Np_ && (uintptr_t)R_ % 256 == 0) {
+      S_[0] = R_;
+      r_is_s0_ = true;
+    }
     add_ = (mode_ != M_SG && !self_add) ? ADD : nullptr;
     const TileCfg tc = nt_config(prec_, cfg_);
     p_.ld = Np_;
@@ -336,7 +345,8 @@ class Fix {
       DL_HIP(hipMemset2DAsync(R_, (size_t)ldr_, 0, (size_t)n_, (size_t)n_, s_));
     } else {
       const void* src = S_[last & 1];
-      DL_HIP(launch_emit(prec_, src, (int)Np_, mode_ == M_PLAIN ? 1 : 0, (int)n_, R_, ldr_, s_));
+      const bool in_place = r_is_s0_ && (src == (const void*)R_ || (iters_ >= 2 && last == iters_));
+      if (!in_place) DL_HIP(launch_emit(prec_, src, (int)Np_, mode_ == M_PLAIN ? 1 : 0, (int)n_, R_, ldr_, s_));
     }
     done_ = true;
     return DL_OK;
@@ -366,6 +376,7 @@ class Fix {
   int64_t pending_ = 0;
   int chunk_ = 0;
   bool done_ = false;
+  bool r_is_s0_ = false;  // the caller's R is iterate buffer S[0]
 };
 
 // Runs `count` fixpoints of one size, mode and precision on stream s, with

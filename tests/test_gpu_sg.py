@@ -54,8 +54,10 @@ def test_precisions_random_relations(dl, prec):
         _check(dl, p, prec, f"er seed={seed}")
 
 
-def test_per_step_parity(dl):
-    n = 200
+@pytest.mark.parametrize("n", [200, 256])
+def test_per_step_parity(dl, n):
+    """Iterate k equals the oracle's (n = 256 is unpadded: the output buffer
+    doubles as an iterate buffer)."""
     p = dlgen.to_dense(n, dlgen.forest_edges(n, 4))
     _, ones_ref, iters_ref, _ = oracle.sg_seminaive(p)
     for k in range(0, iters_ref + 2):

@@ -71,9 +71,11 @@ def test_precisions(dl, prec, method):
 
 
 @pytest.mark.parametrize("method", [0, 1])
-def test_per_step_parity(dl, method):
-    """Iterate k of the GPU series equals the oracle's iterate k, with model sizes."""
-    n = 300
+@pytest.mark.parametrize("n", [300, 512])
+def test_per_step_parity(dl, method, n):
+    """Iterate k of the GPU series equals the oracle's iterate k, with model
+    sizes (n = 512 is unpadded: the output buffer doubles as an iterate
+    buffer, so unconverged and converged stops both read it back)."""
     a = dlgen.to_dense(n, dlgen.er_edges(n, 1.3 / n, 5))
     if method == dl.DL_TC_PLAIN:
         _, ones_ref, iters_ref, _ = oracle.tc_seminaive(a)
