@@ -746,7 +746,11 @@ int Runner::iterate(int L, const std::vector<int>& heads, const std::vector<Mat>
     ++k;
     P_HIP(hipMemsetAsync(g->dcnt, 0, (size_t)M * sizeof(unsigned long long), s));
     for (int h = 0; h < M; ++h) {
-      const int8_t* addp = A[h].M;
+      // the head's current iterate stands in for its non-recursive part A[h]:
+      // R^(k) = A + F(R^(k-1)) lies inside A + F(R^(k)) (F monotone, the
+      // iterates grow) and contains A, so A + F(R^(k)) = R^(k) + F(R^(k));
+      // for self-recursive terms it is also the product's left operand
+      const int8_t* addp = cur[h].M;
       const size_t q = ops[h].size();
       for (size_t i = 0; i < q; ++i) {
         const Op& o = ops[h][i];
