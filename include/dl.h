@@ -221,10 +221,11 @@ int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream);
  * Without an entry the library picks by size (4 when Np = 256, or DL_F32
  * at Np = 512; else 0 when (Np/256)^2 >= 256 tiles, 1 when (Np/128)^2 >=
  * 128, else 2; Np = dl_padded_size).
- * dl_tune times one squaring-step launch of every configuration on a
- * pseudo-random 0/1 relation of size n in precision prec (a few ms each, on
+ * dl_tune times squaring-step launches of every configuration on a
+ * pseudo-random 0/1 relation of size n in precision prec (five interleaved
+ * rounds of about 4 ms per configuration, median per configuration; on
  * `stream`, blocking), records the fastest for (prec, Np) in the context
- * (the size rule's choice when it is within 3% of the fastest) and
+ * (the size rule's choice when it is within 5% of the fastest) and
  * returns it in *cfg and its time per launch in *ms; cand_ms (host, five
  * doubles) receives every configuration's time, -1 for configurations that
  * do not apply (any of the three may be NULL).

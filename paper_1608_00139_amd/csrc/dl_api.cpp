@@ -599,7 +599,7 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
   NTParams p{};
   p.X = op[0];
   p.Y = op[1];
-  p.add = ADD;
+  p.add = prec == P_I8 ? (const int8_t*)op[0] : ADD;  // as the fixpoint driver's steps
   p.out = op[2];
   p.outT = op[3];
   p.ld = Np;
@@ -626,37 +626,59 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
     *ms = (double)t / reps;
     return e;
   };
-  int best = -1;
-  double best_ms = 0.0, def_ms[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // Candidates that apply; each is warmed up, then timed in kRounds rounds
+  // that visit the candidates in turn (so slow drifts of the clock affect
+  // all of them alike), about 4 ms of launches per candidate and round; a
+  // candidate's time is its median over the rounds.
+  constexpr int kRounds = 5;
+  std::vector<int> cands;
+  std::vector<int> reps;
+  std::vector<std::vector<double>> samples;
   hipError_t e = hipSuccess;
-  for (int cfg = 0; cfg < nt_config_count(prec) && e == hipSuccess; ++cfg) {
-    if (cand_ms) cand_ms[cfg] = -1.0;
-    if (!nt_config_valid(prec, cfg, Np)) continue;
+  auto set_tiles = [&](int cfg) {
     const TileCfg tc = nt_config(prec, cfg);
     p.tiles_m = (int)(Np / tc.bm);
     p.tiles_n = (int)(Np / tc.bn);
-    double first = 0.0, ms = 0.0;
+  };
+  for (int cfg = 0; cfg < nt_config_count(prec) && e == hipSuccess; ++cfg) {
+    if (cand_ms) cand_ms[cfg] = -1.0;
+    if (!nt_config_valid(prec, cfg, Np)) continue;
+    set_tiles(cfg);
+    double first = 0.0;
     if ((e = timed(cfg, 1, &first)) != hipSuccess) break;  // warm-up (code load, clocks)
     if ((e = timed(cfg, 1, &first)) != hipSuccess) break;
-    // about 5 ms of launches per candidate, 3 .. 50 of them
-    const int reps = (int)std::min(50.0, std::max(3.0, 5.0 / std::max(first, 1e-3)));
-    if ((e = timed(cfg, reps, &ms)) != hipSuccess) break;
-    if (cand_ms) cand_ms[cfg] = ms;
-    def_ms[cfg] = ms;
-    if (best < 0 || ms < best_ms) {
-      best = cfg;
-      best_ms = ms;
-    }
+    cands.push_back(cfg);
+    reps.push_back((int)std::min(40.0, std::max(2.0, 4.0 / std::max(first, 1e-3))));
+    samples.emplace_back();
   }
+  for (int round = 0; round < kRounds && e == hipSuccess; ++round)
+    for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+      set_tiles(cands[i]);
+      double ms = 0.0;
+      if ((e = timed(cands[i], reps[i], &ms)) == hipSuccess) samples[i].push_back(ms);
+    }
   (void)hipEventDestroy(ea);
   (void)hipEventDestroy(eb);
   if (e != hipSuccess) return hip_fail(e, "autotune launches");
+  int best = -1;
+  double best_ms = 0.0, cfg_ms[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (size_t i = 0; i < cands.size(); ++i) {
+    std::vector<double>& v = samples[i];
+    std::sort(v.begin(), v.end());
+    const double ms = v[v.size() / 2];
+    cfg_ms[cands[i]] = ms;
+    if (cand_ms) cand_ms[cands[i]] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = cands[i];
+      best_ms = ms;
+    }
+  }
   // keep the size rule's choice unless another configuration beats it by
-  // more than 3% (timing noise would otherwise flip near-ties between runs)
+  // more than 5% (run-to-run noise would otherwise flip near-ties)
   const int def = choose_nt_config(prec, Np);
-  if (def != best && def_ms[def] <= 1.03 * best_ms) {
+  if (def != best && cfg_ms[def] > 0.0 && cfg_ms[def] <= 1.05 * best_ms) {
     best = def;
-    best_ms = def_ms[def];
+    best_ms = cfg_ms[def];
   }
   bool found = false;
   for (auto& t : ctx->tuned)
