@@ -497,25 +497,34 @@ def run_serving(dl, torch, count: int, seed: int = 0):
             return edges[offs[r.rid]:offs[r.rid + 1]]
         return make_input
 
+    # grouped-step tile sizes from the library's autotuner (one batch, kept
+    # for the runs below)
+    tb = dl.Batch(1 << 20, 4)
+    tiles = tb.tune()
+    tb.close()
+    log("serving tiles: " + ", ".join(f"{e['n']}:{e['tile']}" for e in tiles))
+
     burst_n = min(count, 2000)
     burst = dlgen.serving_stream(burst_n, seed, rate=0.0)
     log(f"serving: closed-loop burst of {burst_n}")
     mk = prepare(burst)
     warm = dlgen.serving_stream(64, seed + 1, rate=0.0)
-    run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512, lookahead=1)
-    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512, lookahead=1)
+    run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
     sat = sb.summary()
     rate = 0.8 * sat["req_per_s"]
     stream = dlgen.serving_stream(count, seed, rate=rate)
     log(f"serving: Poisson stream of {count} at {rate:.0f} req/s")
     mk = prepare(stream)
-    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512, lookahead=1)
+    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
     ops = 0.0
     for c in st.completions:
         per_step = 2.0 if c.kind == 1 else 1.0
         ops += per_step * 2.0 * ((c.n + 63) // 64 * 64) ** 3 * (c.iters - 1)
     out = st.summary()
     out.update({"offered_rate": round(rate, 1), "saturation": sat,
+                "tiles": [{"n": e["n"], "tile": e["tile"], "us_per_product_64_128_256": [round(x * 1e3, 2) for x in e["ms"]]}
+                          for e in tiles],
                 "eff_tops_padded": round(ops / st.wall / 1e12, 2),
                 "workload": f"{count} requests, 70% TC (ER p=3/n) / 30% SG (forest), n log-uniform [64, 2048], "
                             f"Poisson arrivals at 0.8x the closed-loop saturation rate, int8 grouped steps, "

@@ -312,6 +312,26 @@ int dl_batch_poll(dl_batch* batch, int64_t* tags, int32_t* slots, int32_t* iters
  * NULL), and free the slot and its pool memory. */
 int dl_batch_fetch(dl_batch* batch, int32_t slot, uint8_t* R, int64_t ldr, int64_t* ones, void* stream);
 
+/* Tile autotuner of the grouped step (the output tile size of each request's
+ * products).  For each size n of `sizes` (host int64 array of k ascending
+ * sizes; NULL / k = 0 for 96, 128, 192, 256, 384, 512, 768, 1024, 1536,
+ * 2048) it times grouped squaring launches over the same pseudo-random
+ * requests of n constants (1 to 256 of them, about eight 2048-sized
+ * products of work) at each tile size 64, 128 and 256 (three interleaved
+ * rounds, median), and records the fastest -- the built-in choice when it
+ * is within 5% -- in the batch's tile table: a request of n constants then
+ * takes the choice of the smallest tabled size >= n (the built-in rule above
+ * the largest).  tiles (host int32[k]) and ms (host double[3 k]: time per
+ * request-product for tiles 64, 128, 256) may be NULL.  Temporary device
+ * memory of up to a few hundred MB is allocated outside the pool and freed;
+ * the call blocks on `stream` and leaves admitted requests untouched (their
+ * tile was fixed at admission).
+ * dl_batch_set_tiles sets the table directly (sizes ascending, tiles 64, 128
+ * or 256; k = 0 restores the built-in rule: 64 up to n = 256, 128 up to
+ * 1024, else 256). */
+int dl_batch_tune(dl_batch* batch, const int64_t* sizes, int32_t k, int32_t* tiles, double* ms, void* stream);
+int dl_batch_set_tiles(dl_batch* batch, const int64_t* sizes, const int32_t* tiles, int32_t k);
+
 /* Occupancy: running requests, used slots, free pool bytes. */
 int dl_batch_info(dl_batch* batch, int32_t* active, int32_t* used_slots, size_t* pool_free_bytes);
 

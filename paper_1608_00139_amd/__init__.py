@@ -85,6 +85,8 @@ def load() -> ctypes.CDLL:
         "dl_batch_submit_edges": ([vp, ctypes.c_int, i64, vp, i64, i64, pi32, vp], ctypes.c_int),
         "dl_batch_step": ([vp, pi32, pi32, vp], ctypes.c_int),
         "dl_batch_set_lookahead": ([vp, i32], ctypes.c_int),
+        "dl_batch_tune": ([vp, pi64, i32, pi32, ctypes.POINTER(dbl), vp], ctypes.c_int),
+        "dl_batch_set_tiles": ([vp, pi64, pi32, i32], ctypes.c_int),
         "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
         "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
         "dl_batch_info": ([vp, pi32, pi32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -582,6 +584,26 @@ class Batch:
         # the library reads the edges in the next dl_batch_step: keep them alive
         self._pending_edges.append(edges)
         return int(slot.value)
+
+    def tune(self, sizes: list | None = None) -> list[dict]:
+        """Time the grouped step at each tile size for each request size and
+        keep the fastest per size (dl_batch_tune); returns one entry per
+        size: n, tile, ms per request-product for tiles 64 / 128 / 256."""
+        k = len(sizes) if sizes else 10
+        arr = (ctypes.c_int64 * k)(*sizes) if sizes else None
+        tiles = (ctypes.c_int32 * k)()
+        ms = (ctypes.c_double * (3 * k))()
+        _check(load().dl_batch_tune(self._h, arr, len(sizes) if sizes else 0, tiles, ms, _stream_ptr(self.stream)))
+        got = list(sizes) if sizes else [96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+        return [{"n": got[i], "tile": int(tiles[i]), "ms": [float(ms[3 * i + j]) for j in range(3)]}
+                for i in range(k)]
+
+    def set_tiles(self, table: list) -> None:
+        """Tile table as from tune(): entries with "n" (ascending) and "tile"."""
+        k = len(table)
+        ns = (ctypes.c_int64 * max(k, 1))(*[int(e["n"]) for e in table])
+        ts = (ctypes.c_int32 * max(k, 1))(*[int(e["tile"]) for e in table])
+        _check(load().dl_batch_set_tiles(self._h, ns, ts, k))
 
     def dl_batch_step(self) -> tuple[int, int]:
         active = ctypes.c_int32()

@@ -111,6 +111,9 @@ struct dl_batch {
   AdmitDesc* h_adm = nullptr;   // pinned host copy
   hipEvent_t ev[2] = {nullptr, nullptr};  // end of each set's read-back
   std::vector<AdmitDesc> pend;  // edge-list requests admitted since the last round
+  // tile table: requests with n <= tile_n[i] (the first such i) use tile_t[i]
+  std::vector<int64_t> tile_n;
+  std::vector<int> tile_t;
   int lookahead = 0;
   int64_t rounds_issued = 0;
   Round inflight;               // issued, not yet read (look-ahead only)
@@ -123,6 +126,17 @@ struct dl_batch {
 };
 
 namespace {
+
+// Output tiles by request size: 64 x 64 up to n = 256, 128 x 128 up to
+// n = 1024, 256 x 256 (the direct-to-LDS kernel) above, unless the batch's
+// tile table (dl_batch_tune / dl_batch_set_tiles) says otherwise.
+int default_tile(int64_t n) { return n <= 256 ? 64 : (n <= 1024 ? 128 : 256); }
+
+int tile_for(const dl_batch* b, int64_t n) {
+  for (size_t i = 0; i < b->tile_n.size(); ++i)
+    if (n <= b->tile_n[i]) return b->tile_t[i];
+  return default_tile(n);
+}
 
 bool pool_alloc(dl_batch* b, size_t bytes, size_t* off) {
   for (auto it = b->free_list.begin(); it != b->free_list.end(); ++it) {
@@ -154,9 +168,6 @@ void pool_free(dl_batch* b, size_t off, size_t bytes) {
   }
 }
 
-// Output tiles by request size: 64 x 64 up to n = 256, 128 x 128 up to
-// n = 1024, 256 x 256 (the direct-to-LDS kernel) above.
-int tile_for(int64_t n) { return n <= 256 ? 64 : (n <= 1024 ? 128 : 256); }
 int list_of(int tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : 2); }
 constexpr int kLists = 3;
 int64_t pad_to(int64_t n, int t) { return (n + t - 1) / t * t; }
@@ -268,7 +279,7 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
       break;
     }
   if (slot < 0) return bfail(DL_EAGAIN, "no free request slot");
-  const int tile = tile_for(n);
+  const int tile = tile_for(b, n);
   const int64_t Np = pad_to(n, tile);
   const size_t bytes = request_bytes(kind, Np);
   size_t off = 0;
@@ -563,6 +574,138 @@ int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* 
   else
     pool_free(b, r.off, r.bytes);
   r = Req();
+  return DL_OK;
+}
+
+int dl_batch_set_tiles(dl_batch* b, const int64_t* sizes, const int32_t* tiles, int32_t k) {
+  if (!b || k < 0 || (k > 0 && (!sizes || !tiles))) return bfail(DL_EINVAL, "bad tile table");
+  for (int i = 0; i < k; ++i) {
+    if (sizes[i] <= 0 || (i > 0 && sizes[i] <= sizes[i - 1])) return bfail(DL_EINVAL, "sizes must ascend");
+    if (tiles[i] != 64 && tiles[i] != 128 && tiles[i] != 256) return bfail(DL_EINVAL, "tiles are 64, 128 or 256");
+  }
+  b->tile_n.assign(sizes, sizes + k);
+  b->tile_t.assign(tiles, tiles + k);
+  return DL_OK;
+}
+
+int dl_batch_tune(dl_batch* b, const int64_t* sizes_in, int32_t k, int32_t* tiles_out, double* ms_out,
+                  void* stream) {
+  static const int64_t kSizes[] = {96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+  if (!b || k < 0 || (k > 0 && !sizes_in)) return bfail(DL_EINVAL, "bad size list");
+  const int64_t* sizes = k > 0 ? sizes_in : kSizes;
+  const int ns = k > 0 ? k : (int)(sizeof kSizes / sizeof kSizes[0]);
+  for (int i = 0; i < ns; ++i)
+    if (sizes[i] <= 0 || sizes[i] > 16384 || (i > 0 && sizes[i] <= sizes[i - 1]))
+      return bfail(DL_EINVAL, "sizes must ascend within 1 .. 16384");
+  hipStream_t s = (hipStream_t)stream;
+  BHIP(hipSetDevice(b->device));
+  static const int kTiles[3] = {64, 128, 256};
+  constexpr int kRounds = 3;
+  std::vector<int32_t> choice(ns);
+  std::vector<double> times((size_t)3 * ns, -1.0);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  BHIP(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    (void)hipEventDestroy(ea);
+    return bfail(DL_EHIP, "hipEventCreate");
+  }
+  uint8_t* buf = nullptr;
+  size_t buf_bytes = 0;
+  int rc = DL_OK;
+  for (int si = 0; si < ns && rc == DL_OK; ++si) {
+    const int64_t n = sizes[si];
+    // the same requests for every tile size: about eight 2048-sized
+    // products of work, 1 .. 256 requests
+    const double want = 8.0 * 2048.0 * 2048.0 * 2048.0 / ((double)n * n * n);
+    const int count = (int)std::min(256.0, std::max(1.0, std::floor(want)));
+    const int64_t npmax = pad_to(n, 256);
+    const size_t req = 4 * (size_t)npmax * npmax;
+    const size_t need = (size_t)count * req + (size_t)count * sizeof(GroupDesc) + 256;
+    if (need > buf_bytes) {
+      if (buf) (void)hipFree(buf);
+      buf = nullptr;
+      buf_bytes = 0;
+      if (hipMalloc(&buf, need) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = bfail(DL_ENOMEM, "temporary memory for the tile autotuner");
+        break;
+      }
+      buf_bytes = need;
+    }
+    GroupDesc* ddesc = (GroupDesc*)(buf + (size_t)count * req);
+    unsigned long long* dcnt = (unsigned long long*)(ddesc + count);
+    std::vector<double> med(3, -1.0);
+    std::vector<std::vector<double>> samp(3);
+    std::vector<GroupDesc> h((size_t)count);
+    for (int round = 0; round <= kRounds && rc == DL_OK; ++round) {  // round 0 warms up
+      for (int ti = 0; ti < 3 && rc == DL_OK; ++ti) {
+        const int T = kTiles[ti];
+        const int64_t Np = pad_to(n, T);
+        const size_t m = (size_t)Np * Np;
+        int tiles = 0;
+        for (int q = 0; q < count; ++q) {
+          uint8_t* base = buf + (size_t)q * req;
+          GroupDesc& g = h[q];
+          std::memset(&g, 0, sizeof g);
+          g.X = base;
+          g.Y = base + m;
+          g.add = (const int8_t*)base;
+          g.out = base + 2 * m;
+          g.outT = base + 3 * m;
+          g.cnt = dcnt;
+          g.Np = (int)Np;
+          g.n_valid = (int)n;
+          g.tile_start = tiles;
+          tiles += (int)((Np / T) * (Np / T));
+          if (round == 0) {  // pseudo-random 0/1 operands
+            hipError_t e = launch_hash_bool(base, Np, (int)n, (int)Np, 11u + (unsigned)q, s);
+            if (e == hipSuccess) e = launch_hash_bool(base + m, Np, (int)n, (int)Np, 977u + (unsigned)q, s);
+            if (e != hipSuccess) {
+              rc = bfail(DL_EHIP, "autotuner operands");
+              break;
+            }
+          }
+        }
+        if (rc) break;
+        hipError_t e = hipMemcpyAsync(ddesc, h.data(), sizeof(GroupDesc) * count, hipMemcpyHostToDevice, s);
+        const int grid = std::min(T == 256 ? b->cus : b->grid, tiles);
+        const int reps = round == 0 ? 1 : 3;
+        if (e == hipSuccess) e = hipEventRecord(ea, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_group_step(T, ddesc, count, tiles, grid, s);
+        if (e == hipSuccess) e = hipEventRecord(eb, s);
+        if (e == hipSuccess) e = hipEventSynchronize(eb);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, ea, eb);
+        if (e != hipSuccess) {
+          rc = bfail(DL_EHIP, std::string("autotuner launches: ") + hipGetErrorString(e));
+          break;
+        }
+        if (round > 0) samp[ti].push_back((double)t / reps / count);  // ms per request-product
+      }
+    }
+    if (rc) break;
+    int best = -1;
+    for (int ti = 0; ti < 3; ++ti) {
+      std::sort(samp[ti].begin(), samp[ti].end());
+      med[ti] = samp[ti][samp[ti].size() / 2];
+      times[(size_t)3 * si + ti] = med[ti];
+      if (best < 0 || med[ti] < med[best]) best = ti;
+    }
+    // keep the built-in choice unless another tile beats it by more than 5%
+    const int def = list_of(default_tile(n));
+    choice[si] = med[def] <= 1.05 * med[best] ? kTiles[def] : kTiles[best];
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (buf) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+  }
+  if (rc) return rc;
+  b->tile_n.assign(sizes, sizes + ns);
+  b->tile_t.assign(choice.begin(), choice.end());
+  if (tiles_out) std::copy(choice.begin(), choice.end(), tiles_out);
+  if (ms_out) std::copy(times.begin(), times.end(), ms_out);
   return DL_OK;
 }
 

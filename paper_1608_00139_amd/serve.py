@@ -57,15 +57,18 @@ class StreamStats:
 
 
 def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool = False,
-               batch: Batch | None = None, lookahead: int = 0) -> tuple[StreamStats, dict]:
+               batch: Batch | None = None, lookahead: int = 0, tiles: list | None = None) -> tuple[StreamStats, dict]:
     """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
 
     make_input(req) returns the request's relation as a uint8 device tensor
     (dense n x n) or as a device int32 [m, 2] edge list.  lookahead = 1 lets
-    each round's host work overlap the next round on the device.
+    each round's host work overlap the next round on the device.  tiles is a
+    tile table (Batch.tune's result) for a batch this call creates.
     Returns the statistics and, if keep_results, {rid: (model tensor, iters)}.
     """
     b = batch or Batch(pool_bytes, max_active, lookahead=lookahead)
+    if tiles is not None and batch is None:
+        b.set_tiles(tiles)
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting: deque = deque()
     inflight = {}  # slot -> (req, admitted time)

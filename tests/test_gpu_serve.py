@@ -217,6 +217,59 @@ def test_grouped_admission_many_small(dl, lookahead):
     b.close()
 
 
+@pytest.mark.parametrize("tile", [64, 256])
+def test_forced_tile_table(dl, tile):
+    """Every request on one tile size (64 x 64 tiles for sizes up to 1500,
+    or 256 x 256 tiles for requests of 60 constants) gives the oracle's model
+    and the single-call iteration count."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    reqs = dlgen.serving_stream(16, seed=31, rate=0.0, n_lo=60, n_hi=1500)
+
+    def edges_of(r):
+        return torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda()
+
+    announce("serve forced tiles", tile)
+    stats, results = run_stream(reqs, edges_of, pool_bytes=1 << 31, max_active=16, keep_results=True,
+                                lookahead=1, tiles=[{"n": 16384, "tile": tile}])
+    for r in reqs:
+        got, iters = results[r.rid]
+        assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n, tile)
+        assert iters == _alone(dl, r)[1], (r.rid, r.kind, r.n, tile)
+
+
+def test_batch_tune(dl):
+    """The grouped-step autotuner returns a tile size and three positive
+    times per size, installs its table, and a stream afterwards is still
+    exact; bad tables are rejected."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    b = dl.Batch(pool_bytes=1 << 30, max_active=16, lookahead=1)
+    announce("serve tune")
+    table = b.tune([100, 700, 1500])
+    assert [e["n"] for e in table] == [100, 700, 1500]
+    for e in table:
+        assert e["tile"] in (64, 128, 256) and all(x > 0 for x in e["ms"])
+    reqs = dlgen.serving_stream(10, seed=33, rate=0.0, n_lo=64, n_hi=1500)
+
+    def edges_of(r):
+        return torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda()
+
+    stats, results = run_stream(reqs, edges_of, pool_bytes=0, keep_results=True, batch=b)
+    for r in reqs:
+        assert np.array_equal(host(results[r.rid][0]), _oracle(r)), (r.rid, r.kind, r.n)
+    with pytest.raises(dl.DLError):
+        b.set_tiles([{"n": 500, "tile": 64}, {"n": 400, "tile": 128}])  # sizes must ascend
+    with pytest.raises(dl.DLError):
+        b.set_tiles([{"n": 500, "tile": 96}])
+    b.set_tiles([])  # back to the built-in rule
+    b.close()
+
+
 def test_lookahead_switch(dl):
     """Look-ahead can be turned off only when no round is in flight; values
     other than 0 and 1 are rejected."""
