@@ -13,6 +13,9 @@
  *     two-sided X = eps (Q + B X C) equations, the same-generation one
  *   - whole programs, layered by strongly connected components (Sec. 5),
  *     with stratified negation (Sec. 8)
+ * around them: several closures per call (dl_tc_batch), continuous batching
+ * of many small requests (dl_batch_*), and tile autotuners for the product
+ * step (dl_tune*) and for the grouped serving step (dl_batch_tune).
  *
  * Matrix conventions (all entry points):
  *   - Every matrix is n x n, row-major, 0-based: element (i, j) at p[i*ld + j],
@@ -91,7 +94,8 @@ int dl_destroy(dl_ctx* ctx);
 /* Transitive closure of R1 = A (Sec. 3, Theorem 1 gives the same model).
  *   n      number of constants
  *   A      device uint8 [n x lda], nonzero = r1(e_i, e_j)
- *   R      device uint8 [n x ldr], receives the 0/1 least model of r2
+ *   R      device uint8 [n x ldr], receives the 0/1 least model of r2 (it
+ *          may also hold intermediate iterates while the call runs)
  *   method dl_tc_method, prec dl_prec
  *   iters  host int32, see above. */
 int dl_tc(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
