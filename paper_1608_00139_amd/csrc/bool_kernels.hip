@@ -1204,16 +1204,18 @@ template <int PREC>
 __global__ void __launch_bounds__(256)
 k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, int8_t* AT8,
          uint8_t* Aop, uint8_t* ATop, unsigned long long* ones_slot) {
-  // one 64-row strip per blockIdx.y; the strip's 64 x 64 tiles are shared out
-  // over gridDim.x workgroups, so the ones counter takes few atomics
-  __shared__ uint8_t tile[64][64 + 16];
+  // one 128-row strip per blockIdx.y; the strip's 128 x 128 tiles are shared
+  // out over gridDim.x workgroups, so the ones counter takes few atomics.
+  // Each wave reads and writes whole 128-byte row segments: thread t takes
+  // rows t / 8 + 32 k (k < 4), bytes 16 (t % 8) .. + 15 of the tile.  Np is
+  // a multiple of 64: the last strip and tile may be 64 wide (parts beyond Np
+  // are not written).
+  __shared__ uint8_t tile[128][128 + 16];
   const int bi = blockIdx.y;
   const int tid = threadIdx.x;
-  const int r = tid >> 2, c0 = (tid & 3) * 16;
-  const int gi = bi * 64 + r;
-  int cnt = 0;
-  for (int bj = blockIdx.x; bj < Np / 64; bj += gridDim.x) {
-    const int gj0 = bj * 64 + c0;
+  const int r0 = tid >> 3, c0 = (tid & 7) * 16;
+  const int nb = (Np + 127) / 128;
+  auto load = [&](int gi, int gj0) -> u32x4 {
     u32x4 v = {0u, 0u, 0u, 0u};
     if (gi < n) {
       const uint8_t* src = A + (int64_t)gi * lda + gj0;
@@ -1232,21 +1234,40 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
         }
       }
     }
-    const int64_t off = (int64_t)gi * Np + bj * 64 + c0;
-    if (A8) *(u32x4*)(A8 + off) = v;
-    if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v);
-    cnt += popc16(v);
-    if (AT8 || ATop) {
-      *(u32x4*)&tile[r][c0] = v;
-      __syncthreads();
-      u32x4 t;
+    return v;
+  };
+  int cnt = 0;
+  for (int bj = blockIdx.x; bj < nb; bj += gridDim.x) {
+    u32x4 v[4];
 #pragma unroll
-      for (int w = 0; w < 4; ++w)
-        t[w] = (unsigned)tile[c0 + 4 * w][r] | ((unsigned)tile[c0 + 4 * w + 1][r] << 8) |
-               ((unsigned)tile[c0 + 4 * w + 2][r] << 16) | ((unsigned)tile[c0 + 4 * w + 3][r] << 24);
-      const int64_t toff = (int64_t)(bj * 64 + r) * Np + bi * 64 + c0;
-      if (AT8) *(u32x4*)(AT8 + toff) = t;
-      if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
+    for (int k = 0; k < 4; ++k) v[k] = load(bi * 128 + r0 + 32 * k, bj * 128 + c0);
+    const bool col_in = bj * 128 + c0 < Np;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = r0 + 32 * k;
+      if (col_in && bi * 128 + r < Np) {
+        const int64_t off = (int64_t)(bi * 128 + r) * Np + bj * 128 + c0;
+        if (A8) *(u32x4*)(A8 + off) = v[k];
+        if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v[k]);
+      }
+      cnt += popc16(v[k]);  // zero outside [0, n) anyway
+      if (AT8 || ATop) *(u32x4*)&tile[r][c0] = v[k];
+    }
+    if (AT8 || ATop) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int rr = r0 + 32 * k;  // row of the transposed tile = column of the tile
+        u32x4 t;
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+          t[w] = (unsigned)tile[c0 + 4 * w][rr] | ((unsigned)tile[c0 + 4 * w + 1][rr] << 8) |
+                 ((unsigned)tile[c0 + 4 * w + 2][rr] << 16) | ((unsigned)tile[c0 + 4 * w + 3][rr] << 24);
+        if (bj * 128 + rr >= Np || bi * 128 + c0 >= Np) continue;
+        const int64_t toff = (int64_t)(bj * 128 + rr) * Np + bi * 128 + c0;
+        if (AT8) *(u32x4*)(AT8 + toff) = t;
+        if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
+      }
       __syncthreads();  // the tile is refilled by the next iteration
     }
   }
@@ -1265,7 +1286,9 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
 hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
                          int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
                          hipStream_t s) {
-  dim3 grid(Np / 64 < 8 ? Np / 64 : 8, Np / 64);
+  if (Np <= 0 || Np % 64) return hipErrorInvalidValue;
+  const int strips = (Np + 127) / 128;
+  dim3 grid(strips < 16 ? strips : 16, strips);
   uint8_t* a = (uint8_t*)Aop;
   uint8_t* at = (uint8_t*)ATop;
   switch (prec) {
