@@ -56,7 +56,7 @@ class StreamStats:
                 "rounds": self.rounds, "max_active": self.max_active, "admission_waits": self.eagain}
 
 
-def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool = False,
+def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool | set = False,
                batch: Batch | None = None, lookahead: int = 0, tiles: list | None = None) -> tuple[StreamStats, dict]:
     """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
 
@@ -64,7 +64,8 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
     (dense n x n) or as a device int32 [m, 2] edge list.  lookahead = 1 lets
     each round's host work overlap the next round on the device.  tiles is a
     tile table (Batch.tune's result) for a batch this call creates.
-    Returns the statistics and, if keep_results, {rid: (model tensor, iters)}.
+    Returns the statistics and, if keep_results, {rid: (model tensor, iters)}
+    (keep_results may be a set of rids to keep only those models).
     """
     b = batch or Batch(pool_bytes, max_active, lookahead=lookahead)
     if tiles is not None and batch is None:
@@ -113,12 +114,13 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
         stats.rounds += 1
         for tag, slot, iters in b.dl_batch_poll():
             req, adm = inflight.pop(slot)
-            out = torch.empty((req.n, req.n), dtype=torch.uint8, device="cuda") if keep_results else None
+            keep = (req.rid in keep_results) if isinstance(keep_results, set) else bool(keep_results)
+            out = torch.empty((req.n, req.n), dtype=torch.uint8, device="cuda") if keep else None
             ones = b.dl_batch_fetch(slot, out)
             fin = time.perf_counter() - t0
             stats.completions.append(Completion(tag, 0 if req.kind == "tc" else 1, req.n, iters, ones,
                                                 req.arrival, adm, fin))
-            if keep_results:
+            if keep:
                 results[req.rid] = (out, iters)
     torch.cuda.synchronize()
     stats.wall = time.perf_counter() - t0

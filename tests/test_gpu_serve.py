@@ -319,3 +319,50 @@ def test_large_requests_all_tile_sizes(dl, lookahead):
             got, iters = results[r.rid]
             assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
             assert iters == _alone(dl, r)[1], (r.rid, r.kind, r.n)
+
+
+def test_config_serving_stream_10000(dl):
+    """The serving configuration as the benchmark runs it: 10,000 requests
+    (70% closure on ER p = 3/n, 30% same generation on forests, n
+    log-uniform in [64, 2048]) admitted as device edge lists into an 8 GiB
+    pool with 512 slots, one round of look-ahead and the autotuned tile
+    table.  Every request finishes; a sample of 104 (every 97th) is
+    compared with the oracle's model and iteration count."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    reqs = dlgen.serving_stream(10000, seed=0, rate=0.0)
+    flat, offs = [], [0]
+    for r in reqs:
+        e = dlgen.request_edges(r).astype(np.int32)
+        flat.append(e)
+        offs.append(offs[-1] + len(e))
+    edges = torch.from_numpy(np.concatenate(flat)).cuda()
+
+    def mk(r):
+        return edges[offs[r.rid]:offs[r.rid + 1]]
+
+    tb = dl.Batch(1 << 20, 4)
+    tiles = tb.tune()
+    tb.close()
+    sample = set(range(0, len(reqs), 97))
+    announce("serve config 10000", len(sample))
+    stats, results = run_stream(reqs, mk, pool_bytes=8 << 30, max_active=512, keep_results=sample,
+                                lookahead=1, tiles=tiles)
+    assert len(stats.completions) == len(reqs)
+    assert sorted(c.tag for c in stats.completions) == list(range(len(reqs)))
+    by_tag = {c.tag: c for c in stats.completions}
+    for rid in sorted(sample):
+        r = reqs[rid]
+        a = dlgen.to_dense(r.n, dlgen.request_edges(r))
+        got, iters = results[rid]
+        if r.kind == "tc":
+            ref = oracle.tc_seminaive(a)[0]
+            _, hist = oracle.bfs(a, want_matrix=False)
+            it_ref = oracle.square_schedule_from_hist(hist)[0]
+        else:
+            ref, _, it_ref, _ = oracle.sg_seminaive(a)
+        assert np.array_equal(host(got), ref), (rid, r.kind, r.n)
+        assert iters == it_ref, (rid, r.kind, r.n)
+        assert by_tag[rid].ones == int(ref.sum()), (rid, r.kind, r.n)
