@@ -382,7 +382,49 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
                                        for k in ("i8", "fp8", "fp4", "bf16", "f32", "f64")}
     torch.cuda.empty_cache()
     res["programs"] = run_programs(dl, ctx, torch)
+    res["paper_workloads"] = run_paper_workloads(dl, ctx, torch)
     return res
+
+
+def run_paper_workloads(dl, ctx, torch):
+    """The paper's own closure workloads (ER with self-loops, Sec. 7.1): N = 1000
+    at p = 1e-4 .. 1 and N = 10^4 at p = 1e-3, timed with int8 squaring and
+    with the fp64 epsilon solve (eps = 1 / (1 + max row sum), the largest the
+    bound allows, as in the paper's runs); the two models are compared.  The
+    paper's times (Octave on a CPU) are context, not a target."""
+    import numpy as np
+
+    import dlgen
+
+    out = []
+    for n, ps in ((1000, (1e-4, 1e-3, 1e-2, 1e-1, 1.0)), (10000, (1e-3,))):
+        for p in ps:
+            log(f"paper workload n={n} p={p}")
+            a = dlgen.to_dense(n, dlgen.er_edges(n, p, 0, self_loops=True))
+            ad = torch.from_numpy(a).cuda()
+            r8 = torch.empty_like(ad)
+            re = torch.empty_like(ad)
+            eps = 1.0 / (1.0 + float(a.sum(axis=1).max()))
+
+            def med(fn, k=3):
+                ts = []
+                for _ in range(k):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fn()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                return sorted(ts)[k // 2]
+
+            t8 = med(lambda: dl.dl_tc(ad, method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=r8, ctx=ctx))
+            _, it8 = dl.dl_tc(ad, method=dl.DL_TC_SQUARE, prec=dl.DL_I8, out=r8, ctx=ctx)
+            te = med(lambda: dl.dl_solve_eps(ad, eps, out=re, ctx=ctx))
+            out.append({"n": n, "p": p, "edges": int(a.sum()), "iters_int8_square": it8,
+                        "int8_square_ms": round(t8 * 1e3, 3), "eps_solve_fp64_ms": round(te * 1e3, 2),
+                        "closure_density": round(float(r8.sum().item()) / n ** 2, 6),
+                        "model_mismatches_eps_vs_int8": int((r8 != re).sum().item())})
+            del ad, r8, re
+    return out
 
 
 PROGRAMS = {
