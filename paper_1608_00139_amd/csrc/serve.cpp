@@ -89,8 +89,16 @@ struct RoundItem {
 
 struct Round {
   std::vector<RoundItem> items;
-  int set = 0;  // counter / descriptor / read-back set
+  int set = 0;        // counter / descriptor / read-back set
+  int64_t seq = -1;   // issue number
   bool live = false;
+};
+
+// Pool memory of a request fetched while round `after` was in flight: free
+// once that round has completed.
+struct Retired {
+  size_t off, bytes;
+  int64_t after;
 };
 
 }  // namespace
@@ -118,7 +126,7 @@ struct dl_batch {
   int64_t rounds_issued = 0;
   Round inflight;               // issued, not yet read (look-ahead only)
   uint64_t next_gen = 1;
-  std::vector<std::pair<size_t, size_t>> retire;  // pool regions freed once `inflight` completes
+  std::vector<Retired> retire;  // pool regions waiting for the round that may still read them
   int max_active = 0;
   int grid = 1024;  // persistent workgroups of the 64 and 128 tile launches
   int cus = 256;
@@ -465,6 +473,7 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
   BHIP(hipMemcpyAsync(hc + M, b->d_cnt + 2 * (size_t)M, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost, s));
   BHIP(hipEventRecord(b->ev[set], s));
   rd.set = set;
+  rd.seq = b->rounds_issued;
   rd.live = true;
   ++b->rounds_issued;
   return DL_OK;
@@ -520,19 +529,27 @@ int dl_batch_step(dl_batch* b, int32_t* active_out, int32_t* finished_out, void*
   int finished = 0, rc = DL_OK;
   Round next;
   if ((rc = issue_round(b, s, next))) return rc;
+  int64_t done_seq = -1;  // rounds up to this one have completed
   if (b->lookahead == 0) {
+    done_seq = next.seq;
     rc = complete_round(b, next, &finished);
   } else {
     // wait for the round issued by the previous call while `next` runs
+    done_seq = b->inflight.live ? b->inflight.seq : -1;
     rc = complete_round(b, b->inflight, &finished);
     b->inflight = std::move(next);
   }
   if (rc) return rc;
-  // pool memory fetched while an older round was in flight is free now
-  if (!b->inflight.live) {
-    for (auto& pr : b->retire) pool_free(b, pr.first, pr.second);
-    b->retire.clear();
+  // pool memory fetched while a now completed round was in flight is free
+  // (the round just issued skipped those requests: their slots were empty)
+  size_t kept = 0;
+  for (const Retired& q : b->retire) {
+    if (q.after <= done_seq)
+      pool_free(b, q.off, q.bytes);
+    else
+      b->retire[kept++] = q;
   }
+  b->retire.resize(kept);
   int active = 0;
   for (int i = 0; i < b->max_active; ++i) active += b->req[i].used && !b->req[i].done;
   if (active_out) *active_out = active;
@@ -570,7 +587,7 @@ int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* 
   }
   if (ones_out) *ones_out = r.ones[r.iters];
   if (b->inflight.live)
-    b->retire.emplace_back(r.off, r.bytes);  // the round in flight may still read it
+    b->retire.push_back({r.off, r.bytes, b->inflight.seq});  // the round in flight may still read it
   else
     pool_free(b, r.off, r.bytes);
   r = Req();
