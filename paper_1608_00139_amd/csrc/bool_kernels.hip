@@ -198,6 +198,49 @@ __device__ inline unsigned elem_nz(const uint8_t* p, int64_t idx) {
   else return p[idx] != 0 ? 1u : 0u;
 }
 
+// The 16 addend flags of row gr, columns gc .. gc + 15 (gc a multiple of 16)
+// as 0/1 bytes: from an int8 0/1 addend, or (p.add_op) from an addend in the
+// operand precision PREC, any nonzero element being true.
+template <int PREC>
+__device__ inline u32x4 load_add16(const NTParams& p, int gr, int gc) {
+  if (PREC == P_I8 || !p.add_op) return *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+  const uint8_t* base = (const uint8_t*)p.add + ((int64_t)gr * p.ld + gc) * elem_nibbles(PREC) / 2;
+  u32x4 v = {0u, 0u, 0u, 0u};
+  if constexpr (PREC == P_FP8) {
+    u32x4 x = *(const u32x4*)base;  // fold each byte's bits into its bit 0
+    x |= x >> 4;
+    x |= x >> 2;
+    x |= x >> 1;
+    v = x & 0x01010101u;
+  } else if constexpr (PREC == P_BF16) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const u32x4 w = ((const u32x4*)base)[h];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = 8 * h + 2 * j;  // elements e (low half) and e + 1 (high half)
+        v[e >> 2] |= ((w[j] & 0xffffu) != 0u ? 1u : 0u) << (8 * (e & 3));
+        v[(e + 1) >> 2] |= ((w[j] >> 16) != 0u ? 1u : 0u) << (8 * ((e + 1) & 3));
+      }
+    }
+  } else if constexpr (PREC == P_F32) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const u32x4 w = ((const u32x4*)base)[h];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[h] |= (w[j] != 0u ? 1u : 0u) << (8 * j);
+    }
+  } else {  // fp4: element e is nibble e of the 8 bytes (low nibble first)
+    const uint2 x = *(const uint2*)base;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const unsigned word = e < 8 ? x.x : x.y;
+      v[e >> 2] |= (((word >> (4 * (e & 7))) & 15u) != 0u ? 1u : 0u) << (8 * (e & 3));
+    }
+  }
+  return v;
+}
+
 __device__ inline int popc16(u32x4 v) {
   return __builtin_popcount(v[0]) + __builtin_popcount(v[1]) + __builtin_popcount(v[2]) +
          __builtin_popcount(v[3]);
@@ -414,7 +457,7 @@ __device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
     const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
     u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
     const int gr = row0 + r, gc = col0 + cs * 16;
-    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
     if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
       const int b = gr - gc;
       v[b >> 2] |= 1u << (8 * (b & 3));
@@ -554,7 +597,7 @@ __global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
     const int r = tid >> 1, cs = tid & 1;
     u32x4 v = *(const u32x4*)(et + r * kSmallEst + 16 * cs);
     const int gr = row0 + r, gc = col0 + 16 * cs;
-    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
     if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
       const int bq = gr - gc;
       v[bq >> 2] |= 1u << (8 * (bq & 3));
@@ -740,7 +783,7 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   // one 16-byte output segment: addend, identity, count, store, LDS copy
   auto emit = [&](u32x4 v, int lr, int lc) {
     const int gr = row0 + lr, gc = col0 + lc;
-    if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+    if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
     if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
       const int b = gr - gc;
       v[b >> 2] |= 1u << (8 * (b & 3));
@@ -955,7 +998,7 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
       const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
       u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
       const int gr = row0 + r, gc = col0 + cs * 16;
-      if (p.add) v |= *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+      if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
       if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
         const int b = gr - gc;
         v[b >> 2] |= 1u << (8 * (b & 3));

@@ -39,7 +39,9 @@ struct NTParams {
   const void* Y;        // [Np x Np] operand; row j of Y is column j of the right factor
   int64_t ld;           // leading dimension of X, Y, out, outT in elements (= Np)
   int Np;               // padded size: M = N = K = Np
-  const int8_t* add;    // optional 0/1 addend [Np x Np] (row-major, ld = Np)
+  const int8_t* add;    // optional addend [Np x Np], row-major: int8 0/1 (pitch Np) or, with
+                        // add_op, in operand precision (pitch ld; nonzero = true)
+  int add_op;           // the addend is in operand precision
   int add_identity;     // if set, OR in (i, i) for i < n_valid
   int n_valid;          // number of real constants
   void* out;            // [Np x Np] next iterate in operand precision

@@ -192,12 +192,13 @@ class Fix {
     uint8_t* op[4];
     for (int i = 0; i < 4; ++i) op[i] = sl_.ws + mat8 + i * matT;
     DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
-    // Addend: A (plain: A^T), or for int8 operands the previous iterate
-    // itself, which gives the same iterates: R^(k) = A + f(R^(k-1)) lies
-    // inside A + f(R^(k)) because f is monotone and R^(k-1) <= R^(k), and it
+    // Addend: the previous iterate itself instead of A (plain: A^T), which
+    // gives the same iterates: R^(k) = A + f(R^(k-1)) lies inside
+    // A + f(R^(k)) because f is monotone and R^(k-1) <= R^(k), and it
     // contains A; so A + f(R^(k)) = R^(k) + f(R^(k)).  No separate addend is
-    // then written or read.
-    const bool self_add = prec_ == P_I8;
+    // written or read; in other precisions than int8 the epilogue reads the
+    // iterate's elements as flags (add_op).
+    const bool self_add = true;
     if (mode_ == M_PLAIN) {
       // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
       Yop_ = op[0];
@@ -296,6 +297,7 @@ class Fix {
       NTParams& p = p_;
       p.step = (int)t;
       const int8_t* add = add_ ? add_ : (const int8_t*)S_[prev];
+      p.add_op = (add_ == nullptr && prec_ != P_I8) ? 1 : 0;
       if (mode_ == M_PLAIN) {
         p.X = S_[prev]; p.Y = Yop_; p.add = add; p.add_identity = 0;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
@@ -587,19 +589,19 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t Np = padded_size_for(prec, n);
   const size_t mat8 = (size_t)Np * Np, matT = (size_t)mat_bytes(prec, Np);
-  // [add int8][X][Y][out][outT][raw int8]: the operands of one squaring step
+  // [unused int8][X][Y][out][outT][raw int8]: the operands of one squaring step
   if ((rc = ensure_ws(ctx, fix_ws_bytes(prec, Np) + mat8))) return rc;
   uint8_t* base = (uint8_t*)ctx->ws;
-  int8_t* ADD = (int8_t*)base;
   uint8_t* op[4];
   for (int i = 0; i < 4; ++i) op[i] = base + mat8 + i * matT;
   uint8_t* raw = base + mat8 + 4 * matT;
   DL_HIP(launch_hash_bool(raw, Np, (int)n, (int)Np, 0x5eedu, s));
-  DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, ADD, nullptr, op[0], op[1], nullptr, s));
+  DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, nullptr, nullptr, op[0], op[1], nullptr, s));
   NTParams p{};
   p.X = op[0];
   p.Y = op[1];
-  p.add = prec == P_I8 ? (const int8_t*)op[0] : ADD;  // as the fixpoint driver's steps
+  p.add = (const int8_t*)op[0];  // the previous iterate, as in the fixpoint driver's steps
+  p.add_op = prec != P_I8 ? 1 : 0;
   p.out = op[2];
   p.outT = op[3];
   p.ld = Np;
