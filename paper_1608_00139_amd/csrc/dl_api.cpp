@@ -152,8 +152,8 @@ struct Timer {
 
 enum Mode { M_PLAIN = 0, M_SQUARE = 1, M_SG = 2 };
 
-// Workspace of one fixpoint: [add int8][op0][op1][op2][op3].
-size_t fix_ws_bytes(int prec, int64_t Np) { return (size_t)Np * Np + 4 * (size_t)mat_bytes(prec, Np) + 256; }
+// Workspace of one fixpoint: four operand-precision matrices.
+size_t fix_ws_bytes(int prec, int64_t Np) { return 4 * (size_t)mat_bytes(prec, Np) + 256; }
 
 // Device and pinned host state of one fixpoint in flight.
 struct FixSlot {
@@ -186,11 +186,9 @@ class Fix {
   int start() {
     Np_ = padded_size_for(prec_, n_);
     cfg_ = pick_config(c_, prec_, Np_);
-    const size_t mat8 = (size_t)Np_ * Np_;
     const size_t matT = (size_t)mat_bytes(prec_, Np_);
-    int8_t* ADD = (int8_t*)sl_.ws;
     uint8_t* op[4];
-    for (int i = 0; i < 4; ++i) op[i] = sl_.ws + mat8 + i * matT;
+    for (int i = 0; i < 4; ++i) op[i] = sl_.ws + i * matT;
     DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
     // Addend: the previous iterate itself instead of A (plain: A^T), which
     // gives the same iterates: R^(k) = A + f(R^(k-1)) lies inside
@@ -198,22 +196,19 @@ class Fix {
     // contains A; so A + f(R^(k)) = R^(k) + f(R^(k)).  No separate addend is
     // written or read; in other precisions than int8 the epilogue reads the
     // iterate's elements as flags (add_op).
-    const bool self_add = true;
     if (mode_ == M_PLAIN) {
-      // state S = R^T; S^(1) = A^T; product operand Y = A; addend A^T
+      // state S = R^T; S^(1) = A^T; product operand Y = A
       Yop_ = op[0];
       S_[0] = op[1];
       S_[1] = op[2];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, self_add ? nullptr : ADD, Yop_, S_[1],
-                           sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, S_[1], sl_.ring + 1, s_));
     } else if (mode_ == M_SQUARE) {
-      // R^(1) = A with its transpose; addend A
+      // R^(1) = A with its transpose
       S_[0] = op[0];
       ST_[0] = op[1];
       S_[1] = op[2];
       ST_[1] = op[3];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, self_add ? nullptr : ADD, nullptr, S_[1], ST_[1],
-                           sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, S_[1], ST_[1], sl_.ring + 1, s_));
     } else {
       // P in operand precision; S^(1) = I; intermediate T
       Yop_ = op[0];
@@ -233,7 +228,6 @@ class Fix {
       S_[0] = R_;
       r_is_s0_ = true;
     }
-    add_ = (mode_ != M_SG && !self_add) ? ADD : nullptr;
     const TileCfg tc = nt_config(prec_, cfg_);
     p_.ld = Np_;
     p_.Np = (int)Np_;
@@ -296,8 +290,8 @@ class Fix {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       NTParams& p = p_;
       p.step = (int)t;
-      const int8_t* add = add_ ? add_ : (const int8_t*)S_[prev];
-      p.add_op = (add_ == nullptr && prec_ != P_I8) ? 1 : 0;
+      const int8_t* add = (const int8_t*)S_[prev];  // the previous iterate is the addend
+      p.add_op = prec_ != P_I8 ? 1 : 0;
       if (mode_ == M_PLAIN) {
         p.X = S_[prev]; p.Y = Yop_; p.add = add; p.add_identity = 0;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
@@ -369,7 +363,6 @@ class Fix {
   int64_t Np_ = 0;
   int cfg_ = 0;
   NTParams p_{};
-  const int8_t* add_ = nullptr;
   void *Yop_ = nullptr, *S_[2] = {nullptr, nullptr}, *ST_[2] = {nullptr, nullptr}, *Tmp_ = nullptr;
   std::vector<int64_t> ones_ = std::vector<int64_t>(2, 0);
   int64_t iters_ = -1;  // set when the repeat is seen
@@ -589,12 +582,12 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t Np = padded_size_for(prec, n);
   const size_t mat8 = (size_t)Np * Np, matT = (size_t)mat_bytes(prec, Np);
-  // [unused int8][X][Y][out][outT][raw int8]: the operands of one squaring step
+  // [X][Y][out][outT][raw int8]: the operands of one squaring step
   if ((rc = ensure_ws(ctx, fix_ws_bytes(prec, Np) + mat8))) return rc;
   uint8_t* base = (uint8_t*)ctx->ws;
   uint8_t* op[4];
-  for (int i = 0; i < 4; ++i) op[i] = base + mat8 + i * matT;
-  uint8_t* raw = base + mat8 + 4 * matT;
+  for (int i = 0; i < 4; ++i) op[i] = base + i * matT;
+  uint8_t* raw = base + 4 * matT;
   DL_HIP(launch_hash_bool(raw, Np, (int)n, (int)Np, 0x5eedu, s));
   DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, nullptr, nullptr, op[0], op[1], nullptr, s));
   NTParams p{};

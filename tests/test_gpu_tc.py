@@ -184,7 +184,7 @@ def test_batch_one_slot_budget_and_errors(dl):
 
     n = 300
     inputs = [dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, s)) for s in range(3)]
-    ctx = dl.Context(workspace_budget=2 << 20)  # Np = 512: one fixpoint needs 1.3 MB
+    ctx = dl.Context(workspace_budget=3 << 19)  # Np = 512: one fixpoint needs 1.05 MB, two 2.1 MB
     announce("tc batch one slot")
     rs, its = dl.dl_tc_batch([dev(a) for a in inputs], ctx=ctx)
     for g, a in enumerate(inputs):
