@@ -150,10 +150,11 @@ def test_zero_size_and_errors(dl):
 @pytest.mark.parametrize("count", [1, 2, 5])
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("prec", ["i8", "f32"])
-def test_batch_matches_oracle(dl, count, method, prec):
+@pytest.mark.parametrize("n", [300, 512])
+def test_batch_matches_oracle(dl, count, method, prec, n):
     """dl_tc_batch: every model and iteration count equal to the oracle's,
-    with an empty and a complete relation among random ones."""
-    n = 300
+    with an empty and a complete relation among random ones (n = 512 is
+    unpadded: int8 outputs double as iterate buffers while slots are reused)."""
     inputs = []
     for g in range(count):
         if g == 1:
@@ -163,7 +164,7 @@ def test_batch_matches_oracle(dl, count, method, prec):
         else:
             a = dlgen.to_dense(n, dlgen.er_edges(n, (1.0 + g) / n, 10 + g))
         inputs.append(a)
-    announce("tc batch", count, method, prec)
+    announce("tc batch", count, method, prec, n)
     rs, its = dl.dl_tc_batch([dev(a) for a in inputs], method=method, prec=prec)
     assert len(rs) == count and len(its) == count
     for g, a in enumerate(inputs):
