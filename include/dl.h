@@ -313,7 +313,8 @@ int dl_batch_poll(dl_batch* batch, int64_t* tags, int32_t* slots, int32_t* iters
 
 /* Write the 0/1 model of a finished request into R (device uint8 [n x ldr];
  * NULL to discard), report its number of true entries in *ones (may be
- * NULL), and free the slot and its pool memory. */
+ * NULL), and free the slot and its pool memory.  A request may be fetched
+ * before it is polled; dl_batch_poll then no longer reports it. */
 int dl_batch_fetch(dl_batch* batch, int32_t slot, uint8_t* R, int64_t ldr, int64_t* ones, void* stream);
 
 /* Tile autotuner of the grouped step (the output tile size of each request's

@@ -252,14 +252,21 @@ __device__ inline int wave_sum(int v) {
   return v;
 }
 
-// Block index -> output tile.  The hardware deals workgroups round-robin
-// over the 8 XCDs (block b on XCD b % 8).  Give each XCD a contiguous run of
-// logical tiles, then walk the logical tiles in groups of GM tile rows so
-// the workgroups resident on one XCD share row and column panels in its L2.
-__device__ inline void tile_coords(int b, int nblocks, int tiles_m, int tiles_n, int& tm, int& tn) {
+// Block index -> logical index.  The hardware deals workgroups round-robin
+// over the 8 XCDs (block b on XCD b % 8); the blocks of XCD x get the
+// contiguous run of logical indices [x q + min(x, r), ...), q = nblocks / 8,
+// r = nblocks % 8 (a bijection on [0, nblocks) for any nblocks).
+__device__ inline int xcd_logical(int b, int nblocks) {
   const int q = nblocks >> 3, r = nblocks & 7;
   const int x = b & 7, local = b >> 3;
-  const int logical = x * q + (x < r ? x : r) + local;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// Block index -> output tile: each XCD takes a contiguous run of logical
+// tiles, walked in groups of GM tile rows so that the workgroups resident on
+// one XCD share row and column panels in its L2.
+__device__ inline void tile_coords(int b, int nblocks, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int logical = xcd_logical(b, nblocks);
   constexpr int GM = 8;
   const int per_group = GM * tiles_n;
   const int group = logical / per_group;
@@ -645,14 +652,16 @@ static hipError_t set_lds_attr_small() {
 // work list is the concatenation of every request's 64 x 64 output tiles;
 // desc[a].tile_start is the running tile count.  A persistent grid walks the
 // list with a stride of gridDim.x, so every workgroup ends after at most
-// ceil(total / gridDim.x) tiles.
+// ceil(total / gridDim.x) tiles.  Each pass over gridDim.x consecutive tiles
+// gives every XCD a contiguous run of them (xcd_logical), so neighbouring
+// tiles of one request, which read the same operand panels, share an L2.
 // T x T tiles, four waves of (T/2) x (T/2): 64 for small requests, 128 for
 // the others (four times the work per tile, twice the operand reuse).
 template <int T>
 __global__ void __launch_bounds__(256)
 k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  for (int item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+  for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
     int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -1058,7 +1067,7 @@ k_nt_dma(NTParams p) {
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  for (int item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+  for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
     int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

@@ -586,6 +586,8 @@ int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* 
     BHIP(hipStreamSynchronize(s));
   }
   if (ones_out) *ones_out = r.ones[r.iters];
+  // a request fetched before it was polled is no longer reported by dl_batch_poll
+  b->finished.erase(std::remove(b->finished.begin(), b->finished.end(), slot), b->finished.end());
   if (b->inflight.live)
     b->retire.push_back({r.off, r.bytes, b->inflight.seq});  // the round in flight may still read it
   else

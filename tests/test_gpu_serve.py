@@ -119,6 +119,39 @@ def test_edge_requests(dl):
 
 
 @pytest.mark.parametrize("lookahead", [0, 1])
+def test_fetch_before_poll(dl, lookahead):
+    """A request fetched without being polled is not reported by a later
+    poll, also after its slot has been reused by a new request."""
+    b = dl.Batch(pool_bytes=1 << 24, max_active=2, lookahead=lookahead)
+    announce("serve fetch before poll", lookahead)
+    n_path = 256  # a directed path: about log2(n) + 2 squaring iterations
+    path = np.zeros((n_path, n_path), np.uint8)
+    path[np.arange(n_path - 1), np.arange(1, n_path)] = 1
+    s_empty = b.dl_batch_submit(b.TC, dev(np.zeros((70, 70), np.uint8)), 10)
+    s_path = b.dl_batch_submit(b.TC, dev(path), 11)
+    for _ in range(3):  # the empty relation is finished after one or two rounds
+        b.dl_batch_step()
+    assert b.dl_batch_fetch(s_empty) == 0  # not polled
+    three = np.ones((3, 3), np.uint8)
+    s_new = b.dl_batch_submit(b.TC, dev(three), 12)
+    assert s_new == s_empty  # the fetched slot is reused
+    polled = {}
+    for _ in range(30):
+        b.dl_batch_step()
+        for tag, slot, iters in b.dl_batch_poll():
+            assert tag != 10, "a fetched request was polled"
+            n = {11: n_path, 12: 3}[tag]
+            out = dev(np.zeros((n, n), np.uint8))
+            b.dl_batch_fetch(slot, out)
+            polled[tag] = (host(out), iters)
+        if len(polled) == 2:
+            break
+    assert sorted(polled) == [11, 12]
+    assert np.array_equal(polled[11][0], oracle.tc_seminaive(path)[0])
+    assert polled[12][0].all() and polled[12][1] == 2
+
+
+@pytest.mark.parametrize("lookahead", [0, 1])
 def test_edge_list_admission(dl, lookahead):
     """Requests admitted as device edge lists give the same models and
     iteration counts as dense admission and the oracle; repeated pairs count
