@@ -28,6 +28,12 @@
 // slot fetched and reused meanwhile is not confused with its previous
 // request; pool memory released by dl_batch_fetch returns to the pool only
 // after the round that may still read it has completed.
+//
+// Per round the device sees one descriptor upload (all tile lists), the
+// grouped launches and one counter read-back.  The round counters are never
+// cleared: every round of a set reads all of that set's counters back, so a
+// product's count is the difference from the value read in the set's
+// previous round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -111,10 +117,11 @@ struct dl_batch {
   std::map<size_t, size_t> free_list;  // offset -> size
   std::vector<Req> req;
   // two sets (alternating rounds) of everything a round reads or writes:
-  GroupDesc* d_desc = nullptr;  // device descriptors: 64-, 128- and 256-tile lists [max] each, per set
+  GroupDesc* d_desc = nullptr;  // device descriptors [max] per set: the 256-, 128- and 64-tile lists in turn
   GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
-  unsigned long long* d_cnt = nullptr;  // round counters [max] per set, then admission counters [max]
-  unsigned long long* h_cnt = nullptr;  // per set: round counters [max], admission counters [max]
+  unsigned long long* d_cnt = nullptr;  // per set: round counters [max], then admission counters [max]
+  unsigned long long* h_cnt = nullptr;  // pinned copy, same layout
+  std::vector<unsigned long long> last;  // per set: round counters as read back in its previous round
   AdmitDesc* d_adm = nullptr;   // grouped admission descriptors [max] per set
   AdmitDesc* h_adm = nullptr;   // pinned host copy
   hipEvent_t ev[2] = {nullptr, nullptr};  // end of each set's read-back
@@ -221,17 +228,17 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   }
   b->pool_bytes = pool_bytes;
   b->free_list[0] = pool_bytes;
-  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * kLists * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * kLists * max_active, hipHostMallocDefault)) !=
-      hipSuccess)
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
-  if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 3 * max_active)) != hipSuccess)
+  if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 4 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
   if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 4 * max_active, hipHostMallocDefault)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned counter allocation failed"));
-  if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 3 * max_active)) != hipSuccess)
+  if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 4 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_EHIP, "counter clear"));
+  b->last.assign((size_t)2 * max_active, 0ull);
   if ((e = hipMalloc(&b->d_adm, sizeof(AdmitDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "admission descriptor allocation failed"));
   if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
@@ -307,7 +314,9 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   const size_t m = (size_t)Np * Np;
   r.ones.push_back(0);
   r.gen = b->next_gen++;
-  unsigned long long* adm = b->d_cnt + 2 * b->max_active + slot;
+  // admission counter, read back by the next round, which uses counter set
+  // rounds_issued % 2 (the round in flight, if any, uses the other set)
+  unsigned long long* adm = b->d_cnt + (size_t)(b->rounds_issued & 1) * 2 * b->max_active + b->max_active + slot;
   if (kind == 0) {
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // R0, R0T, R1, R1T
     if (!deferred) BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
@@ -412,17 +421,26 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
     BHIP(hipMemcpyAsync(da, ha, sizeof(AdmitDesc) * na, hipMemcpyHostToDevice, s));
     BHIP(launch_admit(da, na, units, edges, s));
   }
-  // this round's work lists (64, 128 and 256 tiles); the counters of a
-  // request's product are at d_cnt[set][slot]
-  unsigned long long* cnt = b->d_cnt + (size_t)set * M;
-  GroupDesc* hset = b->h_desc + (size_t)set * kLists * M;
-  GroupDesc* dset = b->d_desc + (size_t)set * kLists * M;
+  // this round's work lists (256, 128 and 64 tiles, one after the other in
+  // the set's descriptors); the counter of a request's product is
+  // d_cnt[set][slot]
+  unsigned long long* cnt = b->d_cnt + (size_t)set * 2 * M;
+  GroupDesc* hset = b->h_desc + (size_t)set * M;
+  GroupDesc* dset = b->d_desc + (size_t)set * M;
   int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};
+  for (int i = 0; i < M; ++i) {
+    const Req& r = b->req[i];
+    if (r.used && !r.done) ++na[list_of(r.tile)];
+  }
+  int first[kLists], fill[kLists] = {0, 0, 0};
+  first[2] = 0;
+  first[1] = na[2];
+  first[0] = na[2] + na[1];
   for (int i = 0; i < M; ++i) {
     Req& r = b->req[i];
     if (!r.used || r.done) continue;
     const int li = list_of(r.tile);
-    GroupDesc& g = hset[li * M + na[li]];
+    GroupDesc& g = hset[first[li] + fill[li]];
     std::memset(&g, 0, sizeof g);
     g.Np = (int)r.Np;
     g.n_valid = (int)r.n;
@@ -458,19 +476,18 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
     }
     tiles[li] += (int)((r.Np / r.tile) * (r.Np / r.tile));
     rd.items.push_back(it);
-    ++na[li];
+    ++fill[li];
   }
   if (rd.items.empty()) return DL_OK;
-  BHIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * M, s));
+  BHIP(hipMemcpyAsync(dset, hset, sizeof(GroupDesc) * rd.items.size(), hipMemcpyHostToDevice, s));
   for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
     if (!na[li]) continue;
-    BHIP(hipMemcpyAsync(dset + li * M, hset + li * M, sizeof(GroupDesc) * na[li], hipMemcpyHostToDevice, s));
     const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
-    BHIP(launch_group_step(64 << li, dset + li * M, na[li], tiles[li], std::min(grid, tiles[li]), s));
+    BHIP(launch_group_step(64 << li, dset + first[li], na[li], tiles[li], std::min(grid, tiles[li]), s));
   }
-  unsigned long long* hc = b->h_cnt + (size_t)set * 2 * M;
-  BHIP(hipMemcpyAsync(hc, cnt, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost, s));
-  BHIP(hipMemcpyAsync(hc + M, b->d_cnt + 2 * (size_t)M, sizeof(unsigned long long) * M, hipMemcpyDeviceToHost, s));
+  // round and admission counters of the set in one read-back
+  BHIP(hipMemcpyAsync(b->h_cnt + (size_t)set * 2 * M, cnt, sizeof(unsigned long long) * 2 * M,
+                      hipMemcpyDeviceToHost, s));
   BHIP(hipEventRecord(b->ev[set], s));
   rd.set = set;
   rd.seq = b->rounds_issued;
@@ -487,19 +504,21 @@ int complete_round(dl_batch* b, Round& rd, int* finished) {
   rd.live = false;
   const int M = b->max_active;
   const unsigned long long* hc = b->h_cnt + (size_t)rd.set * 2 * M;
+  unsigned long long* last = b->last.data() + (size_t)rd.set * M;
   for (const RoundItem& it : rd.items) {
     Req& r = b->req[it.slot];
     if (!r.used || r.gen != it.gen || r.done) continue;
     if (it.admit) r.ones.push_back((int64_t)hc[M + it.slot]);  // ones[1] = |A|
+    const int64_t ones = (int64_t)(hc[it.slot] - last[it.slot]);  // this round's product
     if (it.kind == 0) {
       r.computed = it.t;
-      r.ones.push_back((int64_t)hc[it.slot]);
+      r.ones.push_back(ones);
     } else if (it.phase == 0) {
       r.phase = 1;
     } else {
       r.computed = it.t;
       r.phase = 0;
-      r.ones.push_back((int64_t)hc[it.slot]);
+      r.ones.push_back(ones);
     }
     settle(r);
     if (r.done) {
@@ -507,6 +526,7 @@ int complete_round(dl_batch* b, Round& rd, int* finished) {
       ++*finished;
     }
   }
+  std::copy(hc, hc + M, last);
   return DL_OK;
 }
 
