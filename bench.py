@@ -697,7 +697,7 @@ def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
     wfac = gib_kib / (sum(cw) / len(cw))
     fetch = sum(f) / len(f) * ffac * 1024
     write = sum(w) / len(w) * wfac * 1024
-    algo = 2 * N * N + 2 * N * N  # X and Y read (the addend is X itself), out and out^T written
+    algo = 2 * N * N + 2 * N * N  # X and Y read, out and out^T written (no addend read)
     print("# HBM traffic per launch of the int8 step kernel at N=8192 (rocprofv3 --pmc)")
     print(f"kernel: {kernel}")
     print(f"kernel_source_sha256: {source_hash()}")
@@ -707,7 +707,7 @@ def pmc_summary(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv) -> int:
     print(f"fetch_bytes_per_launch: {fetch:.0f}")
     print(f"write_bytes_per_launch: {write:.0f}")
     print(f"traffic_bytes_per_launch: {fetch + write:.0f}")
-    print(f"algorithmic_bytes_per_launch: {algo}  (X, Y read, the addend being X; out, out^T written; int8)")
+    print(f"algorithmic_bytes_per_launch: {algo}  (X, Y read; out, out^T written; int8)")
     print(f"traffic_over_algorithmic: {(fetch + write) / algo:.3f}")
     return 0
 

@@ -246,6 +246,16 @@ __device__ inline int popc16(u32x4 v) {
          __builtin_popcount(v[3]);
 }
 
+// v | the identity bit of its segment: row gr, columns gc .. gc + 15 hold
+// the diagonal element (gr, gr) when gc <= gr < gc + 16 and gr < n.
+__device__ inline u32x4 with_diag(u32x4 v, int gr, int gc, int n) {
+  if (gr >= gc && gr < gc + 16 && gr < n) {
+    const int b = gr - gc;
+    v[b >> 2] |= 1u << (8 * (b & 3));
+  }
+  return v;
+}
+
 __device__ inline int wave_sum(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -441,6 +451,21 @@ __device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
   }
 
   // ---- epilogue: 0/1 tile in LDS, [BM][EST] bytes
+  constexpr int SEG_PER_ROW = BN / 16;
+  constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
+  // int8 addend segments of this thread (segment i: tile row q / SEG_PER_ROW,
+  // 16-byte column q % SEG_PER_ROW, q = tid + i NT), all requested before
+  // the first is needed, so the tile waits on one memory round trip (wider
+  // operand-precision addends are read per segment: held together they
+  // would cost occupancy)
+  constexpr bool BATCH = Op::kPrec == P_I8;
+  u32x4 addv[SEGS];
+#pragma unroll
+  for (int i = 0; i < SEGS; ++i) {
+    const int q = tid + i * K::NT;
+    addv[i] = u32x4{0u, 0u, 0u, 0u};
+    if (BATCH && p.add) addv[i] = load_add16<Op::kPrec>(p, row0 + q / SEG_PER_ROW, col0 + (q % SEG_PER_ROW) * 16);
+  }
   uint8_t* et = smem;
 #pragma unroll
   for (int i = 0; i < K::FM; ++i)
@@ -455,23 +480,19 @@ __device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
   __syncthreads();
 
   int cnt = 0;
-  constexpr int SEG_PER_ROW = BN / 16;
-  constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
   uint8_t* outb = (uint8_t*)p.out;
-#pragma unroll 4
+#pragma unroll
   for (int i = 0; i < SEGS; ++i) {
     const int q = tid + i * K::NT;
     const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
     u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
     const int gr = row0 + r, gc = col0 + cs * 16;
-    if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
-    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-      const int b = gr - gc;
-      v[b >> 2] |= 1u << (8 * (b & 3));
-    }
+    if (BATCH) v |= addv[i];
+    else if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
+    if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
     cnt += popc16(v);
     store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-    if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
+    if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = p.outT_ident ? with_diag(v, gr, gc, p.n_valid) : v;
   }
 
   if (p.outT) {
@@ -605,13 +626,10 @@ __global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
     u32x4 v = *(const u32x4*)(et + r * kSmallEst + 16 * cs);
     const int gr = row0 + r, gc = col0 + 16 * cs;
     if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
-    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-      const int bq = gr - gc;
-      v[bq >> 2] |= 1u << (8 * (bq & 3));
-    }
+    if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
     cnt = popc16(v);
     store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * NIB / 2, v);
-    if (p.outT) *(u32x4*)(et + r * kSmallEst + 16 * cs) = v;
+    if (p.outT) *(u32x4*)(et + r * kSmallEst + 16 * cs) = p.outT_ident ? with_diag(v, gr, gc, p.n_valid) : v;
   }
   if (p.outT) {
     __syncthreads();
@@ -679,6 +697,7 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.Np = g.Np;
     p.add = g.add;
     p.add_identity = g.add_identity;
+    p.outT_ident = g.outT_ident;
     p.n_valid = g.n_valid;
     p.out = g.out;
     p.outT = g.outT;
@@ -789,23 +808,40 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   static_assert(CHUNKS == 16, "the LDS swizzle assumes 256-byte tile rows");
   uint8_t* outb = (uint8_t*)p.out;
   int cnt = 0;
+  // Output segment e of this lane: row lr, columns lc .. lc + 15 of the tile.
+  constexpr int NSEG = K::FR == 16 ? K::FM * (K::FN / 4) : K::FM * K::FN;
+  auto seg_row = [&](int e) {
+    return K::FR == 16 ? wm * (K::FM * 16) + 16 * (e / (K::FN / 4)) + (lane & 15)
+                       : wm * (K::FM * 32) + 32 * (e / K::FN) + (lane & 31);
+  };
+  auto seg_col = [&](int e) {
+    return K::FR == 16 ? wn * (K::FN * 16) + 16 * (4 * (e % (K::FN / 4)) + (lane >> 4))
+                       : wn * (K::FN * 32) + 32 * (e % K::FN) + 16 * (lane >> 5);
+  };
+  // every addend segment is requested before the first is needed, so the
+  // tile waits on one memory round trip instead of one per segment
+  u32x4 addv[NSEG];
+#pragma unroll
+  for (int e = 0; e < NSEG; ++e) {
+    addv[e] = u32x4{0u, 0u, 0u, 0u};
+    if (p.add) addv[e] = load_add16<Op::kPrec>(p, row0 + seg_row(e), col0 + seg_col(e));
+  }
   // one 16-byte output segment: addend, identity, count, store, LDS copy
-  auto emit = [&](u32x4 v, int lr, int lc) {
+  // (with the identity when the transposed copy is the next step's Y)
+  auto emit = [&](u32x4 v, int e) {
+    const int lr = seg_row(e), lc = seg_col(e);
     const int gr = row0 + lr, gc = col0 + lc;
-    if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
-    if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-      const int b = gr - gc;
-      v[b >> 2] |= 1u << (8 * (b & 3));
-    }
+    v |= addv[e];
+    if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
     cnt += popc16(v);
     store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-    if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = v;
+    if (p.outT)
+      *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = p.outT_ident ? with_diag(v, gr, gc, p.n_valid) : v;
   };
   if constexpr (K::FR == 16) {
-    const int g = lane >> 4, c = lane & 15;
+    const int g = lane >> 4;
 #pragma unroll
     for (int i = 0; i < K::FM; ++i) {
-      const int lr = wm * (K::FM * 16) + 16 * i + c;  // row within the tile
 #pragma unroll
       for (int q = 0; q < K::FN / 4; ++q) {
         unsigned P[4];
@@ -824,17 +860,16 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
 #pragma unroll
           for (int d = 0; d < 4; ++d) v[d] = d == k ? got : v[d];
         }
-        emit(v, lr, wn * (K::FN * 16) + 16 * (4 * q + g));
+        emit(v, i * (K::FN / 4) + q);
       }
     }
   } else {
     // 32 x 32 fragments: item 4 q + b of lane (h, r) = (lane / 32, lane % 32)
     // is C[row 32 i + r][column 32 j + 8 q + 4 h + b]; lanes r and r + 32
     // swap two dwords so that lane h holds columns 16 h .. 16 h + 15
-    const int h = lane >> 5, rl = lane & 31;
+    const int h = lane >> 5;
 #pragma unroll
     for (int i = 0; i < K::FM; ++i) {
-      const int lr = wm * (K::FM * 32) + 32 * i + rl;
 #pragma unroll
       for (int j = 0; j < K::FN; ++j) {
         const auto& a = acc[i][j];
@@ -846,7 +881,7 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
         const unsigned r0 = (unsigned)__shfl_xor((int)(h ? D[0] : D[2]), 32, 64);
         const unsigned r1 = (unsigned)__shfl_xor((int)(h ? D[1] : D[3]), 32, 64);
         const u32x4 v = h ? u32x4{r0, D[2], r1, D[3]} : u32x4{D[0], r0, D[1], r1};
-        emit(v, lr, wn * (K::FN * 32) + 32 * j + 16 * h);
+        emit(v, i * K::FN + j);
       }
     }
   }
@@ -985,6 +1020,15 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
     cnt = dma_epilogue_swapped<K, Op>(p, acc, smem, row0, col0, wm, wn, lane, tid);
   } else {
     // ---- epilogue of k_nt_step: the 0/1 tile through LDS byte by byte
+    constexpr int SEG_PER_ROW = BN / 16;
+    constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
+    u32x4 addv[SEGS];  // addend segments, requested together as in nt_tile
+#pragma unroll
+    for (int i = 0; i < SEGS; ++i) {
+      const int q = tid + i * K::NT;
+      addv[i] = u32x4{0u, 0u, 0u, 0u};
+      if (p.add) addv[i] = load_add16<Op::kPrec>(p, row0 + q / SEG_PER_ROW, col0 + (q % SEG_PER_ROW) * 16);
+    }
     uint8_t* et = smem;
 #pragma unroll
     for (int i = 0; i < K::FM; ++i)
@@ -998,23 +1042,18 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
         }
     __syncthreads();
 
-    constexpr int SEG_PER_ROW = BN / 16;
-    constexpr int SEGS = BM * SEG_PER_ROW / K::NT;
     uint8_t* outb = (uint8_t*)p.out;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < SEGS; ++i) {
       const int q = tid + i * K::NT;
       const int r = q / SEG_PER_ROW, cs = q % SEG_PER_ROW;
       u32x4 v = *(const u32x4*)(et + r * K::EST + cs * 16);
       const int gr = row0 + r, gc = col0 + cs * 16;
-      if (p.add) v |= load_add16<Op::kPrec>(p, gr, gc);
-      if (p.add_identity && gr >= gc && gr < gc + 16 && gr < p.n_valid) {
-        const int b = gr - gc;
-        v[b >> 2] |= 1u << (8 * (b & 3));
-      }
+      v |= addv[i];
+      if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
       cnt += popc16(v);
       store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-      if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = v;
+      if (p.outT) *(u32x4*)(et + r * K::EST + cs * 16) = p.outT_ident ? with_diag(v, gr, gc, p.n_valid) : v;
     }
     if (p.outT) {
       __syncthreads();
@@ -1084,6 +1123,7 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.Np = g.Np;
     p.add = g.add;
     p.add_identity = g.add_identity;
+    p.outT_ident = g.outT_ident;
     p.n_valid = g.n_valid;
     p.out = g.out;
     p.outT = g.outT;
@@ -1251,11 +1291,13 @@ int choose_nt_config(int prec, int64_t np) {
 // ----------------------------------------------------------------- ingest / emit
 // Ingest: normalise the caller's bytes (nonzero = true) into 0/1, zero-pad to
 // Np x Np, and write the layouts the chosen fixpoint needs: int8 A and A^T
-// (epilogue addends) and A, A^T in operand precision.  Counts the ones of A.
+// and A, A^T in operand precision, the latter two optionally with the
+// identity on the first n constants (ident bits 0 and 1: the right operand
+// of a closure step).  Counts the ones of A.
 template <int PREC>
 __global__ void __launch_bounds__(256)
 k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, int8_t* AT8,
-         uint8_t* Aop, uint8_t* ATop, unsigned long long* ones_slot) {
+         uint8_t* Aop, uint8_t* ATop, int ident, unsigned long long* ones_slot) {
   // one 128-row strip per blockIdx.y; the strip's 128 x 128 tiles are shared
   // out over gridDim.x workgroups, so the ones counter takes few atomics.
   // Each wave reads and writes whole 128-byte row segments: thread t takes
@@ -1300,7 +1342,9 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
       if (col_in && bi * 128 + r < Np) {
         const int64_t off = (int64_t)(bi * 128 + r) * Np + bj * 128 + c0;
         if (A8) *(u32x4*)(A8 + off) = v[k];
-        if (Aop) store_bool16<PREC>(Aop + elem_offset(PREC, off), v[k]);
+        if (Aop)
+          store_bool16<PREC>(Aop + elem_offset(PREC, off),
+                             (ident & 1) ? with_diag(v[k], bi * 128 + r, bj * 128 + c0, n) : v[k]);
       }
       cnt += popc16(v[k]);  // zero outside [0, n) anyway
       if (AT8 || ATop) *(u32x4*)&tile[r][c0] = v[k];
@@ -1318,7 +1362,9 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
         if (bj * 128 + rr >= Np || bi * 128 + c0 >= Np) continue;
         const int64_t toff = (int64_t)(bj * 128 + rr) * Np + bi * 128 + c0;
         if (AT8) *(u32x4*)(AT8 + toff) = t;
-        if (ATop) store_bool16<PREC>(ATop + elem_offset(PREC, toff), t);
+        if (ATop)
+          store_bool16<PREC>(ATop + elem_offset(PREC, toff),
+                             (ident & 2) ? with_diag(t, bj * 128 + rr, bi * 128 + c0, n) : t);
       }
       __syncthreads();  // the tile is refilled by the next iteration
     }
@@ -1336,7 +1382,7 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
 }
 
 hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
-                         int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
+                         int8_t* AT8, void* Aop, void* ATop, int ident, unsigned long long* ones_slot,
                          hipStream_t s) {
   if (Np <= 0 || Np % 64) return hipErrorInvalidValue;
   const int strips = (Np + 127) / 128;
@@ -1344,11 +1390,11 @@ hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np,
   uint8_t* a = (uint8_t*)Aop;
   uint8_t* at = (uint8_t*)ATop;
   switch (prec) {
-    case P_I8: hipLaunchKernelGGL(k_ingest<P_I8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
-    case P_F32: hipLaunchKernelGGL(k_ingest<P_F32>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
-    case P_BF16: hipLaunchKernelGGL(k_ingest<P_BF16>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
-    case P_FP8: hipLaunchKernelGGL(k_ingest<P_FP8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
-    default: hipLaunchKernelGGL(k_ingest<P_FP4>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ones_slot); break;
+    case P_I8: hipLaunchKernelGGL(k_ingest<P_I8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ident, ones_slot); break;
+    case P_F32: hipLaunchKernelGGL(k_ingest<P_F32>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ident, ones_slot); break;
+    case P_BF16: hipLaunchKernelGGL(k_ingest<P_BF16>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ident, ones_slot); break;
+    case P_FP8: hipLaunchKernelGGL(k_ingest<P_FP8>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ident, ones_slot); break;
+    default: hipLaunchKernelGGL(k_ingest<P_FP4>, grid, dim3(256), 0, s, A, lda, n, Np, A8, AT8, a, at, ident, ones_slot); break;
   }
   return hipGetLastError();
 }

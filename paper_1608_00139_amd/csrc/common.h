@@ -34,6 +34,9 @@ __host__ __device__ constexpr int64_t elem_offset(int prec, int64_t e) { return 
 __host__ __device__ constexpr int64_t mat_bytes(int prec, int64_t np) { return np * np * elem_nibbles(prec) / 2; }
 
 // Parameters of one boolean product step  out = [add + X * Y^T != 0].
+// Closure steps need no addend: with the identity stored in Y (Y = R^T + I
+// for squaring, A + I for the plain series), X Y^T = R R + R already holds
+// the previous iterate; outT_ident writes the next Y that way.
 struct NTParams {
   const void* X;        // [Np x Np] operand, row-major, K contiguous
   const void* Y;        // [Np x Np] operand; row j of Y is column j of the right factor
@@ -46,6 +49,7 @@ struct NTParams {
   int n_valid;          // number of real constants
   void* out;            // [Np x Np] next iterate in operand precision
   void* outT;           // optional transposed copy of out
+  int outT_ident;       // outT gets (i, i) for i < n_valid as well: out^T + I
   unsigned long long* ones;  // model-size ring (read for the repeat test)
   int count;            // 1: add this iterate's number of ones to ones[step % kRing]
   int* conv;            // convergence step (null: no early exit)
@@ -66,6 +70,7 @@ struct GroupDesc {
   int Np;
   int n_valid;
   int add_identity;
+  int outT_ident;  // outT = out^T + I (see NTParams)
   int tile_start;  // first work-list index of this request
 };
 
@@ -104,8 +109,10 @@ bool nt_config_valid(int prec, int cfg, int64_t np);  // cfg usable at padded si
 hipError_t launch_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed, hipStream_t s);
 int64_t padded_size_for(int prec, int64_t n);
 
+// ident: bit 0 adds the identity (first n constants) to Aop, bit 1 to ATop;
+// the ones counted are those of A alone.
 hipError_t launch_ingest(int prec, const uint8_t* A, int64_t lda, int n, int Np, int8_t* A8,
-                         int8_t* AT8, void* Aop, void* ATop, unsigned long long* ones_slot,
+                         int8_t* AT8, void* Aop, void* ATop, int ident, unsigned long long* ones_slot,
                          hipStream_t s);
 hipError_t launch_identity(int prec, void* S, int Np, int n, hipStream_t s);
 hipError_t launch_emit(int prec, const void* S, int Np, int transpose, int n, uint8_t* R,

@@ -190,32 +190,34 @@ class Fix {
     uint8_t* op[4];
     for (int i = 0; i < 4; ++i) op[i] = sl_.ws + i * matT;
     DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
-    // Addend: the previous iterate itself instead of A (plain: A^T), which
-    // gives the same iterates: R^(k) = A + f(R^(k-1)) lies inside
+    // The closure steps add the previous iterate instead of A (plain: A^T),
+    // which gives the same iterates: R^(k) = A + f(R^(k-1)) lies inside
     // A + f(R^(k)) because f is monotone and R^(k-1) <= R^(k), and it
-    // contains A; so A + f(R^(k)) = R^(k) + f(R^(k)).  No separate addend is
-    // written or read; in other precisions than int8 the epilogue reads the
-    // iterate's elements as flags (add_op).
+    // contains A; so A + f(R^(k)) = R^(k) + f(R^(k)).  That sum is one
+    // product once the right operand carries the identity: R R + R =
+    // R (R + I) for squaring (Y = R^T + I, written by each step as its
+    // transposed output), S A^T + S = S (A + I)^T for the plain series
+    // (Y = A + I, written at ingest); no addend is read.
     if (mode_ == M_PLAIN) {
-      // state S = R^T; S^(1) = A^T; product operand Y = A
+      // state S = R^T; S^(1) = A^T; product operand Y = A + I
       Yop_ = op[0];
       S_[0] = op[1];
       S_[1] = op[2];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, S_[1], sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, S_[1], 1, sl_.ring + 1, s_));
     } else if (mode_ == M_SQUARE) {
-      // R^(1) = A with its transpose
+      // R^(1) = A and R^(1)T + I
       S_[0] = op[0];
       ST_[0] = op[1];
       S_[1] = op[2];
       ST_[1] = op[3];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, S_[1], ST_[1], sl_.ring + 1, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, S_[1], ST_[1], 2, sl_.ring + 1, s_));
     } else {
       // P in operand precision; S^(1) = I; intermediate T
       Yop_ = op[0];
       S_[0] = op[1];
       S_[1] = op[2];
       Tmp_ = op[3];
-      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, nullptr, nullptr, s_));
+      DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, nullptr, 0, nullptr, s_));
       DL_HIP(launch_identity(prec_, S_[1], (int)Np_, (int)n_, s_));
       DL_HIP(launch_ring_set(sl_.ring, 1, (unsigned long long)n_, s_));
     }
@@ -290,27 +292,27 @@ class Fix {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       NTParams& p = p_;
       p.step = (int)t;
-      const int8_t* add = (const int8_t*)S_[prev];  // the previous iterate is the addend
-      p.add_op = prec_ != P_I8 ? 1 : 0;
+      p.add = nullptr;
+      p.outT_ident = 0;
       if (mode_ == M_PLAIN) {
-        p.X = S_[prev]; p.Y = Yop_; p.add = add; p.add_identity = 0;
+        p.X = S_[prev]; p.Y = Yop_; p.add_identity = 0;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
         int ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
       } else if (mode_ == M_SQUARE) {
-        p.X = S_[prev]; p.Y = ST_[prev]; p.add = add; p.add_identity = 0;
-        p.out = S_[cur]; p.outT = ST_[cur]; p.count = 1; p.check = 1;
+        p.X = S_[prev]; p.Y = ST_[prev]; p.add_identity = 0;
+        p.out = S_[cur]; p.outT = ST_[cur]; p.outT_ident = 1; p.count = 1; p.check = 1;
         int ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
       } else {
-        p.X = Yop_; p.Y = S_[prev]; p.add = nullptr; p.add_identity = 0;
+        p.X = Yop_; p.Y = S_[prev]; p.add_identity = 0;
         p.out = Tmp_; p.outT = nullptr; p.count = 0; p.check = 1;
         int ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
-        p.X = Tmp_; p.Y = Yop_; p.add = nullptr; p.add_identity = 1;
+        p.X = Tmp_; p.Y = Yop_; p.add_identity = 1;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
         ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
@@ -589,14 +591,13 @@ int dl_tune(dl_ctx* ctx, int prec, int64_t n, int32_t* cfg_out, double* ms_out, 
   for (int i = 0; i < 4; ++i) op[i] = base + i * matT;
   uint8_t* raw = base + 4 * matT;
   DL_HIP(launch_hash_bool(raw, Np, (int)n, (int)Np, 0x5eedu, s));
-  DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, nullptr, nullptr, op[0], op[1], nullptr, s));
-  NTParams p{};
+  DL_HIP(launch_ingest(prec, raw, Np, (int)n, (int)Np, nullptr, nullptr, op[0], op[1], 2, nullptr, s));
+  NTParams p{};  // a squaring step, as the fixpoint driver launches it
   p.X = op[0];
   p.Y = op[1];
-  p.add = (const int8_t*)op[0];  // the previous iterate, as in the fixpoint driver's steps
-  p.add_op = prec != P_I8 ? 1 : 0;
   p.out = op[2];
   p.outT = op[3];
+  p.outT_ident = 1;
   p.ld = Np;
   p.Np = (int)Np;
   p.n_valid = (int)n;

@@ -904,7 +904,7 @@ int dl_program_run(dl_program* g, int method, void* stream) {
     if (g->kind[p] == K_GIVEN) {
       rc = r.alloc_mat(&g->val[p], true);
       if (!rc && launch_ingest(P_I8, g->bound[p], g->bound_ld[p], (int)g->n, (int)r.Np, g->val[p].M, g->val[p].T,
-                               nullptr, nullptr, nullptr, s) != hipSuccess)
+                               nullptr, nullptr, 0, nullptr, s) != hipSuccess)
         rc = perr(DL_EHIP, "ingest failed");
     } else if (g->kind[p] == K_EQ) {
       rc = r.alloc_mat(&g->val[p], true);

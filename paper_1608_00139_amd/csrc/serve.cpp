@@ -320,8 +320,9 @@ int admit(dl_batch* b, int kind, int64_t n, int64_t tag, int32_t* slot_out, hipS
   if (kind == 0) {
     for (int i = 0; i < 4; ++i) r.b[i] = base + m * i;  // R0, R0T, R1, R1T
     if (!deferred) BHIP(launch_ring_clear(adm, nullptr, 0, 1, 0, s));
-    // R^(1) = A and R^(1)T = A^T; each squaring step takes its previous
-    // iterate as the addend (R + R R = A + R R along the iteration)
+    // R^(1) = A and R^(1)T = A^T + I: a squaring step computes
+    // [R (R^T + I)^T] = [R R + R] (= [A + R R] along the iteration) and
+    // writes the next R^T + I as its transposed output
     int rc = fill(n, Np, (int8_t*)base, (int8_t*)r.b[2], (int8_t*)r.b[3], adm);
     if (rc) {
       pool_free(b, off, bytes);
@@ -356,9 +357,9 @@ int dl_batch_submit(dl_batch* b, int kind, int64_t n, const uint8_t* A, int64_t 
   hipStream_t s = (hipStream_t)stream;
   return admit(b, kind, n, tag, slot_out, s, false,
                [&](int64_t nn, int64_t Np, int8_t* base, int8_t* M, int8_t* MT, unsigned long long* ones) -> int {
-                 // closure: M = R^(1), MT = R^(1)T; same generation: M = P
+                 // closure: M = R^(1), MT = R^(1)T + I; same generation: M = P
                  (void)base;
-                 BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, nullptr, nullptr, M, MT, ones, s));
+                 BHIP(launch_ingest(P_I8, A, lda, (int)nn, (int)Np, nullptr, nullptr, M, MT, kind == 0 ? 2 : 0, ones, s));
                  return DL_OK;
                });
 }
@@ -371,11 +372,12 @@ int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges
                [&](int64_t nn, int64_t Np, int8_t* base, int8_t* M, int8_t* MT, unsigned long long* ones) -> int {
                  const long long mb = (long long)Np * Np;
                  // the request's buffers are contiguous from base: closure
-                 // clears R0, R0T, R1, R1T; same generation P, S0 and S1 = I
+                 // clears R0, R0T, R1 and R1T = I (before the edges' A^T);
+                 // same generation P, S0 and S1 = I
                  AdmitDesc a{};
                  a.base = base;
                  a.clear_units = (kind == 0 ? 4 : 3) * mb / 16;
-                 a.ident_off = kind == 0 ? -1 : 2 * mb;
+                 a.ident_off = kind == 0 ? 3 * mb : 2 * mb;
                  a.M = M;
                  a.M2 = nullptr;
                  a.MT = MT;
@@ -453,7 +455,7 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       g.X = r.b[2 * prev];
       g.Y = r.b[2 * prev + 1];
-      g.add = (const int8_t*)r.b[2 * prev];  // the previous iterate is the addend
+      g.outT_ident = 1;  // the next step's right operand R^T + I
       g.out = r.b[2 * cur];
       g.outT = r.b[2 * cur + 1];
       g.cnt = cnt + i;
@@ -688,7 +690,7 @@ int dl_batch_tune(dl_batch* b, const int64_t* sizes_in, int32_t k, int32_t* tile
           std::memset(&g, 0, sizeof g);
           g.X = base;
           g.Y = base + m;
-          g.add = (const int8_t*)base;
+          g.outT_ident = 1;
           g.out = base + 2 * m;
           g.outT = base + 3 * m;
           g.cnt = dcnt;
