@@ -514,7 +514,8 @@ def run_serving(dl, torch, count: int, seed: int = 0):
     [64, 2048], ER p = 3/n or random forests.  A closed-loop burst of
     min(count, 2000) requests (all arriving at t = 0) measures the saturated
     throughput; then `count` requests arrive as a Poisson process at 0.8x that
-    rate and are served with continuous batching.  Latency = completion -
+    rate and are served with continuous batching (and, for the latency curve,
+    up to 3000 more at 0.5x and at 0.95x).  Latency = completion -
     arrival.  Relations are generated as edge lists before the run, kept on
     the device, and built into the request's buffers by the library's
     edge-list admission (dl_batch_submit_edges)."""
@@ -564,7 +565,21 @@ def run_serving(dl, torch, count: int, seed: int = 0):
         per_step = 2.0 if c.kind == 1 else 1.0
         ops += per_step * 2.0 * ((c.n + 63) // 64 * 64) ** 3 * (c.iters - 1)
     out = st.summary()
-    out.update({"offered_rate": round(rate, 1), "saturation": sat,
+    # latency at lighter and heavier load: shorter streams at 0.5x and 0.95x
+    # the saturated rate (the 0.8x stream above is the headline)
+    sweep = []
+    for k, frac in enumerate((0.5, 0.8, 0.95)):
+        if frac == 0.8:
+            s_ = out
+        else:
+            sw = dlgen.serving_stream(min(count, 3000), seed + 2 + k, rate=frac * sat["req_per_s"])
+            log(f"serving: Poisson stream of {len(sw)} at {frac}x saturation")
+            sx, _ = run_stream(sw, prepare(sw), pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+            s_ = sx.summary()
+        sweep.append({"offered_frac": frac, "offered_rate": round(frac * sat["req_per_s"], 1),
+                      "requests": s_["requests"], "req_per_s": s_["req_per_s"],
+                      "p50_ms": s_["p50_ms"], "p99_ms": s_["p99_ms"]})
+    out.update({"offered_rate": round(rate, 1), "saturation": sat, "load_sweep": sweep,
                 "tiles": [{"n": e["n"], "tile": e["tile"], "us_per_product_64_128_256": [round(x * 1e3, 2) for x in e["ms"]]}
                           for e in tiles],
                 "eff_tops_padded": round(ops / st.wall / 1e12, 2),

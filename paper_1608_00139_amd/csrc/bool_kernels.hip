@@ -916,14 +916,29 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   return cnt;
 }
 
+// Operand panels of the tile a persistent workgroup takes next: X from its
+// first output row, Y from its first output column, row pitch in bytes.
+struct DmaPanels {
+  const uint8_t* X = nullptr;
+  const uint8_t* Y = nullptr;
+  int64_t ldb = 0;
+};
+
 // One BM x BN output tile (tm, tn) of the direct-to-LDS product; the whole
 // workgroup calls it.  smem holds the LDS ring (and the epilogue tile).
+// A persistent caller may pass the panels of its next tile: once this tile's
+// last slice is being multiplied, the next tile's first slice is fetched into
+// ring slot 0 and the epilogue stages its transpose in slot 1, so that fetch
+// overlaps the epilogue.  Returns whether it did; the caller passes that as
+// `pre` for the next tile, whose slice 0 is then already in flight.
+// tid is threadIdx.x (a persistent caller passes it through an opaque move
+// each tile, so that nothing derived from it is kept live across tiles).
 template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
-__device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, uint8_t* smem) {
+__device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, uint8_t* smem, int tid,
+                                            bool pre = false, DmaPanels next = DmaPanels()) {
   typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
   const int row0 = tm * BM, col0 = tn * BN;
   const int64_t ldb = p.ld * K::NIB / 2;
@@ -931,14 +946,20 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
   const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
   const int nk = (int)(ldb / KB);
 
-  // per-lane source address of each of this wave's DMA instructions
-  const uint8_t* src[K::DMA_PER_WAVE];
-#pragma unroll
-  for (int j = 0; j < K::DMA_PER_WAVE; ++j) {
+  // per-lane source address of DMA instruction j of this wave in panels
+  // (Xb, Yb) of row pitch lb
+  auto lane_src = [&](const uint8_t* Xb, const uint8_t* Yb, int64_t lb, int j) {
     const int r = (wave + j * K::NWAVES) * K::ROWS_PER_DMA + lane / K::KC;  // X rows then Y rows
     const int c = (lane % K::KC) ^ rsw<K::KC>(r);
-    src[j] = ((r < BM) ? (Xg + (int64_t)r * ldb) : (Yg + (int64_t)(r - BM) * ldb)) + c * 16;
-  }
+    return ((r < BM) ? (Xb + (int64_t)r * lb) : (Yb + (int64_t)(r - BM) * lb)) + c * 16;
+  };
+  const uint8_t* src[K::DMA_PER_WAVE];
+#pragma unroll
+  for (int j = 0; j < K::DMA_PER_WAVE; ++j) src[j] = lane_src(Xg, Yg, ldb, j);
+  // the next tile's slice 0 goes to slot 0 while this tile's last slice
+  // (slot 1: nk even) is multiplied and its epilogue uses slot 1
+  constexpr bool CAN_PREFETCH = K::SWAPPED && NSTAGE == 2 && (size_t)BM * BN <= K::STAGE_BYTES;
+  const bool prefetch = CAN_PREFETCH && next.X != nullptr && nk % 2 == 0;
   auto issue = [&](int kt) {
     uint8_t* stage = smem + (kt % NSTAGE) * K::STAGE_BYTES;
 #pragma unroll
@@ -998,10 +1019,10 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
     }
   };
 
-  // prologue: NSTAGE - 1 slices in flight
+  // prologue: NSTAGE - 1 slices in flight (slice 0 may be in flight already)
 #pragma unroll
   for (int s0 = 0; s0 < NSTAGE - 1; ++s0)
-    if (s0 < nk) issue(s0);
+    if (s0 < nk && !(pre && s0 == 0)) issue(s0);
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's DMA for slice kt has landed once at most the later
     // slices' instructions are outstanding; the barrier extends that to
@@ -1010,14 +1031,27 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
     else wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
     if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+    if (prefetch && kt == nk - 1) {
+#pragma unroll
+      for (int j = 0; j < K::DMA_PER_WAVE; ++j)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)lane_src(next.X, next.Y,
+                                                                                               next.ldb, j),
+                                         (__attribute__((address_space(3))) void*)(smem + (wave + j * K::NWAVES) * 1024),
+                                         16, 0, 0);
+    }
     compute(kt % NSTAGE);
   }
-  wait_vmcnt<0>();
-  __syncthreads();
+  if (prefetch) {
+    __builtin_amdgcn_s_barrier();  // every wave is done reading slot 1; the next slice 0 stays in flight
+  } else {
+    wait_vmcnt<0>();
+    __syncthreads();
+  }
 
   int cnt = 0;
   if constexpr (K::SWAPPED) {
-    cnt = dma_epilogue_swapped<K, Op>(p, acc, smem, row0, col0, wm, wn, lane, tid);
+    cnt = dma_epilogue_swapped<K, Op>(p, acc, prefetch ? smem + K::STAGE_BYTES : smem, row0, col0, wm, wn, lane,
+                                      tid);
   } else {
     // ---- epilogue of k_nt_step: the 0/1 tile through LDS byte by byte
     constexpr int SEG_PER_ROW = BN / 16;
@@ -1087,6 +1121,7 @@ __device__ __forceinline__ void nt_dma_tile(const NTParams& p, int tm, int tn, u
       if (t) atomicAdd(p.ones + (p.step % kRing), t);
     }
   }
+  return prefetch;
 }
 
 template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
@@ -1097,25 +1132,38 @@ k_nt_dma(NTParams p) {
   if (step_is_done(p)) return;
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
-  nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem);
+  nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem, (int)threadIdx.x);
 }
 
 // Grouped serving step with the direct-to-LDS 256 x 256 tiles (requests with
 // Np a multiple of 256): one workgroup per CU walks the concatenated tile
-// lists as k_group_step does.
+// lists as k_group_step does, fetching each next tile's first K slice while
+// it finishes the current one.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
-    int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
+  auto find = [&](int item) {  // last request whose first tile is <= item
+    int lo = 0, hi = nreq - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (desc[mid].tile_start <= item) lo = mid;
       else hi = mid - 1;
     }
-    const GroupDesc& g = desc[lo];
+    return lo;
+  };
+  bool pre = false;  // this tile's first slice is in flight already
+  for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
+    const GroupDesc& g = desc[find(item)];
     const int local = item - g.tile_start;
     const int tiles_n = g.Np / 256;
+    DmaPanels next;
+    if (item + (int)gridDim.x < total_tiles) {
+      const GroupDesc& h = desc[find(item + gridDim.x)];
+      const int nl = item + gridDim.x - h.tile_start, nt = h.Np / 256;
+      next.ldb = h.Np;
+      next.X = (const uint8_t*)h.X + (int64_t)(nl / nt) * 256 * h.Np;
+      next.Y = (const uint8_t*)h.Y + (int64_t)(nl % nt) * 256 * h.Np;
+    }
     NTParams p{};
     p.X = g.X;
     p.Y = g.Y;
@@ -1131,7 +1179,9 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.count = g.cnt != nullptr;
     p.step = 0;
     __syncthreads();  // the previous tile's epilogue is done with LDS
-    nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, local / tiles_n, local % tiles_n, smem);
+    int tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    pre = nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, local / tiles_n, local % tiles_n, smem, tid, pre, next);
   }
 }
 
