@@ -345,11 +345,10 @@ struct NTKernel {
 // whole workgroup must call it (it synchronises through LDS).
 template <int BM, int BN, int WM, int WN, int KB, class Op, int SWZ, int PREF>
 __device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
-                                        unsigned long long* cnt_dst, uint8_t* smem) {
+                                        unsigned long long* cnt_dst, uint8_t* smem, int tid) {
   typedef NTKernel<BM, BN, WM, WN, KB, Op, SWZ, PREF> K;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
   const int64_t ldb = p.ld * K::NIB / 2;  // row pitch in bytes
   const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
@@ -539,7 +538,7 @@ k_nt_step(NTParams p) {
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
   nt_tile<BM, BN, WM, WN, KB, Op, SWZ, PREF>(p, tm * BM, tn * BN, p.count ? p.ones + (p.step % kRing) : nullptr,
-                                             smem);
+                                             smem, (int)threadIdx.x);
 }
 
 // ----------------------------------------------------------------- small relations
@@ -702,7 +701,9 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.out = g.out;
     p.outT = g.outT;
     __syncthreads();  // the previous tile's epilogue is done with LDS
-    nt_tile<T, T, T / 2, T / 2, 64, OpI8, 2, 1>(p, tm * T, tn * T, g.cnt, smem);
+    int tid;  // re-derived per tile: nothing computed from it stays live across tiles
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    nt_tile<T, T, T / 2, T / 2, 64, OpI8, 2, 1>(p, tm * T, tn * T, g.cnt, smem, tid);
   }
 }
 
