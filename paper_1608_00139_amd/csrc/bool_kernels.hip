@@ -917,6 +917,10 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   return cnt;
 }
 
+// Persistent grid of the direct-to-LDS step: the device's compute units,
+// rounded down to a multiple of 8 (set by bool_kernels_init).
+static int g_cus = 256;
+
 // Operand panels of the tile a persistent workgroup takes next: X from its
 // first output row, Y from its first output column, row pitch in bytes.
 struct DmaPanels {
@@ -1131,9 +1135,29 @@ __attribute__((amdgpu_waves_per_eu(1, ((BM / WM) * (BN / WN) + 3) / 4 > 2 ? ((BM
 k_nt_dma(NTParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   if (step_is_done(p)) return;
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
-  nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem, (int)threadIdx.x);
+  // Persistent: workgroup b takes the tiles of blocks b, b + G, b + 2G, ...
+  // (G = gridDim.x, a multiple of 8 when it is below the tile count, so
+  // each block keeps the XCD that tile_coords assigns it) and fetches each
+  // next tile's first slice during the current tile's epilogue.
+  const int T = p.tiles_m * p.tiles_n;
+  const int64_t ldb = p.ld * elem_nibbles(Op::kPrec) / 2;
+  bool pre = false;
+  for (int v = blockIdx.x; v < T; v += gridDim.x) {
+    int tm, tn;
+    tile_coords(v, T, p.tiles_m, p.tiles_n, tm, tn);
+    DmaPanels next;
+    if (v + (int)gridDim.x < T) {
+      int tm2, tn2;
+      tile_coords(v + gridDim.x, T, p.tiles_m, p.tiles_n, tm2, tn2);
+      next.X = (const uint8_t*)p.X + (int64_t)tm2 * BM * ldb;
+      next.Y = (const uint8_t*)p.Y + (int64_t)tn2 * BN * ldb;
+      next.ldb = ldb;
+    }
+    __syncthreads();  // the previous tile's epilogue is done with LDS
+    int tid;          // re-derived per tile: nothing computed from it stays live across tiles
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    pre = nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem, tid, pre, next);
+  }
 }
 
 // Grouped serving step with the direct-to-LDS 256 x 256 tiles (requests with
@@ -1189,7 +1213,9 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
 template <class Op, int BM, int BN, int WM, int WN, int KB, int NSTAGE>
 static hipError_t launch_dma(const NTParams& p, hipStream_t s) {
   typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
-  const int grid = p.tiles_m * p.tiles_n;
+  // one workgroup per compute unit (a multiple of 8), or one per tile
+  const int tiles = p.tiles_m * p.tiles_n;
+  const int grid = tiles > g_cus ? g_cus : tiles;
   hipLaunchKernelGGL((k_nt_dma<BM, BN, WM, WN, KB, Op, NSTAGE>), dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p);
   return hipGetLastError();
 }
@@ -1277,6 +1303,10 @@ size_t group_dma_lds() { return DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_B
 
 hipError_t bool_kernels_init() {
   hipError_t e;
+  int dev = 0, cus = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  g_cus = cus >= 8 ? cus / 8 * 8 : 8;
   if ((e = hipFuncSetAttribute((const void*)k_group_dma, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)group_dma_lds())) != hipSuccess)
     return e;
