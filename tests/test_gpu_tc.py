@@ -334,6 +334,23 @@ def test_tile_configs_sizes(dl):
             _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
 
 
+def test_persistent_uneven_passes(dl):
+    """n = 4300 (Np = 4352, 17 x 17 = 289 tiles of 256): the persistent step
+    kernel's workgroups take one or two tiles, the second with its first
+    slice fetched during the first's epilogue; both methods, the int8 and
+    the operand-format paths, and same generation on the same sizes."""
+    n = 4300
+    a = dlgen.to_dense(n, dlgen.er_edges(n, 2.5 / n, 43))
+    for prec in ("i8", "bf16", "fp8"):
+        _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "persistent")
+    _check_closure(dl, a, dl.DL_TC_PLAIN, "i8", "persistent")
+    p = dlgen.to_dense(n, dlgen.forest_edges(n, 44))
+    sg_ref, _, sg_it, _ = oracle.sg_seminaive(p)
+    announce("sg persistent", n)
+    s, it = dl.dl_sg(dev(p), prec="i8")
+    assert np.array_equal(host(s), sg_ref) and it == sg_it
+
+
 def test_config_chung_lu_n32768(dl):
     """Power-law digraph (Chung-Lu, gamma 2.1, mean out-degree 8), n = 32768:
     int8 repeated squaring on 1 GiB matrices, the whole model compared.
