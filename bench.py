@@ -16,7 +16,8 @@ time-to-fixpoint, the plain FP32 iteration and the fp64 epsilon solve on the
 same inputs (with their threshold errors against the int8 model), the bf16
 and fp8 variants, same generation at N = 4096 on random forests, the
 dominant kernel's roofline figures (HIP events inside the library, on the
-launch stream) and the CPU oracle on a bounded sample.
+launch stream, around the first product launch of each chunk of steps in
+the timed region) and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 

@@ -197,11 +197,15 @@ int dl_solve_two_sided(dl_ctx* ctx, int64_t n, const uint8_t* Q, int64_t ldq, co
 int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* eps_max,
                  void* stream);
 
-/* Kernel timing.  When enabled, the library brackets each launch of its
+/* Kernel timing.  When enabled, the library brackets launches of its
  * product kernels with HIP events on the call's stream and accumulates, per
- * kernel class, the number of launches that did work and their total
- * duration.  Classes: 0 = boolean product step (all precisions), 1 = fp64
- * trailing update of the epsilon solve, 2 = all other kernels. */
+ * kernel class, the number of timed launches that did work and their total
+ * duration.  The fixpoint calls (dl_tc, dl_tc_batch, dl_sg) time the first
+ * product of each chunk of steps they enqueue, so that the other launches
+ * run back to back (an event pair between two launches adds about 10 us);
+ * layered programs time every product.  Classes: 0 = boolean product step
+ * (all precisions), 1 = fp64 trailing update of the epsilon solve, 2 = all
+ * other kernels. */
 int dl_set_timing(dl_ctx* ctx, int enable);
 int dl_kernel_stats(dl_ctx* ctx, int kernel_class, int64_t* launches, double* total_ms,
                     int reset);

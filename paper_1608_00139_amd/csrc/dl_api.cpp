@@ -267,9 +267,9 @@ class Fix {
   void finish(int64_t* ones_out, int32_t* steps_out, int32_t* converged_out) {
     const int64_t last = computed_;
     if (c_->timing) {
-      // launches that did work: every product of steps 2 .. computed
-      const int per = (mode_ == M_SG) ? 2 : 1;
-      tm_.collect(0, (last >= 2 ? (last - 1) : 0) * per);
+      // the timed launches (one per chunk) did work when some product did:
+      // steps 2 .. computed
+      tm_.collect(0, last >= 2 ? (last - 1) : 0);
     }
     if (ones_out) {
       for (int64_t k = 0; k <= last; ++k) ones_out[k] = k < (int64_t)ones_.size() ? ones_[k] : 0;
@@ -294,29 +294,32 @@ class Fix {
       p.step = (int)t;
       p.add = nullptr;
       p.outT_ident = 0;
+      // timing samples the chunk's first product: it always does work (the
+      // chunk exists because the last read-back showed no repeat, except
+      // for an empty relation, which finish() leaves uncounted), and the
+      // others run back to back (events between launches cost ~10 us each)
+      const bool timed = t == s0_;
       if (mode_ == M_PLAIN) {
         p.X = S_[prev]; p.Y = Yop_; p.add_identity = 0;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 1;
-        int ev = tm_.begin(0);
+        int ev = timed ? tm_.begin(0) : -1;
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
       } else if (mode_ == M_SQUARE) {
         p.X = S_[prev]; p.Y = ST_[prev]; p.add_identity = 0;
         p.out = S_[cur]; p.outT = ST_[cur]; p.outT_ident = 1; p.count = 1; p.check = 1;
-        int ev = tm_.begin(0);
+        int ev = timed ? tm_.begin(0) : -1;
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
       } else {
         p.X = Yop_; p.Y = S_[prev]; p.add_identity = 0;
         p.out = Tmp_; p.outT = nullptr; p.count = 0; p.check = 1;
-        int ev = tm_.begin(0);
+        int ev = timed ? tm_.begin(0) : -1;
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
         tm_.end(ev);
         p.X = Tmp_; p.Y = Yop_; p.add_identity = 1;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
-        ev = tm_.begin(0);
         DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
-        tm_.end(ev);
       }
     }
     const int64_t upto = s0_ + cnt - 1;

@@ -334,6 +334,30 @@ def test_tile_configs_sizes(dl):
             _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
 
 
+def test_kernel_timing(dl):
+    """Timing on: one timed product per chunk of steps, none for an empty
+    relation; the model is the oracle's."""
+    ctx = dl.Context()
+    n = 600
+    path = np.zeros((n, n), np.uint8)
+    path[np.arange(n - 1), np.arange(1, n)] = 1  # D = n - 1: 12 squaring iterations
+    ctx.set_timing(True)
+    for a in (dlgen.to_dense(n, dlgen.er_edges(n, 1.0 / n, 9)), path):
+        ref, _, _, _ = oracle.tc_seminaive(a)
+        ctx.kernel_stats(0, reset=True)
+        announce("timing", n)
+        r, it = dl.dl_tc(dev(a), method=dl.DL_TC_SQUARE, prec="i8", ctx=ctx)
+        launches, ms = ctx.kernel_stats(0, reset=True)
+        assert np.array_equal(host(r), ref)
+        # chunks of the squaring schedule start at steps 2, 8, 12, 20, ...;
+        # one is enqueued while no repeat has been seen (it starts <= it)
+        assert launches == sum(1 for s0 in (2, 8, 12, 20, 36) if s0 <= it) and ms > 0.0
+    _, it0 = dl.dl_tc(dev(np.zeros((n, n), np.uint8)), method=dl.DL_TC_SQUARE, prec="i8", ctx=ctx)
+    assert it0 == 1 and ctx.kernel_stats(0, reset=True)[0] == 0
+    ctx.set_timing(False)
+    ctx.close()
+
+
 def test_persistent_uneven_passes(dl):
     """n = 4300 (Np = 4352, 17 x 17 = 289 tiles of 256): the persistent step
     kernel's workgroups take one or two tiles, the second with its first
