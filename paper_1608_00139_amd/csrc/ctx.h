@@ -8,11 +8,13 @@
 #include <string>
 #include <vector>
 
+#include "common.h"
 #include "eps_solve.h"
 
 // Fixpoints a batched call keeps in flight (each with its own workspace,
 // counters and read-back event).
 constexpr int kFixSlots = 2;
+constexpr size_t kSlotWords = (size_t)dl::kRing + 1;  // a slot's ring and its convergence step
 
 struct EventPair {
   hipEvent_t a, b;
@@ -32,11 +34,12 @@ struct dl_ctx {
   size_t budget = 0;
   void* ws = nullptr;  // main workspace
   size_t ws_size = 0;
-  unsigned long long* ring = nullptr;  // device rings of model sizes (kRing per fixpoint slot)
-  int* conv = nullptr;                 // device convergence steps (conv[4 i] for slot i)
+  unsigned long long* ring = nullptr;  // per fixpoint slot: kRing model sizes, then the slot's
+                                       // convergence step (an int in one more word)
+  int* conv = nullptr;                 // device scratch ints (eps bounds, solver flags)
   int* dscratch = nullptr;             // small device scratch (row max, ...)
-  unsigned long long* h_ring = nullptr;  // pinned host mirror of the rings
-  int* h_conv = nullptr;                 // pinned: conv steps (h_conv[4 i]), scratch ints
+  unsigned long long* h_ring = nullptr;  // pinned host mirror of the slots' rings and steps
+  int* h_conv = nullptr;                 // pinned scratch ints
   hipEvent_t slot_ev[kFixSlots] = {nullptr, nullptr};  // read-back events of the fixpoint slots
   bool timing = false;
   int64_t launches[3] = {0, 0, 0};

@@ -332,8 +332,7 @@ class Fix {
   // The ring holds the last kRing steps, more than one chunk, so every step
   // of the chunk just run is still present when the copy is read.
   int readback(int64_t upto) {
-    DL_HIP(hipMemcpyAsync(sl_.h_ring, sl_.ring, kRing * sizeof(unsigned long long), hipMemcpyDeviceToHost, s_));
-    DL_HIP(hipMemcpyAsync(sl_.h_conv, sl_.conv, sizeof(int), hipMemcpyDeviceToHost, s_));
+    DL_HIP(hipMemcpyAsync(sl_.h_ring, sl_.ring, kSlotWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s_));
     DL_HIP(hipEventRecord(sl_.ev, s_));
     pending_ = upto;
     return DL_OK;
@@ -411,10 +410,11 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
   for (int i = 0; i < nslots; ++i) {
     if (!c->slot_ev[i]) DL_HIP(hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming));
     slots[i].ws = (uint8_t*)c->ws + need * i;
-    slots[i].ring = c->ring + (size_t)kRing * i;
-    slots[i].conv = c->conv + 4 * i;
-    slots[i].h_ring = c->h_ring + (size_t)kRing * i;
-    slots[i].h_conv = c->h_conv + 4 * i;
+    // the slot's ring of model sizes, then its convergence step: one read-back
+    slots[i].ring = c->ring + kSlotWords * i;
+    slots[i].conv = (int*)(slots[i].ring + kRing);
+    slots[i].h_ring = c->h_ring + kSlotWords * i;
+    slots[i].h_conv = (int*)(slots[i].h_ring + kRing);
     slots[i].ev = c->slot_ev[i];
   }
   std::vector<Fix> jobs;
@@ -444,9 +444,13 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
   while (!rc && !inflight.empty()) {
     const int g = inflight.front();
     inflight.erase(inflight.begin());
-    hipError_t e = hipEventSynchronize(jobs[g].slot().ev);
+    // poll rather than block: the next chunk is enqueued as soon as the
+    // read-back lands (a blocking wait adds the thread's wake-up latency)
+    hipError_t e;
+    while ((e = hipEventQuery(jobs[g].slot().ev)) == hipErrorNotReady) {
+    }
     if (e != hipSuccess) {
-      rc = hip_fail(e, "hipEventSynchronize(read-back)");
+      rc = hip_fail(e, "hipEventQuery(read-back)");
       break;
     }
     if ((rc = jobs[g].advance())) break;
@@ -488,16 +492,16 @@ int dl_create(dl_ctx** out, int device, size_t budget) {
   };
   if ((e = hipSetDevice(device)) != hipSuccess) return cleanup(hip_fail(e, "hipSetDevice"));
   if ((e = bool_kernels_init()) != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
-  if ((e = hipMalloc(&c->ring, kFixSlots * kRing * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = hipMalloc(&c->ring, kFixSlots * kSlotWords * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(ring)"));
   if ((e = hipMalloc(&c->conv, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(conv)"));
   c->dscratch = c->conv + 16;
-  if ((e = hipHostMalloc(&c->h_ring, kFixSlots * kRing * sizeof(unsigned long long), hipHostMallocDefault)) !=
+  if ((e = hipHostMalloc(&c->h_ring, kFixSlots * kSlotWords * sizeof(unsigned long long), hipHostMallocDefault)) !=
       hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(ring)"));
   if ((e = hipHostMalloc(&c->h_conv, 64 * sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(conv)"));
-  if ((e = hipMemset(c->ring, 0, kFixSlots * kRing * sizeof(unsigned long long))) != hipSuccess)
+  if ((e = hipMemset(c->ring, 0, kFixSlots * kSlotWords * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemset(ring)"));
   if ((e = hipMemset(c->conv, 0, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMemset(conv)"));
   if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
