@@ -545,23 +545,30 @@ k_nt_step(NTParams p) {
 // Whole-K tiles for small n: a 32 x 32 output tile per workgroup whose 32 rows
 // of X and 32 rows of Y are fetched completely into LDS at once
 // (global_load_lds_dwordx4, all issued before the first wait), so the product
-// waits on memory once instead of once per K slice.  Four waves each own a
-// 16 x 16 block of the tile and alternate two accumulators over K.  LDS: row
+// waits on memory once instead of once per K slice.  Sixteen waves: four
+// groups of four, each wave of a group owning one 16 x 16 block of the tile,
+// group k taking every fourth K step from step k (four waves per SIMD hide
+// the LDS latency of the K loop); groups 1..3 leave their partial sums in
+// LDS and group 0 adds them (integer counts, exact also in fp32).  LDS: row
 // r (X rows 0..31, then Y rows) at r * ldb, its 16-byte chunk c stored at
 // c ^ (r & mask) (mask 15, or 7 when a row has fewer than 16 chunks), so the
-// 16 lanes that read one chunk of 16 rows hit distinct banks.  The epilogue
-// tile (32 x 48 bytes) follows the operands.
-constexpr int kSmallMaxLdb = 2048;  // largest row of operand bytes (LDS: 64 rows + epilogue)
+// 16 lanes that read one chunk of 16 rows hit distinct banks; then the
+// partial sums, then the epilogue tile (32 x 48 bytes).
+constexpr int kSmallMaxLdb = 2048;  // largest row of operand bytes (LDS: 64 rows + the rest)
 constexpr int kSmallEst = 48;
+constexpr int kSmallKS = 4;                    // K groups
+constexpr int kSmallThreads = 256 * kSmallKS;  // four waves per group
+constexpr int kSmallPart = (kSmallKS - 1) * 4 * 64 * 16;  // groups 1..3: 4 blocks x 64 lanes x 16 B
 
-size_t small_lds_bytes(int64_t ldb) { return (size_t)64 * ldb + 32 * kSmallEst; }
+size_t small_lds_bytes(int64_t ldb) { return (size_t)64 * ldb + kSmallPart + 32 * kSmallEst; }
 
 template <class Op>
-__global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
+__global__ void __launch_bounds__(kSmallThreads) k_nt_small(NTParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   if (step_is_done(p)) return;
   constexpr int NIB = elem_nibbles(Op::kPrec);
   constexpr int KSTEP_CHUNKS = (64 / Op::FR) * Op::CPL;
+  static_assert(Op::FR == 16 && Op::NI == 4 && sizeof(typename Op::Acc) == 16, "16 x 16 blocks, 16-byte sums");
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
   const int row0 = tm * 32, col0 = tn * 32;
@@ -573,7 +580,7 @@ __global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
   const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
   // 64 * kc chunks, 64 per DMA instruction: instruction i fills LDS chunks
   // [64 i, 64 i + 64), lane L the chunk at position q = 64 i + L
-  for (int i = wave; i < kc; i += 4) {
+  for (int i = wave; i < kc; i += kSmallThreads / 64) {
     const int q = 64 * i + lane;
     const int r = q / kc, pos = q % kc;
     const int c = pos ^ (r & mask);
@@ -583,14 +590,15 @@ __global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
   }
   __syncthreads();  // waits for every load of this workgroup (vmcnt(0)) and joins the waves
 
-  const int wm = wave >> 1, wn = wave & 1;
+  const int kg = wave >> 2, wq = wave & 3;  // K group, block of the tile
+  const int wm = wq >> 1, wn = wq & 1;
   const int g = lane / Op::FR, rf = lane % Op::FR;
   const int ra = 16 * wm + rf, rb = 32 + 16 * wn + rf;
   const uint8_t* xa = smem + (int64_t)ra * ldb;
   const uint8_t* yb = smem + (int64_t)rb * ldb;
-  typename Op::Acc acc0 = Op::zero(), acc1 = Op::zero();
+  typename Op::Acc acc = Op::zero();
   const int ksteps = kc / KSTEP_CHUNKS;
-  for (int ks = 0; ks < ksteps; ks += 2) {
+  for (int ks = kg; ks < ksteps; ks += kSmallKS) {
     u32x4 a[Op::CPL], b[Op::CPL];
 #pragma unroll
     for (int c = 0; c < Op::CPL; ++c) {
@@ -598,24 +606,22 @@ __global__ void __launch_bounds__(256) k_nt_small(NTParams p) {
       a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
       b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
     }
-    acc0 = Op::mma(a, b, acc0);
-    if (ks + 1 < ksteps) {
-#pragma unroll
-      for (int c = 0; c < Op::CPL; ++c) {
-        const int ch = (ks + 1) * KSTEP_CHUNKS + g * Op::CPL + c;
-        a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
-        b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
-      }
-      acc1 = Op::mma(a, b, acc1);
-    }
+    acc = Op::mma(a, b, acc);
   }
-  // 0/1 block into the epilogue tile
-  uint8_t* et = smem + 64 * ldb;
+  typename Op::Acc* part = (typename Op::Acc*)(smem + 64 * ldb);
+  if (kg > 0) part[((kg - 1) * 4 + wq) * 64 + lane] = acc;
+  __syncthreads();
+  uint8_t* et = smem + 64 * ldb + kSmallPart;
+  // group 0: the sums, as a 0/1 block into the epilogue tile
+  if (kg == 0) {
 #pragma unroll
-  for (int v = 0; v < Op::NI; ++v) {
-    int r, c;
-    Op::coord(lane, v, r, c);
-    et[(16 * wm + r) * kSmallEst + 16 * wn + c] = (Op::nz(acc0, v) || Op::nz(acc1, v)) ? 1 : 0;
+    for (int k = 0; k < kSmallKS - 1; ++k) acc += part[(k * 4 + wq) * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < Op::NI; ++v) {
+      int r, c;
+      Op::coord(lane, v, r, c);
+      et[(16 * wm + r) * kSmallEst + 16 * wn + c] = Op::nz(acc, v) ? 1 : 0;
+    }
   }
   __syncthreads();
   int cnt = 0;
@@ -654,7 +660,7 @@ template <class Op>
 static hipError_t launch_small(const NTParams& p, hipStream_t s) {
   const int64_t ldb = p.ld * elem_nibbles(Op::kPrec) / 2;
   if (ldb > kSmallMaxLdb || ldb % 128 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_nt_small<Op>, dim3(p.tiles_m * p.tiles_n), dim3(256), small_lds_bytes(ldb), s, p);
+  hipLaunchKernelGGL(k_nt_small<Op>, dim3(p.tiles_m * p.tiles_n), dim3(kSmallThreads), small_lds_bytes(ldb), s, p);
   return hipGetLastError();
 }
 
@@ -1293,7 +1299,7 @@ static TileCfg cfg_of(int cfg) {
   switch (cfg) {
     case 0: { typedef typename BigCfg<Op>::K K; return {256, 256, BigCfg<Op>::KB, K::NT, K::LDS_BYTES}; }
     case 3: { typedef DmaKernel<256, 256, 64, 64, 128, OpI8x32, 2> K; return {256, 256, 128, K::NT, K::LDS_BYTES}; }
-    case 4: return {32, 32, kSmallMaxLdb, 256, small_lds_bytes(kSmallMaxLdb)};
+    case 4: return {32, 32, kSmallMaxLdb, kSmallThreads, small_lds_bytes(kSmallMaxLdb)};
     case 1: { typedef NTKernel<128, 128, 64, 64, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {128, 128, KSMALL, K::NT, K::LDS_BYTES}; }
     default: { typedef NTKernel<64, 64, 32, 32, KSMALL, Op, (KSMALL == 64 ? 2 : 1)> K; return {64, 64, KSMALL, K::NT, K::LDS_BYTES}; }
   }
