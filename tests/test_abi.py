@@ -71,3 +71,15 @@ def test_tuning_document_round_trip():
         m.tuning_from_json('{"format": "other", "entries": []}')
     with pytest.raises(ValueError):
         m.tuning_from_json(m.tuning_to_json([{"prec": "f99", "np": 512, "cfg": 0}], "x"))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits at once with a message
+    (nothing is imported or launched)."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
