@@ -354,6 +354,33 @@ def test_large_requests_all_tile_sizes(dl, lookahead):
             assert iters == _alone(dl, r)[1], (r.rid, r.kind, r.n)
 
 
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_prefetch_across_requests(dl, lookahead):
+    """Ten requests of 1100 .. 2048 constants on 256 x 256 tiles: a round
+    holds up to 461 tiles for 256 workgroups, so workgroups take a second
+    tile, often of another request with another size, whose first slice they
+    fetch during the first tile's epilogue.  Every model and iteration count
+    is checked."""
+    import torch
+
+    from paper_1608_00139_amd.serve import run_stream
+
+    reqs = dlgen.serving_stream(10, seed=41, rate=0.0, n_lo=1100, n_hi=2048)
+    assert sum(((r.n + 255) // 256) ** 2 for r in reqs) > 256
+    assert len({(r.n + 255) // 256 for r in reqs}) > 2
+
+    def edges_of(r):
+        return torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda()
+
+    announce("serve prefetch", [r.n for r in reqs], lookahead)
+    stats, results = run_stream(reqs, edges_of, pool_bytes=1 << 31, max_active=16, keep_results=True,
+                                lookahead=lookahead, tiles=[{"n": 16384, "tile": 256}])
+    for r in reqs:
+        got, iters = results[r.rid]
+        assert np.array_equal(host(got), _oracle(r)), (r.rid, r.kind, r.n)
+        assert iters == _alone(dl, r)[1], (r.rid, r.kind, r.n)
+
+
 def test_config_serving_stream_10000(dl):
     """The serving configuration as the benchmark runs it: 10,000 requests
     (70% closure on ER p = 3/n, 30% same generation on forests, n
