@@ -922,6 +922,23 @@ int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream) {
 
 int dl_set_timing(dl_ctx* ctx, int enable) {
   if (!ctx) return fail(DL_EINVAL, "ctx is NULL");
+  if (enable) {
+    // event pairs made here rather than on the first launches they bracket
+    // (creating events between launches delays the launches behind them)
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    constexpr size_t kInitialPairs = 256;
+    while (ctx->events.size() < kInitialPairs) {
+      EventPair ep;
+      DL_HIP(hipEventCreate(&ep.a));
+      hipError_t e = hipEventCreate(&ep.b);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(ep.a);
+        return hip_fail(e, "hipEventCreate");
+      }
+      ctx->events.push_back(ep);
+    }
+  }
   ctx->timing = enable != 0;
   return DL_OK;
 }
