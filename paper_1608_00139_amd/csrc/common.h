@@ -107,6 +107,7 @@ int choose_nt_config(int prec, int64_t n);
 int nt_config_count(int prec);  // cfg ids are 0 .. count - 1
 bool nt_config_valid(int prec, int cfg, int64_t np);  // cfg usable at padded size np
 hipError_t launch_hash_bool(uint8_t* M, int64_t ld, int n, int Np, unsigned seed, hipStream_t s);
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t s);
 int64_t padded_size_for(int prec, int64_t n);
 
 // ident: bit 0 adds the identity (first n constants) to Aop, bit 1 to ATop;

@@ -38,7 +38,8 @@ struct dl_ctx {
                                        // convergence step (an int in one more word)
   int* conv = nullptr;                 // device scratch ints (eps bounds, solver flags)
   int* dscratch = nullptr;             // small device scratch (row max, ...)
-  unsigned long long* h_ring = nullptr;  // pinned host mirror of the slots' rings and steps
+  unsigned long long* h_ring = nullptr;  // pinned (coherent) host mirror of the slots' rings and steps
+  unsigned long long* h_ring_dev = nullptr;  // its device mapping, written by k_publish
   int* h_conv = nullptr;                 // pinned scratch ints
   hipEvent_t slot_ev[kFixSlots] = {nullptr, nullptr};  // read-back events of the fixpoint slots
   bool timing = false;

@@ -161,6 +161,7 @@ struct FixSlot {
   unsigned long long* ring = nullptr;    // device ring of model sizes
   int* conv = nullptr;                   // device convergence step
   unsigned long long* h_ring = nullptr;  // pinned copies read after `ev`
+  unsigned long long* h_ring_dev = nullptr;  // device mapping of h_ring
   int* h_conv = nullptr;
   hipEvent_t ev = nullptr;
 };
@@ -328,11 +329,12 @@ class Fix {
     return readback(upto);
   }
 
-  // Copy the ring and the convergence step to pinned memory after a chunk.
-  // The ring holds the last kRing steps, more than one chunk, so every step
-  // of the chunk just run is still present when the copy is read.
+  // Write the ring and the convergence step to pinned host memory after a
+  // chunk (a kernel: a runtime copy left a ~10 us gap before it).  The ring
+  // holds the last kRing steps, more than one chunk, so every step of the
+  // chunk just run is still present when the host reads it.
   int readback(int64_t upto) {
-    DL_HIP(hipMemcpyAsync(sl_.h_ring, sl_.ring, kSlotWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s_));
+    DL_HIP(launch_publish(sl_.ring, sl_.h_ring_dev, (int)kSlotWords, s_));
     DL_HIP(hipEventRecord(sl_.ev, s_));
     pending_ = upto;
     return DL_OK;
@@ -414,6 +416,7 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
     slots[i].ring = c->ring + kSlotWords * i;
     slots[i].conv = (int*)(slots[i].ring + kRing);
     slots[i].h_ring = c->h_ring + kSlotWords * i;
+    slots[i].h_ring_dev = c->h_ring_dev + kSlotWords * i;
     slots[i].h_conv = (int*)(slots[i].h_ring + kRing);
     slots[i].ev = c->slot_ev[i];
   }
@@ -496,9 +499,13 @@ int dl_create(dl_ctx** out, int device, size_t budget) {
     return cleanup(hip_fail(e, "hipMalloc(ring)"));
   if ((e = hipMalloc(&c->conv, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(conv)"));
   c->dscratch = c->conv + 16;
-  if ((e = hipHostMalloc(&c->h_ring, kFixSlots * kSlotWords * sizeof(unsigned long long), hipHostMallocDefault)) !=
-      hipSuccess)
+  // coherent: the device's writes of the read-back reach host memory without
+  // a cache in between; the slot event after them orders them for the host
+  if ((e = hipHostMalloc(&c->h_ring, kFixSlots * kSlotWords * sizeof(unsigned long long),
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(ring)"));
+  if ((e = hipHostGetDevicePointer((void**)&c->h_ring_dev, c->h_ring, 0)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipHostGetDevicePointer(ring)"));
   if ((e = hipHostMalloc(&c->h_conv, 64 * sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return cleanup(hip_fail(e, "hipHostMalloc(conv)"));
   if ((e = hipMemset(c->ring, 0, kFixSlots * kSlotWords * sizeof(unsigned long long))) != hipSuccess)

@@ -1,8 +1,9 @@
 // prog_kernels.hip -- elementwise kernels on int8 0/1 matrices (Np x Np,
 // row-major, zero padded): disjunction of relations, complement for negated
 // atoms (Sec. 8), transposed copies for converse atoms, the column-sum norm,
-// the edge-list scatter that admits serving requests, and the pseudo-random
-// relation the tile autotuner times its candidates on.
+// the edge-list scatter that admits serving requests, the fixpoint driver's
+// read-back into pinned host memory, and the pseudo-random relation the tile
+// autotuner times its candidates on.
 #include "common.h"
 
 namespace dl {
@@ -211,6 +212,22 @@ hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, lon
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+// dst[i] = src[i] for i < n, dst a device mapping of pinned host memory: the
+// fixpoint driver's read-back of a slot's model sizes and convergence step,
+// as an ordinary launch that follows the step launches without the gap a
+// runtime copy leaves before it.
+__global__ void __launch_bounds__(256) k_publish(const unsigned long long* __restrict__ src, unsigned long long* dst,
+                                                 int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_publish, dim3(blocks < 64 ? blocks : 64), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
 }
 
 // M[i][j] = a pseudo-random bit (density 1/2) for i, j < n, 0 in the padding
