@@ -214,10 +214,11 @@ hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, lon
   return hipSuccess;
 }
 
-// dst[i] = src[i] for i < n, dst a device mapping of pinned host memory: the
-// fixpoint driver's read-back of a slot's model sizes and convergence step,
-// as an ordinary launch that follows the step launches without the gap a
-// runtime copy leaves before it.
+// dst[i] = src[i] for i < n 8-byte words, one side a device mapping of
+// coherent pinned host memory: the fixpoint driver's read-back of a slot's
+// model sizes and convergence step, and the serving rounds' descriptor
+// uploads and counter read-backs, as ordinary launches that follow the step
+// launches without the gap a runtime copy leaves before it.
 __global__ void __launch_bounds__(256) k_publish(const unsigned long long* __restrict__ src, unsigned long long* dst,
                                                  int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = src[i];

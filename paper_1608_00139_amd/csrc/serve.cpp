@@ -118,12 +118,16 @@ struct dl_batch {
   std::vector<Req> req;
   // two sets (alternating rounds) of everything a round reads or writes:
   GroupDesc* d_desc = nullptr;  // device descriptors [max] per set: the 256-, 128- and 64-tile lists in turn
-  GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout
+  GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout (coherent, device-mapped:
+                                // a kernel moves them, see move_words)
+  GroupDesc* h_desc_dev = nullptr;  // device mapping of h_desc
   unsigned long long* d_cnt = nullptr;  // per set: round counters [max], then admission counters [max]
-  unsigned long long* h_cnt = nullptr;  // pinned copy, same layout
+  unsigned long long* h_cnt = nullptr;  // pinned copy, same layout (coherent, device-mapped)
+  unsigned long long* h_cnt_dev = nullptr;  // device mapping of h_cnt
   std::vector<unsigned long long> last;  // per set: round counters as read back in its previous round
   AdmitDesc* d_adm = nullptr;   // grouped admission descriptors [max] per set
-  AdmitDesc* h_adm = nullptr;   // pinned host copy
+  AdmitDesc* h_adm = nullptr;   // pinned host copy (coherent, device-mapped)
+  AdmitDesc* h_adm_dev = nullptr;  // device mapping of h_adm
   hipEvent_t ev[2] = {nullptr, nullptr};  // end of each set's read-back
   std::vector<AdmitDesc> pend;  // edge-list requests admitted since the last round
   // tile table: requests with n <= tile_n[i] (the first such i) use tile_t[i]
@@ -192,6 +196,13 @@ size_t request_bytes(int kind, int64_t Np) {
   return 4 * m;  // closure: R, R^T (two each); SG: P, S (two), T
 }
 
+// Move `bytes` (a multiple of 8) from src to dst on s with k_publish; one
+// side is a device mapping of coherent pinned host memory.
+hipError_t move_words(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  return launch_publish((const unsigned long long*)src, (unsigned long long*)dst, (int)(bytes / 8), s);
+}
+static_assert(sizeof(GroupDesc) % 8 == 0 && sizeof(AdmitDesc) % 8 == 0, "descriptors move as 8-byte words");
+
 // Detect the first repeat in the known model sizes.
 void settle(Req& r) {
   for (int64_t k = 1; k < (int64_t)r.ones.size(); ++k)
@@ -230,19 +241,26 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   b->free_list[0] = pool_bytes;
   if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
+  // host buffers the device reads or writes directly (k_publish moves them;
+  // runtime copies left a gap of ~10 us before each in the kernel trace)
+  constexpr unsigned kMapped = hipHostMallocMapped | hipHostMallocCoherent;
+  if ((e = hipHostMalloc(&b->h_desc, sizeof(GroupDesc) * 2 * max_active, kMapped)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned descriptor allocation failed"));
   if ((e = hipMalloc(&b->d_cnt, sizeof(unsigned long long) * 4 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "counter allocation failed"));
-  if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 4 * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_cnt, sizeof(unsigned long long) * 4 * max_active, kMapped)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned counter allocation failed"));
   if ((e = hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 4 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_EHIP, "counter clear"));
   b->last.assign((size_t)2 * max_active, 0ull);
   if ((e = hipMalloc(&b->d_adm, sizeof(AdmitDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "admission descriptor allocation failed"));
-  if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * 2 * max_active, hipHostMallocDefault)) != hipSuccess)
+  if ((e = hipHostMalloc(&b->h_adm, sizeof(AdmitDesc) * 2 * max_active, kMapped)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "pinned admission descriptor allocation failed"));
+  if (hipHostGetDevicePointer((void**)&b->h_desc_dev, b->h_desc, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&b->h_cnt_dev, b->h_cnt, 0) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&b->h_adm_dev, b->h_adm, 0) != hipSuccess)
+    return fail_destroy(bfail(DL_EHIP, "hipHostGetDevicePointer"));
   for (auto& ev : b->ev)
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
       return fail_destroy(bfail(DL_EHIP, "event creation failed"));
@@ -420,7 +438,7 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
       ha[i] = a;
     }
     b->pend.clear();
-    BHIP(hipMemcpyAsync(da, ha, sizeof(AdmitDesc) * na, hipMemcpyHostToDevice, s));
+    BHIP(move_words(b->h_adm_dev + (size_t)set * M, da, sizeof(AdmitDesc) * na, s));
     BHIP(launch_admit(da, na, units, edges, s));
   }
   // this round's work lists (256, 128 and 64 tiles, one after the other in
@@ -481,15 +499,14 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
     ++fill[li];
   }
   if (rd.items.empty()) return DL_OK;
-  BHIP(hipMemcpyAsync(dset, hset, sizeof(GroupDesc) * rd.items.size(), hipMemcpyHostToDevice, s));
+  BHIP(move_words(b->h_desc_dev + (size_t)set * M, dset, sizeof(GroupDesc) * rd.items.size(), s));
   for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
     if (!na[li]) continue;
     const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
     BHIP(launch_group_step(64 << li, dset + first[li], na[li], tiles[li], std::min(grid, tiles[li]), s));
   }
   // round and admission counters of the set in one read-back
-  BHIP(hipMemcpyAsync(b->h_cnt + (size_t)set * 2 * M, cnt, sizeof(unsigned long long) * 2 * M,
-                      hipMemcpyDeviceToHost, s));
+  BHIP(move_words(cnt, b->h_cnt_dev + (size_t)set * 2 * M, sizeof(unsigned long long) * 2 * M, s));
   BHIP(hipEventRecord(b->ev[set], s));
   rd.set = set;
   rd.seq = b->rounds_issued;
