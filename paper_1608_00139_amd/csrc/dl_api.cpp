@@ -190,7 +190,8 @@ class Fix {
     const size_t matT = (size_t)mat_bytes(prec_, Np_);
     uint8_t* op[4];
     for (int i = 0; i < 4; ++i) op[i] = sl_.ws + i * matT;
-    DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, 2, 1, s_));
+    // the whole ring, so that chunks need no clear until the steps wrap
+    DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, 0, kRing, 1, s_));
     // The closure steps add the previous iterate instead of A (plain: A^T),
     // which gives the same iterates: R^(k) = A + f(R^(k-1)) lies inside
     // A + f(R^(k)) because f is monotone and R^(k-1) <= R^(k), and it
@@ -288,7 +289,8 @@ class Fix {
   int chunk() {
     if (chunk_ == 0) chunk_ = mode_ == M_SQUARE ? 6 : 4;
     const int cnt = (int)std::min<int64_t>(chunk_, (int64_t)max_steps_ - s0_ + 1);
-    DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, (int)s0_, cnt, 0, s_));
+    // entries of steps >= kRing still hold the counts of kRing steps before
+    if (s0_ + cnt > kRing) DL_HIP(launch_ring_clear(sl_.ring, sl_.conv, (int)s0_, cnt, 0, s_));
     for (int64_t t = s0_; t < s0_ + cnt; ++t) {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       NTParams& p = p_;

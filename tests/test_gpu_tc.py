@@ -334,6 +334,20 @@ def test_tile_configs_sizes(dl):
             _check_closure(dl, a, dl.DL_TC_SQUARE, prec, "tiles")
 
 
+def test_plain_series_past_the_ring(dl):
+    """A directed path of 4500 constants: the plain series needs D + 1 = 4500
+    iterations, more steps than the 4096-entry ring of model sizes holds, so
+    later steps reuse (and first clear) ring entries.  The model has a closed
+    form: r(e_i, e_j) iff i < j."""
+    n = 4500
+    path = np.zeros((n, n), np.uint8)
+    path[np.arange(n - 1), np.arange(1, n)] = 1
+    announce("plain past the ring", n)
+    r, it = dl.dl_tc(dev(path), method=dl.DL_TC_PLAIN, prec="i8")
+    assert it == n
+    assert np.array_equal(host(r), np.triu(np.ones((n, n), np.uint8), 1))
+
+
 def test_kernel_timing(dl):
     """Timing on: one timed product per chunk of steps, none for an empty
     relation; the model is the oracle's."""
