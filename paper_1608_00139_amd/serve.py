@@ -122,6 +122,7 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
                                                 req.arrival, adm, fin))
             if keep:
                 results[req.rid] = (out, iters)
-    torch.cuda.synchronize()
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
     stats.wall = time.perf_counter() - t0
     return stats, results
