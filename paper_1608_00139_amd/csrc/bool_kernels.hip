@@ -1391,7 +1391,10 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
   // rows t / 8 + 32 k (k < 4), bytes 16 (t % 8) .. + 15 of the tile.  Np is
   // a multiple of 64: the last strip and tile may be 64 wide (parts beyond Np
   // are not written).
-  __shared__ uint8_t tile[128][128 + 16];
+  // row pitch 132 bytes: the transposed byte reads below (lanes 16 tile rows
+  // apart) spread over the banks (at most 2-way; a 144-byte pitch put 8
+  // lanes on one bank); rows are written as dwords
+  __shared__ __attribute__((aligned(16))) uint8_t tile[128][132];
   const int bi = blockIdx.y;
   const int tid = threadIdx.x;
   const int r0 = tid >> 3, c0 = (tid & 7) * 16;
@@ -1434,7 +1437,11 @@ k_ingest(const uint8_t* __restrict__ A, int64_t lda, int n, int Np, int8_t* A8, 
                              (ident & 1) ? with_diag(v[k], bi * 128 + r, bj * 128 + c0, n) : v[k]);
       }
       cnt += popc16(v[k]);  // zero outside [0, n) anyway
-      if (AT8 || ATop) *(u32x4*)&tile[r][c0] = v[k];
+      if (AT8 || ATop) {
+        unsigned* t = (unsigned*)&tile[r][c0];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) t[w] = v[k][w];
+      }
     }
     if (AT8 || ATop) {
       __syncthreads();
