@@ -147,9 +147,19 @@ int dl_sg_steps(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* 
  *        sum of the 0/1 matrix (Lemma 1); otherwise DL_EINVAL.
  *   X    optional device double [n x ldx] receiving the real solution
  *        (NULL to skip).
- *   iters is set to 0: the solve is direct, no fixpoint iteration. */
+ *   iters is set to 0: the solve is direct, no fixpoint iteration.
+ *   underflow (host int32, may be NULL) receives 1 when an entry of R may
+ *        be a false negative from fp64 underflow, else 0.  A true entry is
+ *        at least eps^L for a shortest path of length L (footnote to
+ *        Lemma 2), and along that path the entries of X shrink by at most a
+ *        factor eps per edge, so a true entry below the smallest normal
+ *        double (DBL_MIN) implies one in [DBL_MIN, DBL_MIN / eps), computed
+ *        accurately.  The flag is set when the smallest positive entry of X
+ *        is below 2 DBL_MIN / eps; 0 guarantees R is the least model.  The
+ *        flag is set for some inputs whose R is still exact (it is
+ *        conservative), never missed for one whose R is not. */
 int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double eps, uint8_t* R,
-                 int64_t ldr, double* X, int64_t ldx, int32_t* iters, void* stream);
+                 int64_t ldr, double* X, int64_t ldx, int32_t* iters, int32_t* underflow, void* stream);
 
 /* Same-generation epsilon form (Sec. 7.2): solves X = eps (I + P X P^T), a
  * discrete Sylvester (Stein) equation (Sec. 6.3), in fp64 by Smith's

@@ -11,6 +11,8 @@ What it computes, each piece with the passage it follows:
   Because DB1 is linear, the facts after round k equal the matrix iterate
   R^(k) of the series R^(0)=0, R^(k+1)=min1(R1 + R1 R^(k)) (Sec. 3), so
   the per-round counts double as per-step counts of that series.
+* ``tc_seminaive_edges`` -- the same rounds from an edge list, with the
+  rounds alone timed (the CPU baseline's timed region).
 * ``tc_square_literal`` -- the series R^(k+1)=min1(R1 + R^(k) R^(k)) of the
   non-linear closure program in Sec. 8, step by step with Boolean rows.
 * ``bfs`` -- one breadth-first search per source: reachability and the
@@ -53,6 +55,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
+_default_threads = 1
 
 
 def _load():
@@ -76,12 +79,24 @@ def _load():
         lib.or_bfs.restype = ctypes.c_int
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_tc_seminaive_edges.argtypes = [i64, i64, ctypes.c_void_p, ctypes.c_int, pu8, pi64, pi64,
+                                              ctypes.c_void_p, ctypes.c_void_p]
+        lib.or_tc_seminaive_edges.restype = ctypes.c_int
+        global _default_threads
+        _default_threads = int(lib.or_num_threads())
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def default_threads() -> int:
+    """OpenMP's thread count when the library was loaded (OMP_NUM_THREADS,
+    else every core the process may use): the all-core setting."""
+    _load()
+    return _default_threads
 
 
 def _as_u8(a) -> np.ndarray:
@@ -123,6 +138,29 @@ def tc_seminaive(a, maxsteps: int | None = None):
     iterate R^(k) of the plain series and ``converged`` is False.
     """
     return _iterate("or_tc_seminaive", a, maxsteps)
+
+
+def tc_seminaive_edges(n: int, edges, threads: int = 0, want_model: bool = True):
+    """Closure of the relation given as an edge list ([m, 2] pairs (i, j)),
+    by the same semi-naive rounds as ``tc_seminaive``, with the rounds timed
+    alone (set-up and the dense copy of the model are outside the clock).
+
+    ``threads`` > 0 sets the OpenMP thread count (it stays set for later
+    oracle calls); 0 restores the count the library was loaded with.
+    Returns (R or None, iters, model ones, seconds, threads used).
+    """
+    threads = int(threads) if threads > 0 else default_threads()
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    out = np.zeros((n, n), dtype=np.uint8) if want_model else None
+    ones = np.zeros(1, dtype=np.int64)
+    iters = np.zeros(1, dtype=np.int64)
+    secs = np.zeros(1, dtype=np.float64)
+    used = np.zeros(1, dtype=np.int32)
+    rc = _load().or_tc_seminaive_edges(n, e.shape[0], _ptr(e) if e.size else None, threads,
+                                       None if out is None else _ptr(out), _ptr(ones), _ptr(iters),
+                                       _ptr(secs), _ptr(used))
+    _check(rc, "or_tc_seminaive_edges")
+    return out, int(iters[0]), int(ones[0]), float(secs[0]), int(used[0])
 
 
 def tc_square_literal(a, maxsteps: int | None = None):

@@ -36,9 +36,11 @@
  * Return value: 0 on success, 1 if maxsteps was reached first (the result is
  * then the last iterate computed), 2 on allocation failure, 3 on bad input.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -113,8 +115,49 @@ int or_num_threads(void) {
  *   Delta_{k+1}(x) = ( OR_{y in succ(x)} Delta_k(y) ) \ T_k(x),
  *   T_{k+1} = T_k  u  Delta_{k+1}.
  * Stops at the first empty Delta (that round is counted in iters) or after
- * maxsteps rounds, in which case R holds T_maxsteps.
+ * maxsteps rounds, in which case T holds T_maxsteps.
+ *
+ * tc_rounds runs the rounds after round 1: on entry *T = *D = T_1 (bitset
+ * rows, w words each), Dn is scratch of the same size and ones[1] holds
+ * |T_1|.  *D and *Dn may be swapped on return.  Returns 0 or 1 as below and
+ * leaves the number of rounds in *k.
  */
+static int tc_rounds(int64_t n, int64_t w, const csr* g, word* T, word** Dp, word** Dnp, int64_t* ones,
+                     int64_t maxsteps, int64_t* kp) {
+  word* D = *Dp;
+  word* Dn = *Dnp;
+  int rc = 0;
+  int64_t k = 1;
+  int64_t delta = ones ? ones[1] : 1;
+  if (!ones) {
+    delta = 0;
+    for (int64_t i = 0; i < n; ++i) delta += popcount_row(T + i * w, w);
+  }
+  while (delta != 0) {
+    if (k == maxsteps) { rc = 1; break; }
+    delta = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : delta)
+    for (int64_t x = 0; x < n; ++x) {
+      word* dst = Dn + x * w;
+      memset(dst, 0, (size_t)w * sizeof(word));
+      for (int64_t e = g->ptr[x]; e < g->ptr[x + 1]; ++e) {
+        const word* src = D + (int64_t)g->idx[e] * w;
+        for (int64_t q = 0; q < w; ++q) dst[q] |= src[q];
+      }
+      word* t = T + x * w;
+      for (int64_t q = 0; q < w; ++q) { dst[q] &= ~t[q]; t[q] |= dst[q]; }
+      delta += popcount_row(dst, w);
+    }
+    word* tmp = D; D = Dn; Dn = tmp;
+    ++k;
+    if (ones) ones[k] = ones[k - 1] + delta;
+  }
+  *Dp = D;
+  *Dnp = Dn;
+  *kp = k;
+  return rc;
+}
+
 int or_tc_seminaive(int64_t n, const uint8_t* A, uint8_t* R, int64_t* ones, int64_t maxsteps,
                     int64_t* iters) {
   if (n < 0 || maxsteps < 0) return 3;
@@ -131,34 +174,76 @@ int or_tc_seminaive(int64_t n, const uint8_t* A, uint8_t* R, int64_t* ones, int6
   if (maxsteps == 0) {
     memset(T, 0, (size_t)(n * w) * sizeof(word));
   } else {
-    k = 1;
     int64_t c = 0;
     for (int64_t i = 0; i < n; ++i) c += popcount_row(T + i * w, w);
     if (ones) ones[1] = c;
-    int64_t delta = c;
-    while (delta != 0) {
-      if (k == maxsteps) { rc = 1; break; }
-      delta = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : delta)
-      for (int64_t x = 0; x < n; ++x) {
-        word* dst = Dn + x * w;
-        memset(dst, 0, (size_t)w * sizeof(word));
-        for (int64_t e = g.ptr[x]; e < g.ptr[x + 1]; ++e) {
-          const word* src = D + (int64_t)g.idx[e] * w;
-          for (int64_t q = 0; q < w; ++q) dst[q] |= src[q];
-        }
-        word* t = T + x * w;
-        for (int64_t q = 0; q < w; ++q) { dst[q] &= ~t[q]; t[q] |= dst[q]; }
-        delta += popcount_row(dst, w);
-      }
-      word* tmp = D; D = Dn; Dn = tmp;
-      ++k;
-      if (ones) ones[k] = ones[k - 1] + delta;
-    }
+    rc = tc_rounds(n, w, &g, T, &D, &Dn, ones, maxsteps, &k);
   }
   if (iters) *iters = k;
   if (R) bits_to_dense(n, T, R);
   free(T); free(D); free(Dn); free_csr(&g);
+  return rc;
+}
+
+/*
+ * The same closure from an edge list, with the rounds timed on their own.
+ * edges holds m pairs (i, j), row-major [m x 2], meaning r1(e_i, e_j);
+ * pairs outside [0, n) are ignored and repeated pairs count once.  Set-up
+ * (successor lists and T_1 = Delta_1 as bitset rows) is not timed; *seconds
+ * receives the monotonic-clock time of the rounds alone, from T_1 in memory
+ * to the model in memory.  model_ones receives |model|; R (dense n x n,
+ * optional) receives the model after the clock has stopped.  threads > 0
+ * sets the OpenMP thread count for the call; *threads_used reports it.
+ */
+int or_tc_seminaive_edges(int64_t n, int64_t m, const int32_t* edges, int threads, uint8_t* R,
+                          int64_t* model_ones, int64_t* iters, double* seconds, int* threads_used) {
+  if (n < 0 || m < 0 || (m > 0 && !edges)) return 3;
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+  if (threads_used) *threads_used = omp_get_max_threads();
+#else
+  (void)threads;
+  if (threads_used) *threads_used = 1;
+#endif
+  int64_t w = nwords(n);
+  word* T = (word*)calloc((size_t)(n * w + 1), sizeof(word));
+  word* D = (word*)calloc((size_t)(n * w + 1), sizeof(word));
+  word* Dn = (word*)calloc((size_t)(n * w + 1), sizeof(word));
+  csr g = {(int64_t*)calloc((size_t)(n + 1), sizeof(int64_t)), NULL};
+  if (!T || !D || !Dn || !g.ptr) { free(T); free(D); free(Dn); free(g.ptr); return 2; }
+  /* distinct pairs as bitset rows, then successor lists read off the rows */
+  for (int64_t e = 0; e < m; ++e) {
+    int64_t i = edges[2 * e], j = edges[2 * e + 1];
+    if (i >= 0 && i < n && j >= 0 && j < n) set_bit(T + i * w, j);
+  }
+  int64_t c = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t ri = popcount_row(T + i * w, w);
+    g.ptr[i + 1] = g.ptr[i] + ri;
+    c += ri;
+  }
+  g.idx = (int32_t*)malloc((size_t)(c + 1) * sizeof(int32_t));
+  if (!g.idx) { free(T); free(D); free(Dn); free_csr(&g); return 2; }
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t f = g.ptr[i];
+    for (int64_t j = 0; j < n; ++j)
+      if (get_bit(T + i * w, j)) g.idx[f++] = (int32_t)j;
+  }
+  memcpy(D, T, (size_t)(n * w) * sizeof(word));
+  int64_t k = 0;
+  int64_t* ones = (int64_t*)calloc((size_t)(n + 3), sizeof(int64_t));
+  if (!ones) { free(T); free(D); free(Dn); free_csr(&g); return 2; }
+  ones[1] = c;
+  struct timespec t0, t1;
+  clock_gettime(CLOCK_MONOTONIC, &t0);
+  int rc = n == 0 ? 0 : tc_rounds(n, w, &g, T, &D, &Dn, ones, n + 2, &k);
+  clock_gettime(CLOCK_MONOTONIC, &t1);
+  if (n == 0) k = 1;
+  if (seconds) *seconds = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+  if (iters) *iters = k;
+  if (model_ones) *model_ones = ones[k];
+  if (R) bits_to_dense(n, T, R);
+  free(ones); free(T); free(D); free(Dn); free_csr(&g);
   return rc;
 }
 

@@ -70,7 +70,7 @@ def load() -> ctypes.CDLL:
                          pi32, vp], ctypes.c_int),
         "dl_sg": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, pi32, vp], ctypes.c_int),
         "dl_sg_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, pi64, pi32, pi32, vp], ctypes.c_int),
-        "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
+        "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, pi32, vp], ctypes.c_int),
         "dl_eps_bound": ([vp, i64, vp, i64, ctypes.POINTER(dbl), vp], ctypes.c_int),
         "dl_sg_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
         "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
@@ -362,20 +362,23 @@ def dl_eps_bound(A: torch.Tensor, ctx: Context | None = None, stream=None) -> fl
 
 
 def dl_solve_eps(A: torch.Tensor, eps: float, want_x: bool = False, out: torch.Tensor | None = None,
-                 ctx: Context | None = None, stream=None):
-    """Epsilon form: returns (R, X or None); R = [(I - eps A)^-1 eps A > 0]."""
+                 ctx: Context | None = None, stream=None, underflow: bool = False):
+    """Epsilon form: returns (R, X or None); R = [(I - eps A)^-1 eps A > 0].
+    With underflow=True returns (R, X or None, flag), flag = 1 when an entry
+    of R may have been lost to fp64 underflow (see include/dl.h)."""
     n, lda = _mat(A, "A")
     R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=A.device)
     _, ldr = _mat(R, "R")
     X = torch.empty((n, n), dtype=torch.float64, device=A.device) if want_x else None
     ldx = max(n, 1)
     it = ctypes.c_int32()
+    uf = ctypes.c_int32()
     c = _ctx(ctx)
     _check(load().dl_solve_eps(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, float(eps),
                                ctypes.c_void_p(R.data_ptr()), ldr,
                                ctypes.c_void_p(X.data_ptr()) if X is not None else None, ldx,
-                               ctypes.byref(it), _stream_ptr(stream)))
-    return R, X
+                               ctypes.byref(it), ctypes.byref(uf), _stream_ptr(stream)))
+    return (R, X, int(uf.value)) if underflow else (R, X)
 
 
 def dl_sg_eps(P: torch.Tensor, eps: float, want_x: bool = False, out: torch.Tensor | None = None,
@@ -581,8 +584,14 @@ class Batch:
         if rc == DL_EAGAIN:
             return None
         _check(rc)
-        # the library reads the edges in the next dl_batch_step: keep them alive
+        # the library reads the edges in the next dl_batch_step, whose scatter
+        # may still be in flight on the batch's stream when that call returns
+        # (look-ahead): keep a reference until then, and tell the caching
+        # allocator the memory is in use on that stream, so it is not handed
+        # to a new tensor before the scatter has read it
         self._pending_edges.append(edges)
+        if m:
+            edges.record_stream(self.stream if self.stream is not None else torch.cuda.current_stream(edges.device))
         return int(slot.value)
 
     def tune(self, sizes: list | None = None) -> list[dict]:

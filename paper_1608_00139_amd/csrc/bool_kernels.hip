@@ -3,13 +3,19 @@
 // Every step of the three fixpoints is one "NT" product with a fused
 // threshold:   out(i, j) = [ add(i, j) + sum_k X(i, k) Y(j, k)  !=  0 ].
 // Both operands are row-major with K contiguous, the layout the MFMA
-// operand registers want.  The products of the paper map onto it as:
+// operand registers want.  The fixpoint driver launches the products of the
+// paper as follows (no addend: each closure step adds the previous iterate,
+// which leaves the iterates unchanged, folded into the right operand as an
+// identity):
 //   closure, plain   R' = min1(A + A R)     run transposed: S = R^T,
-//                    S' = [A^T + S A^T]     X = S, Y = A, add = A^T
-//   closure, squared R' = min1(A + R R)     X = R, Y = R^T, add = A,
-//                                           and the epilogue also writes R'^T
+//                    S' = [S (A + I)^T]     X = S, Y = A + I (written once
+//                                           at ingest)
+//   closure, squared R' = min1(A + R R)     X = R, Y = R^T + I; the epilogue
+//                    R' = [R (R + I)]       also writes R'^T + I, the next
+//                                           step's Y (outT_ident)
 //   same generation  T  = [P S]             X = P, Y = S (S is symmetric)
 //                    S' = [I + T P^T]       X = T, Y = P, add = identity
+// Layered programs still pass an addend (their running sums).
 // min1 on the non-negative integer counts is the test "!= 0" (Sec. 2, 3).
 //
 // Operands hold exactly 0 or 1 in the chosen precision (int8, fp32, bf16 or

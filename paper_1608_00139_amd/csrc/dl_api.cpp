@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <climits>
 #include <cstdio>
@@ -780,7 +781,7 @@ int dl_eps_bound(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double* 
 }
 
 int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double eps, uint8_t* R, int64_t ldr,
-                 double* X, int64_t ldx, int32_t* iters, void* stream) {
+                 double* X, int64_t ldx, int32_t* iters, int32_t* underflow, void* stream) {
   int rc = check_common(ctx, n, A, lda, R, ldr);
   if (rc) return rc;
   if (X && n > 0) {
@@ -791,6 +792,7 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
   }
   if (!(eps > 0.0)) return fail(DL_EINVAL, "eps must be positive");
   if (iters) *iters = 0;
+  if (underflow) *underflow = 0;
   if (n == 0) return DL_OK;
   double bound = 0.0;
   if ((rc = dl_eps_bound(ctx, n, A, lda, &bound, stream))) return rc;
@@ -803,12 +805,21 @@ int dl_solve_eps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, double e
   std::string err;
   double tmsum = 0.0;
   int64_t tcount = 0;
+  double minpos = INFINITY;
   hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, A, lda, A, lda, eps, R, ldr, X, ldx, s, ctx->timing,
-                               &tmsum, &tcount, &err);
+                               &tmsum, &tcount, &minpos, &err);
   if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
   if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
   ctx->ms[1] += tmsum;
   ctx->launches[1] += tcount;
+  // X = eps A + eps A X, so along a shortest path i -> v -> ... -> j the
+  // true entries X_vj, X_ij shrink by at most a factor eps per edge, from
+  // X_.j >= eps at the last edge.  A true entry below the smallest normal
+  // double therefore implies one in [DBL_MIN, DBL_MIN / eps), which the
+  // elimination computes to full relative accuracy; if the smallest positive
+  // entry computed is at least twice that, no true entry is that small and
+  // none was lost.
+  if (underflow) *underflow = minpos < 2.0 * DBL_MIN / eps ? 1 : 0;
   return DL_OK;
 }
 
@@ -871,7 +882,7 @@ int dl_solve_linear(dl_ctx* ctx, int64_t n, const uint8_t* B, int64_t ldb, const
   double tmsum = 0.0;
   int64_t tcount = 0;
   hipError_t e = dl::eps_solve(&ctx->eps, ctx->budget, n, B, ldb, C, ldc, eps, R, ldr, X, ldx, (hipStream_t)stream,
-                               false, &tmsum, &tcount, &err);
+                               false, &tmsum, &tcount, nullptr, &err);
   if (e == hipErrorOutOfMemory) return fail(DL_ENOMEM, err);
   if (e != hipSuccess) return fail(DL_EHIP, err + ": " + hipGetErrorString(e));
   return DL_OK;

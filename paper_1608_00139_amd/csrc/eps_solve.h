@@ -25,10 +25,12 @@ int64_t eps_padded_size(int64_t n);
 // (n x n, ldx).  B = C = A is the closure form.  `budget_left` caps the
 // workspace (0 = no cap).  With timing on, the trailing-update launches are
 // bracketed by events and their count and total time are returned.
+// min_positive (host, may be null) receives the smallest positive entry of X
+// (+inf when X has none).
 hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* B, int64_t ldb,
                      const uint8_t* C, int64_t ldc, double eps, uint8_t* R, int64_t ldr, double* X_out,
                      int64_t ldx, hipStream_t s, bool timing, double* trailing_ms, int64_t* trailing_launches,
-                     std::string* err);
+                     double* min_positive, std::string* err);
 
 // One layer of tail-recursive heads h = 0 .. M-1,
 //   X_h = eps_h (A_h + sum_j B[h][j] X_j),

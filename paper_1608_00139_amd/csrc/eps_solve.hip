@@ -25,6 +25,7 @@
 // (it is at least eps^L for a shortest path of length L, by the footnote to
 // Lemma 2).  Denormals are kept.
 #include <math.h>
+#include <string.h>
 
 #include <string>
 #include <utility>
@@ -266,16 +267,38 @@ __global__ void __launch_bounds__(256) k_eps_init(const uint8_t* B, int64_t ldb,
   }
 }
 
+// R = [X > 0] (and X itself when asked for), plus the smallest positive
+// entry of X: its bits go into *minpos by an unsigned atomic minimum (positive
+// doubles order like their bit patterns), one per workgroup.
 __global__ void __launch_bounds__(256)
-k_eps_emit(const double* W, int Np, int n, uint8_t* R, int64_t ldr, double* X, int64_t ldx) {
+k_eps_emit(const double* W, int Np, int n, uint8_t* R, int64_t ldr, double* X, int64_t ldx,
+           unsigned long long* minpos) {
+  __shared__ unsigned long long red[4];
   const int i = blockIdx.y;
   const int64_t ld = 2 * (int64_t)Np;
+  unsigned long long m = ~0ull;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
     const double x = W[i * ld + Np + j];
     R[(int64_t)i * ldr + j] = x > 0.0 ? 1 : 0;
     if (X) X[(int64_t)i * ldx + j] = x;
+    if (x > 0.0) {
+      const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+      m = b < m ? b : m;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long v = __shfl_xor(m, o);
+    m = v < m ? v : m;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) m = red[w] < m ? red[w] : m;
+    if (m != ~0ull) atomicMin(minpos, m);
   }
 }
+
+__global__ void k_set_word(unsigned long long* p, unsigned long long v) { *p = v; }
 
 // ----------------------------------------------------------------- driver
 int64_t eps_padded_size(int64_t n) { return n <= 0 ? 0 : ((n + NB - 1) / NB) * NB; }
@@ -449,16 +472,19 @@ static size_t gj_scratch_doubles(int64_t ldw) {
 hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint8_t* B, int64_t ldb,
                      const uint8_t* C, int64_t ldc, double eps, uint8_t* R, int64_t ldr, double* X_out,
                      int64_t ldx, hipStream_t s, bool timing, double* trailing_ms, int64_t* trailing_launches,
-                     std::string* err) {
+                     double* min_positive, std::string* err) {
   *trailing_ms = 0.0;
   *trailing_launches = 0;
   const int64_t Np = eps_padded_size(n);
   const int64_t ldw = 2 * Np;
   const size_t wbytes = (size_t)Np * ldw * sizeof(double);
   const size_t dbytes = gj_scratch_doubles(ldw) * sizeof(double);
-  EPS_CK(ensure(ws, budget_left, wbytes + dbytes, "epsilon-solve", err), *err);
+  EPS_CK(ensure(ws, budget_left, wbytes + dbytes + 256, "epsilon-solve", err), *err);
   double* W = (double*)ws->buf;
   double* Dinv = W + (size_t)Np * ldw;
+  unsigned long long* minpos = (unsigned long long*)((char*)ws->buf + wbytes + dbytes);
+  hipLaunchKernelGGL(k_set_word, dim3(1), dim3(1), 0, s, minpos, ~0ull);
+  EPS_CK(hipGetLastError(), "epsilon init");
 
   hipLaunchKernelGGL(k_eps_init, dim3((unsigned)((Np + 255) / 256), (unsigned)Np), dim3(256), 0, s, B, ldb, C, ldc,
                      (int)n, (int)Np, eps, W);
@@ -467,13 +493,23 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   hipError_t e = gj_eliminate(ws, W, Np, ldw, Dinv, s, timing, &evs, err);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
-                       (int)n, R, ldr, X_out, ldx);
+                       (int)n, R, ldr, X_out, ldx, minpos);
     e = hipGetLastError();
     if (e != hipSuccess) *err = "threshold";
+  }
+  unsigned long long mp = ~0ull;
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(&mp, minpos, sizeof mp, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) *err = "smallest positive entry read-back";
   }
   if (e == hipSuccess) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) *err = "epsilon solve sync";
+  }
+  if (min_positive) {
+    double v = INFINITY;
+    if (mp != ~0ull) memcpy(&v, &mp, sizeof v);
+    *min_positive = v;
   }
   for (auto& p : evs) {
     float t = 0.f;

@@ -37,7 +37,8 @@ def test_worked_example_values(dl):
     g = load_sections("worked_example.txt")
     a = g["R1"].astype(np.uint8)
     announce("eps worked example")
-    r, x = dl.dl_solve_eps(dev(a), 0.5, want_x=True)
+    r, x, flag = dl.dl_solve_eps(dev(a), 0.5, want_x=True, underflow=True)
+    assert flag == 0
     xs = host(x)
     exact = np.array([[1, 4, 2, 0], [2, 1, 4, 0], [4, 2, 1, 0], [4, 2, 1, 0]]) / 7.0
     assert np.allclose(xs, exact, rtol=1e-14, atol=1e-16)
@@ -73,6 +74,24 @@ def test_random_vs_lapack_and_closure(dl, n):
         assert np.array_equal(host(r), oracle.tc_seminaive(a)[0])
 
 
+def test_underflow_flag_boundary(dl):
+    """Directed paths at eps = 1/2: X_ij = 2^-(j-i) exactly.  A path of 1000
+    constants keeps every entry at least 2^-999, a normal double far from
+    the smallest one (flag 0, model exact); one of 1030 has entries below
+    2^-1022 (flag 1; no false positive either way)."""
+    for n, want in ((1000, 0), (1030, 1)):
+        a = np.eye(n, k=1, dtype=np.uint8)
+        ref = np.triu(np.ones((n, n), np.uint8), 1)
+        announce("eps underflow flag", n)
+        r, x, flag = dl.dl_solve_eps(dev(a), 0.5, want_x=True, underflow=True)
+        assert flag == want, (n, flag)
+        got = host(r)
+        assert not np.any(got & (1 - ref)), "false positive"
+        if want == 0:
+            assert np.array_equal(got, ref)
+            assert host(x)[0, n - 1] == 2.0 ** -(n - 1)
+
+
 def test_eps_validation(dl):
     a = dlgen.to_dense(50, dlgen.er_edges(50, 0.1, 3))
     bound = oracle.eps_bound(a)
@@ -97,7 +116,8 @@ def test_underflow_negative_control(dl):
     n = 1500
     a = np.eye(n, k=1, dtype=np.uint8)
     announce("eps underflow control")
-    r, x = dl.dl_solve_eps(dev(a), 0.5, want_x=True)
+    r, x, flag = dl.dl_solve_eps(dev(a), 0.5, want_x=True, underflow=True)
+    assert flag == 1, "the call must report that entries may be lost"
     got = host(r)
     ref = oracle.tc_seminaive(a)[0]
     assert not np.any(got & (1 - ref)), "false positive"
@@ -110,12 +130,16 @@ def test_underflow_negative_control(dl):
 
 @pytest.mark.parametrize("pname,p", [("1/N", 1.0 / 8192), ("4/N", 4.0 / 8192), ("0.01", 0.01)])
 def test_config_n8192_zero_threshold_errors(dl, pname, p):
-    """n = 8192, eps = 0.5 / (max row sum + 1): thresholded X equals the closure."""
+    """n = 8192, eps = 0.5 / (max row sum + 1), all nine ER graphs: the
+    thresholded X equals the closure oracle's model (zero threshold errors)
+    and the call reports no possible underflow."""
     n = 8192
-    a = dlgen.to_dense(n, dlgen.er_edges(n, p, 0))
-    eps = 0.5 / (1.0 + float(a.sum(axis=1).max()))
-    announce("eps 8192", pname)
-    r, _ = dl.dl_solve_eps(dev(a), eps)
-    ref = oracle.tc_seminaive(a)[0]
-    errors = int((host(r) != ref).sum())
-    assert errors == 0, f"{errors} threshold errors"
+    for seed in range(3):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, p, seed))
+        eps = 0.5 / (1.0 + float(a.sum(axis=1).max()))
+        announce("eps 8192", pname, seed)
+        r, _, flag = dl.dl_solve_eps(dev(a), eps, underflow=True)
+        ref = oracle.tc_seminaive(a)[0]
+        errors = int((host(r) != ref).sum())
+        assert errors == 0, f"p={pname} seed={seed}: {errors} threshold errors"
+        assert flag == 0

@@ -87,6 +87,48 @@ def test_stratified_negation(dl, n):
         _compare(dl, NEG_TEXT, rels, n, f"negation seed={seed}")
 
 
+@pytest.mark.parametrize("n", [600, 1000])
+@pytest.mark.parametrize("name", ["negation", "even_odd", "transposed", "mixed_general", "layers"])
+def test_programs_on_the_large_tile_kernel(dl, name, n):
+    """The layered programs with every product forced onto the 256 x 256
+    direct-to-LDS step kernel (tile configuration 0, the benchmarked one),
+    so its addend (running sums) and complement paths are held to the
+    layered oracle, not only to the other evaluation method."""
+    ctx = dl.Context()
+    ctx.set_tuning("i8", n, 0)
+    if name == "negation":
+        text = NEG_TEXT
+        rels = {"e": _rand(n, 1.5 / n, 31), "f": _rand(n, 1.0 / n, 32)}
+    else:
+        text, _, edbs = CASES[name]
+        rels = {e: _rand(n, 2.0 / n, 40 + k) for k, e in enumerate(edbs)}
+    ref, ref_layers = oprog.evaluate(text, rels, n)
+    ref_iters = {tuple(h): it for h, it in ref_layers}
+    keep = {k: dev(v) for k, v in rels.items()}
+    for method in (dl.DL_EVAL_ITERATION, dl.DL_EVAL_MATRIX):
+        announce("program cfg0", name, n, method)
+        prog = dl.Program(text, ctx=ctx)
+        for k, t in keep.items():
+            prog.bind(k, t)
+        ctx.kernel_stats(0, reset=True)
+        ctx.set_timing(True)
+        prog.run(method)
+        ctx.set_timing(False)
+        launches, _ = ctx.kernel_stats(0, reset=True)
+        for pname, want in ref.items():
+            got, ones = prog.fetch(pname, n=n)
+            mism = int((host(got) != want).sum())
+            assert mism == 0, f"{name} n={n} method={method} {pname}: {mism} entries differ"
+            assert ones == int(want.sum())
+        for l in prog.layers():
+            if l["method"] == dl.DL_EVAL_ITERATION:
+                assert l["iters"] == ref_iters[tuple(l["heads"])], (name, l)
+        if method == dl.DL_EVAL_ITERATION:
+            assert launches > 0  # products ran (on the forced configuration)
+        prog.close()
+    ctx.close()
+
+
 def test_negated_eq_and_converse_in_constant_terms(dl):
     text = ("d(X,Y) :- not eq(X,Y).\n"
             "u(X,Y) :- e(Y,X).\n"

@@ -141,6 +141,29 @@ def test_tc_random_vs_bruteforce(n, p, seed):
         assert np.array_equal(rs, r) and iters_s == it_s and np.array_equal(ones_s, ones_ss)
 
 
+@pytest.mark.parametrize("n,p,seed", [(0, 0.0, 0), (1, 0.5, 1), (40, 0.06, 2), (257, 1.5 / 257, 3),
+                                      (600, 4 / 600, 4)])
+def test_tc_edge_list_entry_vs_bfs(n, p, seed):
+    """The edge-list entry (the CPU baseline's timed rounds) against BFS
+    reachability and the path-length histogram, with repeated pairs, self
+    loops and out-of-range pairs in the list, at one thread and at all."""
+    e = dlgen.er_edges(n, p, seed, self_loops=True) if n else np.zeros((0, 2), np.int64)
+    junk = np.array([[-1, 0], [0, n], [n, n + 3]], np.int64)
+    lst = np.concatenate([e, e[: len(e) // 2], junk]) if n else junk
+    a = dlgen.to_dense(n, e) if n else np.zeros((0, 0), np.uint8)
+    if n:
+        ref, hist = oracle.bfs(a)
+        it_ref = oracle.plain_schedule_from_hist(hist)[0]
+    else:
+        ref, it_ref = np.zeros((0, 0), np.uint8), 1
+    for threads in (1, 0):
+        r, iters, ones, secs, used = oracle.tc_seminaive_edges(n, lst, threads=threads)
+        assert np.array_equal(r, ref) and iters == it_ref and ones == int(ref.sum())
+        assert secs >= 0.0 and used >= 1
+    assert oracle.tc_seminaive_edges(n, lst, threads=1)[4] == 1
+    assert oracle.tc_seminaive_edges(0, np.zeros((0, 2), np.int32))[4] == oracle.default_threads()
+
+
 def test_tc_naive_tdb_random_small():
     for seed in range(20):
         n = 2 + seed % 4
