@@ -236,9 +236,20 @@ int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream);
  *   3  (DL_I8 only) configuration 0 on the 32 x 32 x 32 int8 MFMA
  *   4  32 x 32 tile, 4 waves of 16 x 16, the whole K extent of its rows in
  *      LDS (operand rows of at most 2 KB: Np <= 2048 / element bytes)
- * Without an entry the library picks by size (4 when Np = 256, or DL_F32
- * at Np = 512; else 0 when (Np/256)^2 >= 256 tiles, 1 when (Np/128)^2 >=
- * 128, else 2; Np = dl_padded_size).
+ *   5  (the plain series only, Np <= 512) the whole fixpoint in one launch:
+ *      one resident workgroup per 32 x 32 tile of the iterate, the constant
+ *      right operand A + I held in LDS for every step, the workgroups of a
+ *      tile row waiting only for each other between steps, the stop decided
+ *      in the kernel from the model sizes (at most one step past the
+ *      confirming one, whose iterate equals the model), R written by the
+ *      kernel; for every other use of the product step it means the size
+ *      rule.  The plain series uses it where it applies unless dl_tune_set
+ *      chose another configuration for that size.  A wait that exceeds two
+ *      seconds ends the launch with DL_EHIP.
+ * Without an entry the library picks by size: 5 for the plain series when
+ * Np <= 512 and its rows fit; otherwise 4 when Np = 256, or DL_F32 at
+ * Np = 512; else 0 when (Np/256)^2 >= 256 tiles, 1 when (Np/128)^2 >= 128,
+ * else 2 (Np = dl_padded_size).
  * dl_tune times squaring-step launches of every configuration on a
  * pseudo-random 0/1 relation of size n in precision prec (five interleaved
  * rounds of about 4 ms per configuration, median per configuration; on

@@ -568,12 +568,55 @@ constexpr int kSmallPart = (kSmallKS - 1) * 4 * 64 * 16;  // groups 1..3: 4 bloc
 
 size_t small_lds_bytes(int64_t ldb) { return (size_t)64 * ldb + kSmallPart + 32 * kSmallEst; }
 
+// The product of a small tile: X rows 0..31 and Y rows 32..63 of the LDS
+// image (chunk c of row r at c ^ (r & mask)), four K groups of four waves,
+// groups 1..3 handing their partial sums to group 0 through LDS, which
+// writes the 0/1 result into the epilogue tile et (32 rows of kSmallEst
+// bytes).  Called by all kSmallThreads threads; ends before the barrier
+// that publishes et.
+template <class Op>
+__device__ inline void small_tile_product(uint8_t* smem, int64_t ldb, int kc, int mask, int lane, int wave,
+                                          uint8_t* et) {
+  constexpr int KSTEP_CHUNKS = (64 / Op::FR) * Op::CPL;
+  const int kg = wave >> 2, wq = wave & 3;  // K group, block of the tile
+  const int wm = wq >> 1, wn = wq & 1;
+  const int g = lane / Op::FR, rf = lane % Op::FR;
+  const int ra = 16 * wm + rf, rb = 32 + 16 * wn + rf;
+  const uint8_t* xa = smem + (int64_t)ra * ldb;
+  const uint8_t* yb = smem + (int64_t)rb * ldb;
+  typename Op::Acc acc = Op::zero();
+  const int ksteps = kc / KSTEP_CHUNKS;
+  for (int ks = kg; ks < ksteps; ks += kSmallKS) {
+    u32x4 a[Op::CPL], b[Op::CPL];
+#pragma unroll
+    for (int c = 0; c < Op::CPL; ++c) {
+      const int ch = ks * KSTEP_CHUNKS + g * Op::CPL + c;
+      a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
+      b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
+    }
+    acc = Op::mma(a, b, acc);
+  }
+  typename Op::Acc* part = (typename Op::Acc*)(smem + 64 * ldb);
+  if (kg > 0) part[((kg - 1) * 4 + wq) * 64 + lane] = acc;
+  __syncthreads();
+  // group 0: the sums, as a 0/1 block into the epilogue tile
+  if (kg == 0) {
+#pragma unroll
+    for (int k = 0; k < kSmallKS - 1; ++k) acc += part[(k * 4 + wq) * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < Op::NI; ++v) {
+      int r, c;
+      Op::coord(lane, v, r, c);
+      et[(16 * wm + r) * kSmallEst + 16 * wn + c] = Op::nz(acc, v) ? 1 : 0;
+    }
+  }
+}
+
 template <class Op>
 __global__ void __launch_bounds__(kSmallThreads) k_nt_small(NTParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   if (step_is_done(p)) return;
   constexpr int NIB = elem_nibbles(Op::kPrec);
-  constexpr int KSTEP_CHUNKS = (64 / Op::FR) * Op::CPL;
   static_assert(Op::FR == 16 && Op::NI == 4 && sizeof(typename Op::Acc) == 16, "16 x 16 blocks, 16-byte sums");
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, p.tiles_m, p.tiles_n, tm, tn);
@@ -596,39 +639,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_nt_small(NTParams p) {
   }
   __syncthreads();  // waits for every load of this workgroup (vmcnt(0)) and joins the waves
 
-  const int kg = wave >> 2, wq = wave & 3;  // K group, block of the tile
-  const int wm = wq >> 1, wn = wq & 1;
-  const int g = lane / Op::FR, rf = lane % Op::FR;
-  const int ra = 16 * wm + rf, rb = 32 + 16 * wn + rf;
-  const uint8_t* xa = smem + (int64_t)ra * ldb;
-  const uint8_t* yb = smem + (int64_t)rb * ldb;
-  typename Op::Acc acc = Op::zero();
-  const int ksteps = kc / KSTEP_CHUNKS;
-  for (int ks = kg; ks < ksteps; ks += kSmallKS) {
-    u32x4 a[Op::CPL], b[Op::CPL];
-#pragma unroll
-    for (int c = 0; c < Op::CPL; ++c) {
-      const int ch = ks * KSTEP_CHUNKS + g * Op::CPL + c;
-      a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
-      b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
-    }
-    acc = Op::mma(a, b, acc);
-  }
-  typename Op::Acc* part = (typename Op::Acc*)(smem + 64 * ldb);
-  if (kg > 0) part[((kg - 1) * 4 + wq) * 64 + lane] = acc;
-  __syncthreads();
   uint8_t* et = smem + 64 * ldb + kSmallPart;
-  // group 0: the sums, as a 0/1 block into the epilogue tile
-  if (kg == 0) {
-#pragma unroll
-    for (int k = 0; k < kSmallKS - 1; ++k) acc += part[(k * 4 + wq) * 64 + lane];
-#pragma unroll
-    for (int v = 0; v < Op::NI; ++v) {
-      int r, c;
-      Op::coord(lane, v, r, c);
-      et[(16 * wm + r) * kSmallEst + 16 * wn + c] = Op::nz(acc, v) ? 1 : 0;
-    }
-  }
+  small_tile_product<Op>(smem, ldb, kc, mask, lane, wave, et);
   __syncthreads();
   int cnt = 0;
   uint8_t* outb = (uint8_t*)p.out;
@@ -674,6 +686,308 @@ template <class Op>
 static hipError_t set_lds_attr_small() {
   return hipFuncSetAttribute((const void*)k_nt_small<Op>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)small_lds_bytes(kSmallMaxLdb));
+}
+
+// ----------------------------------------------------------------- whole plain fixpoint in one launch
+// The plain series of Sec. 3, run transposed (S = R^T): S^(1) = A^T,
+// S^(t) = [S^(t-1) (A + I)^T], for Np <= 512 (operand rows of at most 2 KB),
+// as one launch of one workgroup per 32 x 32 tile of S, all resident at once
+// (cooperative launch).  The right operand A + I never changes: each
+// workgroup builds its 32 rows of it once, from the caller's bytes, and keeps
+// them in LDS; each step it fetches its 32 rows of S^(t-1) (whole K, as in
+// k_nt_small) and writes its tile of S^(t).
+//
+// Row blocks are independent.  Block i of S^(t) (its rows 32 i .. 32 i + 31)
+// is block i of S^(t-1) times (A + I)^T, so it depends on no other block,
+// and once it repeats (S^(k) = S^(k-1) on those rows) it stays fixed.  The
+// tiles_n workgroups of tile row i therefore run their own series: between
+// steps they wait only for each other, through one word per step,
+// rowstep[i][t] = arrivals + 256 x (tiles whose count changed at step t);
+// the series of block i has repeated at step k_i when every tile of it is
+// unchanged there (counts only grow, so "changed" = "count changed"), and
+// all its workgroups stop there together.  The iterates of the whole matrix
+// first repeat at K = max_i k_i; its model sizes, ones[t] = sum_i
+// ones_i[min(t, k_i)], are summed by the last workgroup to finish.  A tile
+// of S^(t) overwrites the same tile of S^(t-2), whose only readers (the
+// workgroups of its row, in step t-1) have arrived at step t-1 before the
+// writer starts step t.
+//
+// Coherence across XCDs without cache flushes: the tiles and counters are
+// written with device-scope stores and atomics (write-through, "sc1") and
+// the next step's rows fetched with device-scope loads (sc1, past any stale
+// L1 or L2 copy); a workgroup waits for its tile's stores to complete
+// (s_waitcnt vmcnt(0)) before it counts its arrival.
+//
+// Each wait polls with a time limit (s_memrealtime ticks, 100 MHz); past it
+// the workgroup raises the abort word, reports it in status_out[1] and
+// leaves, and every other wait sees the abort word and leaves.  On stopping,
+// each workgroup writes its tile of the last iterate into the caller's R,
+// transposed back and cropped to n x n.  The last workgroup to finish writes
+// ring_out[0 .. K] and status_out[0] = K, then zeroes the counters for the
+// next launch.
+
+__device__ inline unsigned ld_agent(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long ld_agent64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this wave's stores and atomics have completed.
+__device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Polls *p until (*p & mask) >= target; returns the word, or ~0u on a time
+// limit (then the abort word is raised and status_out[1] set) or an abort
+// seen in the abort word.
+__device__ inline unsigned wait_word(const unsigned* p, unsigned mask, unsigned target, unsigned* abort_word,
+                                     unsigned* status_out, long long limit) {
+  const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    const unsigned w = ld_agent(p);
+    if ((w & mask) >= target) return w;
+    if (ld_agent(abort_word) != 0u) return ~0u;
+    if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+      st_agent(abort_word, 1u);
+      st_agent(status_out + 1, 1u);
+      return ~0u;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Device-scope (write-through, sc1) stores of 16 and 8 bytes at byte offset
+// off of a buffer (buffer instructions: the compiler knows them as stores
+// and keeps the wait states their data registers need).
+constexpr int kCpolSc1 = 16;  // cache-policy bits of a device-scope access
+__device__ inline __amdgpu_buffer_rsrc_t buffer_of(void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ inline void st_agent_x4(__amdgpu_buffer_rsrc_t r, int off, u32x4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kCpolSc1);
+}
+__device__ inline void st_agent_x2(__amdgpu_buffer_rsrc_t r, int off, unsigned lo, unsigned hi) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  u32x2 v = {lo, hi};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, kCpolSc1);
+}
+
+// 16 boolean bytes as 16 operand elements (the bytes store_bool16 writes),
+// stored with device-scope stores at byte offset off of buffer r.
+template <int PREC>
+__device__ inline void store_bool16_agent(__amdgpu_buffer_rsrc_t r, int off, u32x4 b) {
+  if constexpr (PREC == P_I8) {
+    st_agent_x4(r, off, b);
+  } else if constexpr (PREC == P_FP8) {
+    st_agent_x4(r, off, b * 0x38u);
+  } else if constexpr (PREC == P_FP4) {
+    unsigned w2[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const unsigned x = b[2 * h], y = b[2 * h + 1];
+      const unsigned lo = ((x & 1u) << 1) | (((x >> 8) & 1u) << 5) | (((x >> 16) & 1u) << 9) | (((x >> 24) & 1u) << 13);
+      const unsigned hi = ((y & 1u) << 1) | (((y >> 8) & 1u) << 5) | (((y >> 16) & 1u) << 9) | (((y >> 24) & 1u) << 13);
+      w2[h] = lo | (hi << 16);
+    }
+    st_agent_x2(r, off, w2[0], w2[1]);
+  } else if constexpr (PREC == P_BF16) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      u32x4 v;
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const unsigned x = b[2 * h + w];
+        v[2 * w] = ((x & 1u) ? 0x3F80u : 0u) | (((x >> 8) & 1u) ? 0x3F800000u : 0u);
+        v[2 * w + 1] = (((x >> 16) & 1u) ? 0x3F80u : 0u) | (((x >> 24) & 1u) ? 0x3F800000u : 0u);
+      }
+      st_agent_x4(r, off + 16 * h, v);
+    }
+  } else {  // F32
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const unsigned x = b[w];
+      u32x4 v;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = ((x >> (8 * q)) & 1u) ? 0x3F800000u : 0u;
+      st_agent_x4(r, off + 16 * w, v);
+    }
+  }
+}
+
+// 16-byte LDS chunk of operand elements from the low bits of `bits`
+// (element e of the chunk set iff bit e is set; 32 / nibbles elements).
+template <int PREC>
+__device__ inline u32x4 chunk_of_bits(unsigned bits) {
+  u32x4 v = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    unsigned x = 0u;
+    if constexpr (PREC == P_F32) {
+      x = ((bits >> w) & 1u) ? 0x3F800000u : 0u;
+    } else if constexpr (PREC == P_BF16) {
+      x = (((bits >> (2 * w)) & 1u) ? 0x3F80u : 0u) | (((bits >> (2 * w + 1)) & 1u) ? 0x3F800000u : 0u);
+    } else if constexpr (PREC == P_FP4) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x |= ((bits >> (8 * w + q)) & 1u) << (4 * q + 1);
+    } else {
+      const unsigned one = PREC == P_FP8 ? 0x38u : 1u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x |= ((bits >> (4 * w + q)) & 1u) ? one << (8 * q) : 0u;
+    }
+    v[w] = x;
+  }
+  return v;
+}
+
+template <class Op>
+__global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  __shared__ int s_go;  // 1 compute the step, 0 stop, -1 abort
+  constexpr int NIB = elem_nibbles(Op::kPrec);
+  constexpr int EPC = 32 / NIB;  // operand elements per 16-byte chunk
+  const unsigned G = gridDim.x;
+  const int L = xcd_logical(blockIdx.x, (int)G);  // XCD-contiguous runs of tile rows
+  const int ti = L / p.tiles, tj = L % p.tiles;
+  const int row0 = 32 * ti, col0 = 32 * tj;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ldb = (int64_t)p.Np * NIB / 2;
+  const int kc = (int)(ldb / 16);
+  const int mask = (kc % 16 == 0) ? 15 : 7;
+  const int stride = p.Np + 3;  // entries per row block in rowstep and ones_row
+  unsigned* rowstep = p.rowstep + (int64_t)ti * stride;
+  uint8_t* et = smem + 64 * ldb + kSmallPart;
+
+  // Y = rows col0 .. col0 + 31 of A + I (LDS rows 32..63), built once
+  for (int q = tid; q < 32 * kc; q += kSmallThreads) {
+    const int r = q / kc, c = q % kc;
+    const int j = col0 + r, e0 = c * EPC;
+    unsigned bits = 0u;
+    if (j < p.n) {
+      const uint8_t* arow = p.A + (int64_t)j * p.lda;
+      for (int e = 0; e < EPC; ++e) {
+        const int k = e0 + e;
+        if (k < p.n && (arow[k] != 0 || k == j)) bits |= 1u << e;
+      }
+    }
+    *(u32x4*)(smem + (int64_t)(32 + r) * ldb + 16 * (c ^ ((32 + r) & mask))) = chunk_of_bits<Op::kPrec>(bits);
+  }
+  // S^(1) = A^T: tile element (r, c) is A[col0 + c][row0 + r]
+  for (int q = tid; q < 1024; q += kSmallThreads) {
+    const int r = q & 31, c = q >> 5;
+    const int gi = row0 + r, gj = col0 + c;
+    et[r * kSmallEst + c] = (gi < p.n && gj < p.n && p.A[(int64_t)gj * p.lda + gi] != 0) ? 1 : 0;
+  }
+  __syncthreads();
+
+  int t = 1, prev_cnt = 0;
+  for (;;) {
+    // publish S^(t) from et: stores, count, then the arrival (wave 0)
+    if (wave == 0) {
+      const int r = lane >> 1, cs = lane & 1;
+      const u32x4 v = *(const u32x4*)(et + r * kSmallEst + 16 * cs);
+      store_bool16_agent<Op::kPrec>(buffer_of(p.S[t & 1], (unsigned)(ldb * p.Np)),
+                                    (int)(((int64_t)(row0 + r) * p.Np + col0 + 16 * cs) * NIB / 2), v);
+      const int cnt = wave_sum(popc16(v));
+      if (lane == 0 && cnt) atomicAdd(p.ones_row + (int64_t)ti * stride + t, (unsigned long long)cnt);
+      const unsigned changed = cnt != prev_cnt ? 1u : 0u;
+      prev_cnt = cnt;
+      wait_stores();
+      if (lane == 0) atomicAdd(rowstep + t, 1u + (changed << 8));
+    }
+    ++t;
+    // decide whether step t runs: the row's arrivals at step t - 1
+    if (tid == 0) {
+      int go = 1;
+      if (t > p.max_steps) {
+        go = 0;
+      } else {
+        const unsigned w = wait_word(rowstep + (t - 1), 0xffu, (unsigned)p.tiles, p.finished + 1, p.status_out,
+                                     p.wait_limit);
+        if (w == ~0u) go = -1;
+        else if ((w >> 8) == 0u) go = 0;  // no tile of the row changed: its series repeated at t - 1
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    const int go = s_go;
+    if (go < 0) return;
+    if (go == 0) break;
+    // X = rows row0 .. row0 + 31 of S^(t-1) into LDS rows 0..31
+    const uint8_t* Xg = (const uint8_t*)p.S[(t - 1) & 1] + (int64_t)row0 * ldb;
+    for (int i = wave; i < kc / 2; i += kSmallThreads / 64) {
+      const int q = 64 * i + lane;
+      const int r = q / kc, pos = q % kc;
+      const int c = pos ^ (r & mask);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Xg + (int64_t)r * ldb + 16 * c),
+                                       (__attribute__((address_space(3))) void*)(smem + 1024 * i), 16, 0, kCpolSc1);
+    }
+    __syncthreads();  // vmcnt(0): the panel is in LDS
+    small_tile_product<Op>(smem, ldb, kc, mask, lane, wave, et);
+    __syncthreads();
+  }
+  // the last iterate computed, S^(t-1), back to R = S^T, cropped
+  for (int q = tid; q < 1024; q += kSmallThreads) {
+    const int r = q & 31, c = q >> 5;
+    const int gi = row0 + r, gj = col0 + c;
+    if (gi < p.n && gj < p.n) p.R[(int64_t)gj * p.ldr + gi] = et[r * kSmallEst + c];
+  }
+  // the last workgroup to finish sums the model sizes of the whole matrix
+  if (tid == 0) {
+    if (tj == 0) st_agent(p.krow + ti, (unsigned)(t - 1));
+    wait_stores();
+    s_go = atomicAdd(p.finished, 1u) == G - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  int K = 0;
+  for (int i = 0; i < p.tiles; ++i) {
+    const int k = (int)ld_agent(p.krow + i);
+    K = k > K ? k : K;
+  }
+  for (int s = tid; s <= K; s += kSmallThreads) {
+    unsigned long long sum = 0ull;
+    for (int i = 0; i < p.tiles; ++i) {
+      const int k = (int)ld_agent(p.krow + i);
+      sum += s == 0 ? 0ull : ld_agent64(p.ones_row + (int64_t)i * stride + (s < k ? s : k));
+    }
+    p.ring_out[s] = sum;
+  }
+  if (tid == 0) p.status_out[0] = (unsigned)K;
+  __syncthreads();
+  // every other workgroup is done with the counters: zero them
+  const int64_t rows = (int64_t)p.tiles * stride;
+  for (int64_t i = tid; i < rows; i += kSmallThreads) {
+    st_agent(p.rowstep + i, 0u);
+    __hip_atomic_store(p.ones_row + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (tid < p.tiles) st_agent(p.krow + tid, 0u);
+  if (tid == 0) st_agent(p.finished, 0u);
+}
+
+__global__ void k_fix_small_clear(FixSmallParams p) {
+  const int64_t rows = (int64_t)p.tiles * (p.Np + 3);
+  for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x) {
+    p.rowstep[i] = 0u;
+    p.ones_row[i] = 0ull;
+    if (i < p.tiles) p.krow[i] = 0u;
+    if (i < 2) p.finished[i] = 0u;
+  }
+}
+
+template <class Op>
+static hipError_t set_lds_attr_fix_small() {
+  return hipFuncSetAttribute((const void*)k_fix_small<Op>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)small_lds_bytes(kSmallMaxLdb));
+}
+
+template <class Op>
+static hipError_t launch_fix_small_op(FixSmallParams p, hipStream_t s) {
+  const int64_t ldb = (int64_t)p.Np * elem_nibbles(Op::kPrec) / 2;
+  if (ldb > kSmallMaxLdb || ldb % 128 != 0 || p.tiles * 32 != p.Np) return hipErrorInvalidValue;
+  void* args[] = {&p};
+  return hipLaunchCooperativeKernel((const void*)k_fix_small<Op>, dim3(p.tiles * p.tiles), dim3(kSmallThreads), args,
+                                    (unsigned)small_lds_bytes(ldb), s);
 }
 
 // ----------------------------------------------------------------- grouped step (serving)
@@ -1295,6 +1609,7 @@ static hipError_t init_op() {
   if constexpr (Op::kPrec == P_I8)
     if ((e = set_lds_attr_dma<OpI8x32, 256, 256, 64, 64, 128, 2>()) != hipSuccess) return e;
   if ((e = set_lds_attr_small<Op>()) != hipSuccess) return e;
+  if ((e = set_lds_attr_fix_small<Op>()) != hipSuccess) return e;
   if ((e = set_lds_attr<Op, 128, 128, 64, 64, KSMALL>()) != hipSuccess) return e;
   return set_lds_attr<Op, 64, 64, 32, 32, KSMALL>();
 }
@@ -1350,6 +1665,27 @@ hipError_t launch_nt_step(int prec, int cfg, const NTParams& p, hipStream_t s) {
   }
 }
 
+bool fix_small_supported(int prec, int64_t np) {
+  return np > 0 && np % 256 == 0 && np * elem_nibbles(prec) / 2 <= kSmallMaxLdb && np <= 512;
+}
+
+hipError_t launch_fix_small(int prec, const FixSmallParams& p, bool clear_first, hipStream_t s) {
+  if (!fix_small_supported(prec, p.Np) || p.max_steps < 1 || p.max_steps > p.Np + 2) return hipErrorInvalidValue;
+  if (clear_first) {
+    hipLaunchKernelGGL(k_fix_small_clear, dim3(32), dim3(256), 0, s, p);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  switch (prec) {
+    case P_I8: return launch_fix_small_op<OpI8>(p, s);
+    case P_F32: return launch_fix_small_op<OpF32>(p, s);
+    case P_BF16: return launch_fix_small_op<OpBF16>(p, s);
+    case P_FP8: return launch_fix_small_op<OpFP8>(p, s);
+    case P_FP4: return launch_fix_small_op<OpFP4>(p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Padding: every dimension is a multiple of 256, which every configuration's
 // tile and K slice divide.
 int64_t padded_size_for(int prec, int64_t n) {
@@ -1364,6 +1700,7 @@ int nt_config_count(int prec) {
 }
 
 bool nt_config_valid(int prec, int cfg, int64_t np) {
+  if (cfg == kCfgWholeFixpoint) return fix_small_supported(prec, np);
   if (cfg < 0 || cfg >= nt_config_count(prec) || np <= 0 || np % 256) return false;
   if (cfg == 3) return prec == P_I8;
   if (cfg == 4) return np * elem_nibbles(prec) / 2 <= kSmallMaxLdb;

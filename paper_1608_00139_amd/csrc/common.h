@@ -95,6 +95,48 @@ struct AdmitDesc {
 };
 hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, long long total_edges, hipStream_t s);
 
+// The whole plain closure fixpoint in one cooperative launch (k_fix_small in
+// bool_kernels.hip): one workgroup per 32 x 32 tile of S = R^T, for
+// operand rows of at most 2 KB and Np <= 512.
+struct FixSmallParams {
+  const uint8_t* A;
+  int64_t lda;
+  uint8_t* R;
+  int64_t ldr;
+  void* S[2];                    // iterates in operand precision, Np x Np (S^(t) in S[t & 1])
+  // counters: zero when the launch starts, and left zero by a launch that
+  // ends normally (the last workgroup clears them); see fix_small_words
+  unsigned long long* ones_row;  // [tiles][Np + 3] model size of each row block per step
+  unsigned* rowstep;             // [tiles][Np + 3] arrivals + 256 x changes per row block and step
+  unsigned* krow;                // [tiles] last step of each row block
+  unsigned* finished;            // [0] workgroups done, [1] abort (a wait ran past its limit)
+  // outputs (device or mapped host memory), written by the last workgroup
+  unsigned long long* ring_out;  // ring_out[t] = size of S^(t), t = 0 .. K
+  unsigned* status_out;          // [0] K, the last step of any row block; [1] 1 after an abort
+  int n, Np, tiles;              // tiles = Np / 32 per side
+  int max_steps;                 // at most Np + 2
+  long long wait_limit;          // ticks
+};
+bool fix_small_supported(int prec, int64_t np);
+// Tile-configuration id that selects it for the plain series (the product
+// kernels' configurations are 0 .. nt_config_count - 1; for every other use
+// of the product step this id falls back to the size rule).
+constexpr int kCfgWholeFixpoint = 5;
+// The cooperative launch; with clear_first, a kernel that zeroes the
+// counters runs before it (needed once for fresh memory and after an abort).
+// Counter words (32-bit) for padded size np: fix_small_words(np), the first
+// 2 tiles (np + 3) of them holding ones_row (8-byte aligned).
+hipError_t launch_fix_small(int prec, const FixSmallParams& p, bool clear_first, hipStream_t s);
+inline int64_t fix_small_words(int64_t np) { return 3 * (np / 32) * (np + 3) + (np / 32) + 2; }
+// Points the counters of p into `words` (fix_small_words(p.Np) of them, 8-byte aligned).
+inline void fix_small_place(FixSmallParams& p, unsigned* words) {
+  const int64_t rows = (int64_t)p.tiles * (p.Np + 3);
+  p.ones_row = (unsigned long long*)words;
+  p.rowstep = words + 2 * rows;
+  p.krow = p.rowstep + rows;
+  p.finished = p.krow + p.tiles;
+}
+
 // Launch helpers implemented in bool_kernels.hip.
 struct TileCfg {
   int bm, bn, kb, threads;

@@ -50,6 +50,8 @@ struct dl_ctx {
   std::vector<std::pair<int, int>> pending;  // (class, pair index) to add to ms / launches
   dl::EpsWorkspace eps;  // workspace of the epsilon solve
   std::vector<TuneEntry> tuned;  // tile configurations that override the size rule
+  unsigned* fs_words = nullptr;  // counters of the one-launch plain fixpoint (zero between launches)
+  bool fs_dirty = false;         // a launch ended abnormally: clear them before the next
 };
 
 namespace dl {
@@ -57,4 +59,6 @@ void set_last_error(const std::string& m);
 // Tile configuration of the product kernels for (prec, Np): the tuned entry
 // if there is one, else the size rule of choose_nt_config.
 int pick_config(const dl_ctx* c, int prec, int64_t np);
+// The tuned or set entry for (prec, Np), -1 if there is none.
+int tuned_config(const dl_ctx* c, int prec, int64_t np);
 }  // namespace dl

@@ -44,10 +44,15 @@ int hip_fail(hipError_t e, const char* what) {
 namespace dl {
 void set_last_error(const std::string& m) { g_last_error = m; }
 
-int pick_config(const dl_ctx* c, int prec, int64_t np) {
+int tuned_config(const dl_ctx* c, int prec, int64_t np) {
   for (const auto& t : c->tuned)
     if (t.prec == prec && t.np == np) return t.cfg;
-  return choose_nt_config(prec, np);
+  return -1;
+}
+
+int pick_config(const dl_ctx* c, int prec, int64_t np) {
+  const int t = tuned_config(c, prec, np);
+  return (t >= 0 && t != kCfgWholeFixpoint) ? t : choose_nt_config(prec, np);
 }
 }  // namespace dl
 
@@ -383,6 +388,62 @@ class Fix {
   bool r_is_s0_ = false;  // the caller's R is iterate buffer S[0]
 };
 
+// The plain series at small Np as one cooperative launch (k_fix_small): the
+// iterates in the slot's workspace, its ring for the model sizes and its
+// convergence word for the kernel's status, read back once at the end.  The
+// kernel writes R itself.
+constexpr long long kFixSmallWaitTicks = 200000000;  // 2 s of s_memrealtime (100 MHz)
+
+int run_plain_whole(dl_ctx* c, uint8_t* ws, int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr,
+                    int prec, int32_t max_steps, int64_t* ones_out, int32_t* steps_out, int32_t* converged_out,
+                    hipStream_t s) {
+  const int64_t Np = padded_size_for(prec, n);
+  const size_t matT = (size_t)mat_bytes(prec, Np);
+  FixSmallParams p{};
+  p.A = A;
+  p.lda = lda;
+  p.R = R;
+  p.ldr = ldr;
+  p.S[0] = ws;
+  p.S[1] = ws + matT;
+  p.n = (int)n;
+  p.Np = (int)Np;
+  p.tiles = (int)(Np / 32);
+  p.max_steps = (int)std::min<int64_t>(max_steps, Np + 2);
+  p.wait_limit = kFixSmallWaitTicks;
+  fix_small_place(p, c->fs_words);
+  // results straight into the pinned host ring of slot 0 and the word after it
+  p.ring_out = c->h_ring_dev;
+  p.status_out = (unsigned*)(c->h_ring_dev + kRing);
+  volatile unsigned* st = (volatile unsigned*)(c->h_ring + kRing);
+  st[0] = ~0u;
+  st[1] = 0u;
+  const bool clear = c->fs_dirty;
+  c->fs_dirty = true;  // until the launch is known to have ended normally
+  DL_HIP(launch_fix_small(prec, p, clear, s));
+  DL_HIP(hipStreamSynchronize(s));
+  if (st[1]) return fail(DL_EHIP, "whole-fixpoint kernel: a wait for other workgroups ran past its time limit");
+  if (st[0] == ~0u || st[0] > (unsigned)p.max_steps) return fail(DL_EHIP, "whole-fixpoint kernel reported no result");
+  c->fs_dirty = false;
+  const volatile unsigned long long* ring = c->h_ring;
+  const int64_t K = st[0];
+  // the first repeat of the whole matrix's model sizes (at K if it converged)
+  int64_t k = 1, conv = 0;
+  for (; k <= K; ++k) {
+    const unsigned long long prev = k == 1 ? 0ull : ring[k - 1];
+    if (ring[k] == prev) {
+      conv = 1;
+      break;
+    }
+  }
+  const int64_t steps = conv ? k : K;
+  if (ones_out)
+    for (int64_t j = 0; j <= steps; ++j) ones_out[j] = (int64_t)ring[j];
+  if (steps_out) *steps_out = (int32_t)steps;
+  if (converged_out) *converged_out = (int32_t)conv;
+  return DL_OK;
+}
+
 // Runs `count` fixpoints of one size, mode and precision on stream s, with
 // up to two in flight: while the host reads one's counters back, the device
 // runs the other's products.  Per-fixpoint outputs are indexed by g;
@@ -408,6 +469,22 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
   }
   const int64_t Np = padded_size_for(prec, n);
   const size_t need = fix_ws_bytes(prec, Np);
+  // the plain series takes the whole-fixpoint kernel where it applies unless
+  // the caller set another configuration for this size (an entry recorded
+  // by dl_tune names the fastest product kernel, which this path does not use)
+  const TuneEntry* te = nullptr;
+  for (const auto& t : c->tuned)
+    if (t.prec == prec && t.np == Np) te = &t;
+  const bool forced_other = te && te->cfg != kCfgWholeFixpoint && te->ms == 0.0;
+  if (mode == M_PLAIN && max_steps >= 1 && fix_small_supported(prec, Np) && !forced_other) {
+    if ((rc = ensure_ws(c, need))) return rc;
+    for (int g = 0; g < count; ++g)
+      if ((rc = run_plain_whole(c, (uint8_t*)c->ws, n, A[g], lda, R[g], ldr, prec, max_steps,
+                                g == 0 ? ones_out : nullptr, steps_out ? steps_out + g : nullptr,
+                                converged_out ? converged_out + g : nullptr, s)))
+        return rc;
+    return DL_OK;
+  }
   int nslots = count >= 2 ? kFixSlots : 1;
   if (nslots > 1 && c->budget && need * nslots > c->budget) nslots = 1;  // one at a time within the budget
   if ((rc = ensure_ws(c, need * nslots))) return rc;
@@ -514,6 +591,11 @@ int dl_create(dl_ctx** out, int device, size_t budget) {
   if ((e = hipMemset(c->ring, 0, kFixSlots * kSlotWords * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemset(ring)"));
   if ((e = hipMemset(c->conv, 0, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMemset(conv)"));
+  {
+    const size_t fsb = (size_t)fix_small_words(512) * sizeof(unsigned);
+    if ((e = hipMalloc(&c->fs_words, fsb)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(fixpoint counters)"));
+    if ((e = hipMemset(c->fs_words, 0, fsb)) != hipSuccess) return cleanup(hip_fail(e, "hipMemset(fixpoint counters)"));
+  }
   if ((e = hipDeviceSynchronize()) != hipSuccess) return cleanup(hip_fail(e, "init sync"));
   *out = c;
   return DL_OK;
@@ -526,6 +608,7 @@ int dl_destroy(dl_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->ring) (void)hipFree(c->ring);
   if (c->conv) (void)hipFree(c->conv);
+  if (c->fs_words) (void)hipFree(c->fs_words);
   if (c->h_ring) (void)hipHostFree(c->h_ring);
   if (c->h_conv) (void)hipHostFree(c->h_conv);
   for (auto& ep : c->events) {

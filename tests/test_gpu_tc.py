@@ -265,7 +265,9 @@ def test_autotune(dl, tmp_path):
     with pytest.raises(dl.DLError):
         fresh.set_tuning("f32", 512, 3)  # the 32 x 32 x 32 configuration is int8 only
     with pytest.raises(dl.DLError):
-        fresh.set_tuning("i8", 512, 5)
+        fresh.set_tuning("i8", 512, 6)  # no such configuration
+    with pytest.raises(dl.DLError):
+        fresh.set_tuning("i8", 1024, 5)  # the one-launch fixpoint stops at Np = 512
     with pytest.raises(dl.DLError):
         fresh.set_tuning("f32", 1024, 4)  # 4 KB operand rows do not fit the whole-K tile
     fresh.set_tuning("i8", 1000, -1)
@@ -327,6 +329,75 @@ def test_config_n8192_fp32_plain(dl, pname, p):
     for seed in range(3):
         a = dlgen.to_dense(n, dlgen.er_edges(n, p, seed))
         _check_closure(dl, a, dl.DL_TC_PLAIN, "f32", f"cfg8192 fp32 p={pname} seed={seed}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_whole_fixpoint_kernel_vs_chunked(dl, prec):
+    """The plain series in one launch (tile configuration 5, the default at
+    Np <= 512) and the chunked product kernels (configuration 4 set by the
+    caller) against the oracle: ragged sizes over one and two 256-blocks,
+    strided input and output, per-step model sizes and capped runs."""
+    import torch
+
+    for n in (1, 33, 256, 300, 512):
+        a = dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n if n > 2 else 0.5, 70 + n, self_loops=True))
+        ref, ones, it_ref, _ = oracle.tc_seminaive(a)
+        for cfg in (5, 4):
+            ctx = dl.Context()
+            ctx.set_tuning(prec, n, cfg)
+            announce("whole fixpoint", prec, n, cfg)
+            big = torch.zeros((n, n + 19), dtype=torch.uint8, device="cuda")
+            big[:, 3:n + 3] = dev(a * np.uint8(5))
+            out = torch.full((n, n + 7), 9, dtype=torch.uint8, device="cuda")
+            r, iters = dl.dl_tc(big[:, 3:n + 3], method=dl.DL_TC_PLAIN, prec=prec, out=out[:, :n], ctx=ctx)
+            assert np.array_equal(host(r), ref), (prec, n, cfg)
+            assert iters == it_ref
+            assert bool((out[:, n:] == 9).all())  # padding columns of R untouched
+            sr = dl.dl_tc_steps(dev(a), method=dl.DL_TC_PLAIN, prec=prec, max_steps=it_ref + 3, ctx=ctx)
+            assert sr.steps == it_ref and sr.converged
+            assert sr.ones == [int(x) for x in ones]
+            for k in (1, 2, max(1, it_ref - 1)):
+                sk = dl.dl_tc_steps(dev(a), method=dl.DL_TC_PLAIN, prec=prec, max_steps=k, ctx=ctx)
+                want, ones_k, _, conv_k = oracle.tc_seminaive(a, maxsteps=k)
+                assert np.array_equal(host(sk.R), want), (prec, n, cfg, k)
+                assert sk.steps == min(k, it_ref) and sk.converged == (k >= it_ref)
+                assert sk.ones == [int(x) for x in ones_k]
+            ctx.close()
+
+
+def test_whole_fixpoint_kernel_closed_forms(dl):
+    """Closed forms on the one-launch kernel: the empty relation (iters 1),
+    the complete digraph (iters 3), a directed cycle of 512 constants
+    (D = 512, so 513 iterations: the longest series the kernel can see at
+    Np = 512) and a path of 300."""
+    n = 512
+    cyc = np.zeros((n, n), np.uint8)
+    cyc[np.arange(n), (np.arange(n) + 1) % n] = 1
+    path = np.eye(300, k=1, dtype=np.uint8)
+    cases = [(np.zeros((n, n), np.uint8), np.zeros((n, n), np.uint8), 1),
+             (1 - np.eye(n, dtype=np.uint8), np.ones((n, n), np.uint8), 3),
+             (cyc, np.ones((n, n), np.uint8), n + 1),
+             (path, np.triu(np.ones((300, 300), np.uint8), 1), 300)]
+    for a, want, it_want in cases:
+        for prec in ("f32", "i8"):
+            announce("whole fixpoint closed form", a.shape[0], prec, it_want)
+            r, iters = dl.dl_tc(dev(a), method=dl.DL_TC_PLAIN, prec=prec)
+            assert iters == it_want and np.array_equal(host(r), want)
+
+
+def test_whole_fixpoint_config_validation(dl):
+    ctx = dl.Context()
+    ctx.set_tuning("f32", 512, 5)
+    ctx.set_tuning("i8", 300, 5)
+    with pytest.raises(dl.DLError):
+        ctx.set_tuning("f32", 513, 5)  # Np = 768: rows of 3 KB
+    with pytest.raises(dl.DLError):
+        ctx.set_tuning("i8", 1000, 5)
+    # squaring on a context whose entry is 5 falls back to the size rule
+    a = dlgen.to_dense(300, dlgen.er_edges(300, 2.0 / 300, 3))
+    r, _ = dl.dl_tc(dev(a), method=dl.DL_TC_SQUARE, prec="i8", ctx=ctx)
+    assert np.array_equal(host(r), oracle.tc_seminaive(a)[0])
+    ctx.close()
 
 
 def test_tile_configs_sizes(dl):
