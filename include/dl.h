@@ -123,6 +123,20 @@ int dl_tc_steps(dl_ctx* ctx, int64_t n, const uint8_t* A, int64_t lda, uint8_t* 
 int dl_tc_batch(dl_ctx* ctx, int32_t count, int64_t n, const uint8_t* const* A, int64_t lda,
                 uint8_t* const* R, int64_t ldr, int method, int prec, int32_t* iters, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dl_tc with
+ * method DL_TC_PLAIN for n <= 512 constants, any dl_prec, run by the same
+ * one-launch kernel (tile configuration 5), with every device buffer it
+ * needs (two iterates, counters, read-back words: 2.2 MB at most) in a
+ * static device array that each GPU holds from the first call on it until
+ * the process ends.  Allocates nothing and takes no context.  The current device is the
+ * one used.  Calls on one GPU share that array: calls that overlap on one
+ * GPU (other threads, other streams) race and must not be made.  Arguments
+ * and results as dl_tc; n above the limit is DL_EINVAL; blocks until iters
+ * is known. */
+int dl_tc_noalloc(int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t ldr, int prec,
+                  int32_t* iters, void* stream);
+
 /* Same generation (Sec. 7.2): least S with S = min1(I + P S P^T), where P is
  * the r1 relation (device uint8 [n x ldp]) and I encodes diag(x, x) for
  * every constant.  Each step runs two products, T = min1(P S) and

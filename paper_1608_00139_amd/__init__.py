@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "DL_TC_PLAIN", "DL_TC_SQUARE", "DL_I8", "DL_F32", "DL_BF16", "DL_FP8", "DL_FP4",
     "DLError", "Context", "lib_path", "load",
-    "dl_tc", "dl_tc_steps", "dl_tc_batch", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
+    "dl_tc", "dl_tc_steps", "dl_tc_batch", "dl_tc_noalloc", "dl_sg", "dl_sg_steps", "dl_solve_eps", "dl_eps_bound", "dl_sg_eps",
     "dl_padded_size", "Batch", "DL_EAGAIN", "dl_solve_linear", "dl_solve_two_sided", "Program",
     "DL_EVAL_ITERATION", "DL_EVAL_MATRIX", "dl_measure_peak",
 ]
@@ -71,6 +71,7 @@ def load() -> ctypes.CDLL:
         "dl_sg": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, pi32, vp], ctypes.c_int),
         "dl_sg_steps": ([vp, i64, vp, i64, vp, i64, ctypes.c_int, i32, pi64, pi32, pi32, vp], ctypes.c_int),
         "dl_solve_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, pi32, vp], ctypes.c_int),
+        "dl_tc_noalloc": ([i64, vp, i64, vp, i64, ctypes.c_int, pi32, vp], ctypes.c_int),
         "dl_eps_bound": ([vp, i64, vp, i64, ctypes.POINTER(dbl), vp], ctypes.c_int),
         "dl_sg_eps": ([vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp], ctypes.c_int),
         "dl_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
@@ -270,6 +271,19 @@ def dl_tc(A: torch.Tensor, method: int = DL_TC_SQUARE, prec=DL_I8, out: torch.Te
     c = _ctx(ctx)
     _check(load().dl_tc(c.handle, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()), ldr,
                         int(method), _prec(prec), ctypes.byref(it), _stream_ptr(stream)))
+    return R, int(it.value)
+
+
+def dl_tc_noalloc(A: torch.Tensor, prec=DL_I8, out: torch.Tensor | None = None,
+                  stream=None) -> tuple[torch.Tensor, int]:
+    """Plain closure of A (n <= 512) without any device allocation by the
+    library (its buffers live in a static device array): (R, iters)."""
+    n, lda = _mat(A, "A")
+    R = out if out is not None else torch.empty((n, n), dtype=torch.uint8, device=A.device)
+    _, ldr = _mat(R, "R")
+    it = ctypes.c_int32()
+    _check(load().dl_tc_noalloc(n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()), ldr,
+                                _prec(prec), ctypes.byref(it), _stream_ptr(stream)))
     return R, int(it.value)
 
 

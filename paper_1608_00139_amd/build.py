@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libdl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["bool_kernels.hip", "eps_solve.hip", "prog_kernels.hip", "peak.hip", "dl_api.cpp", "serve.cpp", "program.cpp"]
+SOURCES = ["bool_kernels.hip", "eps_solve.hip", "prog_kernels.hip", "peak.hip", "dl_api.cpp", "serve.cpp", "program.cpp",
+           "noalloc.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -723,7 +723,7 @@ static hipError_t set_lds_attr_small() {
 // leaves, and every other wait sees the abort word and leaves.  On stopping,
 // each workgroup writes its tile of the last iterate into the caller's R,
 // transposed back and cropped to n x n.  The last workgroup to finish writes
-// ring_out[0 .. K] and status_out[0] = K, then zeroes the counters for the
+// ring_out[0 .. K] and status_out = {K, 0}, then zeroes the counters for the
 // next launch.
 
 __device__ inline unsigned ld_agent(const unsigned* p) {
@@ -953,7 +953,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
     }
     p.ring_out[s] = sum;
   }
-  if (tid == 0) p.status_out[0] = (unsigned)K;
+  if (tid == 0) {
+    p.status_out[0] = (unsigned)K;
+    p.status_out[1] = 0u;
+  }
   __syncthreads();
   // every other workgroup is done with the counters: zero them
   const int64_t rows = (int64_t)p.tiles * stride;
