@@ -64,6 +64,8 @@ def main() -> int:
                     help="summarise a rocprofv3 --kernel-trace results database and exit")
     ap.add_argument("--eps-only", action="store_true",
                     help="run only the fp64 epsilon solve on the p = 4/N, seed 0 graph (for kernel traces) and exit")
+    ap.add_argument("--peaks", action="store_true",
+                    help="print the measured matrix-core rates and LDS data-path rates (dl_measure_peak) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain 1 GiB device copies (traffic-counter calibration) and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
@@ -74,6 +76,9 @@ def main() -> int:
     ap.add_argument("--counter-summary", metavar="CSV",
                     help="per-launch averages of every counter in a rocprofv3 --pmc CSV for the step kernel, "
                          "per CU cycle, and exit")
+    ap.add_argument("--kernel", metavar="SUBSTRING",
+                    help="with --counter-summary: summarise the kernels whose name contains SUBSTRING "
+                         "(the most launched one) instead of the int8 step kernel")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving workload (--serve-requests of them) and print its JSON")
     ap.add_argument("--programs-only", action="store_true",
@@ -102,9 +107,11 @@ def main() -> int:
     if args.mfma_summary:
         return mfma_summary(args.mfma_summary)
     if args.counter_summary:
-        return counter_summary(args.counter_summary)
+        return counter_summary(args.counter_summary, args.kernel)
     if args.copy_calibration:
         return copy_calibration()
+    if args.peaks:
+        return peaks()
     if args.eps_only:
         return eps_only()
     if args.gpus != 1:
@@ -380,7 +387,9 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
                     "threshold_errors_vs_int8_model": int((s != ref).sum().item())})
     res["sg_eps_fp64_n4096"] = sge
     res["measured_mfma_peaks_tops"] = {k: round(dl.dl_measure_peak(k, ctx=ctx) / 1e12, 1)
-                                       for k in ("i8", "fp8", "fp4", "bf16", "f32", "f64")}
+                                       for k in ("i8", "fp8", "fp4", "bf16", "f32", "f64", "f64_agpr")}
+    res["measured_lds_rates_tb_per_s"] = {k: round(dl.dl_measure_peak(k, ctx=ctx) / 1e12, 1)
+                                          for k in ("lds_read", "lds_fill")}
     torch.cuda.empty_cache()
     res["programs"] = run_programs(dl, ctx, torch)
     res["paper_workloads"] = run_paper_workloads(dl, ctx, torch)
@@ -705,6 +714,27 @@ def eps_only(reps: int = 3) -> int:
     return 0
 
 
+def peaks(reps: int = 3) -> int:
+    """dl_measure_peak for every kind, `reps` times each: matrix-core rates in
+    TOPS / TFLOP/s, LDS read and global-to-LDS fill rates in TB/s and in
+    bytes per clock per CU at 2.4 GHz (256 CUs)."""
+    import torch
+
+    import paper_1608_00139_amd as dl
+
+    torch.cuda.set_device(0)
+    ctx = dl.Context(0)
+    for kind in ("i8", "fp8", "fp4", "bf16", "f32", "f64", "f64_agpr", "lds_read", "lds_fill"):
+        vals = [dl.dl_measure_peak(kind, ctx=ctx) for _ in range(reps)]
+        if kind.startswith("lds"):
+            print(f"{kind}: " + ", ".join(f"{v / 1e12:.1f} TB/s ({v / 256 / 2.4e9:.0f} B/clk/CU)" for v in vals),
+                  flush=True)
+        else:
+            print(f"{kind}: " + ", ".join(f"{v / 1e12:.1f} T/s" for v in vals), flush=True)
+    ctx.close()
+    return 0
+
+
 def copy_calibration() -> int:
     """Three plain device copies of 1 GiB: read 1 GiB and write 1 GiB each."""
     import torch
@@ -826,7 +856,7 @@ def mfma_summary(csv_path: str) -> int:
     return 0
 
 
-def counter_summary(csv_path: str) -> int:
+def counter_summary(csv_path: str, kernel: str | None = None) -> int:
     """Averages over the step kernel's full launches (duration above 10% of
     the longest) of each counter in a rocprofv3 --pmc CSV, also divided by
     the kernel's CU cycles (GRBM_GUI_ACTIVE / XCDs x CUs; the CSV must hold
@@ -848,9 +878,10 @@ def counter_summary(csv_path: str) -> int:
         d[r["Counter_Name"]] = float(r["Counter_Value"])
     counts = {}
     for d in disp.values():
-        if "k_nt_dma" in d["name"] and ("OpI8," in d["name"] or "OpI8x32," in d["name"]):
+        if (kernel is not None and kernel in d["name"]) or (
+                kernel is None and "k_nt_dma" in d["name"] and ("OpI8," in d["name"] or "OpI8x32," in d["name"])):
             counts[d["name"]] = counts.get(d["name"], 0) + 1
-    top = max(counts, key=counts.get)  # the timed workload's step kernel
+    top = max(counts, key=counts.get)  # the timed workload's step kernel, or the named one
     ds = [d for d in disp.values() if d["name"] == top]
     top = max(d["ns"] for d in ds)
     ds = [d for d in ds if d["ns"] >= 0.1 * top]

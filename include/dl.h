@@ -239,7 +239,14 @@ int dl_kernel_stats(dl_ctx* ctx, int kernel_class, int64_t* launches, double* to
  * receives the rate in operations per second (2 M N K per instruction).
  * kind: 0 int8 (32x32x32, the faster int8 shape), 1 fp32 16x16x4, 2 bf16
  * 16x16x32, 3 fp8 e4m3 and 4 fp4 e2m1 16x16x128, 5 fp64 16x16x4.  A reference for the kernels' rates
- * beside the datasheet figures. */
+ * beside the datasheet figures.  Two data-path kinds report bytes per second
+ * instead: 6 LDS reads (ds_read_b128, 1 KB per wave and instruction, no bank
+ * conflicts, 16 waves per compute unit), 7 global-to-LDS fills
+ * (global_load_lds_dwordx4 from a 1 MB L2-resident buffer, eight
+ * instructions in flight per wave; uses 1 MB of the context's workspace).
+ * Kind 8 is kind 5 with the accumulators in AGPRs instead of architectural
+ * VGPRs (the library's fp64 kernels use VGPRs: on gfx950 the AGPR form runs
+ * the fp64 MFMA at about 60% of the VGPR form's rate). */
 int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream);
 
 /* Tile autotuner for the product step shared by every fixpoint (Sec. 3's

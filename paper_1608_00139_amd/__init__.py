@@ -524,11 +524,13 @@ class Program:
         return out, int(ones.value)
 
 
-PEAK_KINDS = {"i8": 0, "f32": 1, "bf16": 2, "fp8": 3, "fp4": 4, "f64": 5}
+PEAK_KINDS = {"i8": 0, "f32": 1, "bf16": 2, "fp8": 3, "fp4": 4, "f64": 5, "lds_read": 6, "lds_fill": 7,
+              "f64_agpr": 8}
 
 
 def dl_measure_peak(kind: str, ctx: Context | None = None, stream=None) -> float:
-    """Measured MFMA throughput of the device in operations per second."""
+    """Measured MFMA throughput of the device in operations per second
+    (kinds "lds_read" and "lds_fill": bytes per second of the LDS data paths)."""
     out = ctypes.c_double()
     c = _ctx(ctx)
     _check(load().dl_measure_peak(c.handle, PEAK_KINDS[kind], ctypes.byref(out), _stream_ptr(stream)))

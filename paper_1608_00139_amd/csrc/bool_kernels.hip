@@ -1041,6 +1041,7 @@ size_t group_dma_lds();
 
 hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
   if (nreq <= 0 || total_tiles <= 0) return hipSuccess;
+  if (nreq > kMaxGroupRequests) return hipErrorInvalidValue;
   if (tile == 64) {
     typedef NTKernel<64, 64, 32, 32, 64, OpI8, 2, 1> K;
     hipLaunchKernelGGL(k_group_step<64>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
@@ -1104,6 +1105,13 @@ struct DmaKernel {
   static_assert((BM * BN / 16) % NT == 0, "epilogue segments must divide evenly");
 };
 
+// Workgroup barrier that orders this wave's LDS accesses only: global
+// stores and direct-to-LDS loads in flight stay in flight (__syncthreads
+// would wait for every one of them).  The memory clobber keeps the compiler
+// from moving memory accesses across it.  For LDS data written by plain LDS
+// stores; data that arrives by direct-to-LDS loads needs wait_vmcnt first.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // s_waitcnt with vmcnt = N and no wait on the other counters (gfx9
 // encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 template <int N>
@@ -1129,7 +1137,10 @@ __device__ inline void wait_vmcnt() {
 // stores four 16-byte segments of out^T.  Returns this thread's ones.
 __device__ inline int ep_swz(int r) { return (r ^ (r >> 4)) & 15; }
 
-template <class K, class Op>
+// HAS_ADD: p.add is set.  Without an addend no global load is issued here,
+// so nothing in the epilogue waits on memory (a next tile's first slice
+// prefetched just before it stays in flight).
+template <class K, class Op, bool HAS_ADD>
 __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op::Acc (&acc)[K::FM][K::FN],
                                            uint8_t* et, int row0, int col0, int wm, int wn, int lane, int tid) {
   static_assert((K::FR == 16 && Op::NI == 4) || (K::FR == 32 && Op::NI == 16), "16 x 16 or 32 x 32 fragments");
@@ -1154,14 +1165,14 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
 #pragma unroll
   for (int e = 0; e < NSEG; ++e) {
     addv[e] = u32x4{0u, 0u, 0u, 0u};
-    if (p.add) addv[e] = load_add16<Op::kPrec>(p, row0 + seg_row(e), col0 + seg_col(e));
+    if constexpr (HAS_ADD) addv[e] = load_add16<Op::kPrec>(p, row0 + seg_row(e), col0 + seg_col(e));
   }
   // one 16-byte output segment: addend, identity, count, store, LDS copy
   // (with the identity when the transposed copy is the next step's Y)
   auto emit = [&](u32x4 v, int e) {
     const int lr = seg_row(e), lc = seg_col(e);
     const int gr = row0 + lr, gc = col0 + lc;
-    v |= addv[e];
+    if constexpr (HAS_ADD) v |= addv[e];
     if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
     cnt += popc16(v);
     store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
@@ -1216,7 +1227,7 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
     }
   }
   if (p.outT) {
-    __syncthreads();
+    lds_barrier();  // the staged tile; the next tile's prefetched slice may stay in flight
     uint8_t* outt = (uint8_t*)p.outT;
     constexpr int RB = BM / 16, CB = BN / 4;
     for (int blk = tid; blk < RB * CB; blk += K::NT) {
@@ -1384,8 +1395,9 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
 
   int cnt = 0;
   if constexpr (K::SWAPPED) {
-    cnt = dma_epilogue_swapped<K, Op>(p, acc, prefetch ? smem + K::STAGE_BYTES : smem, row0, col0, wm, wn, lane,
-                                      tid);
+    uint8_t* et = prefetch ? smem + K::STAGE_BYTES : smem;
+    cnt = p.add ? dma_epilogue_swapped<K, Op, true>(p, acc, et, row0, col0, wm, wn, lane, tid)
+                : dma_epilogue_swapped<K, Op, false>(p, acc, et, row0, col0, wm, wn, lane, tid);
   } else {
     // ---- epilogue of k_nt_step: the 0/1 tile through LDS byte by byte
     constexpr int SEG_PER_ROW = BN / 16;
@@ -1447,12 +1459,16 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
     __shared__ int red[K::NWAVES];
     cnt = wave_sum(cnt);
     if (lane == 0) red[wave] = cnt;
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) {
       unsigned long long t = 0;
 #pragma unroll
       for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
-      if (t) atomicAdd(p.ones + (p.step % kRing), t);
+      // a global (not flat) atomic: a flat one would first wait for the
+      // prefetched slice, whose LDS writes it might alias
+      if (t)
+        __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)(p.ones + (p.step % kRing)), t,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   return prefetch;
@@ -1496,23 +1512,32 @@ k_nt_dma(NTParams p) {
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
 k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  auto find = [&](int item) {  // last request whose first tile is <= item
-    int lo = 0, hi = nreq - 1;
+  // every request's first tile, in LDS: the search for a tile's request
+  // takes LDS reads instead of a chain of dependent global loads
+  int* first = (int*)(smem + DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES);
+  for (int i = threadIdx.x; i < nreq; i += blockDim.x) first[i] = desc[i].tile_start;
+  __syncthreads();
+  auto find = [&](int item, int lo) {  // last request whose first tile is <= item, at or after lo
+    int hi = nreq - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (desc[mid].tile_start <= item) lo = mid;
+      if (first[mid] <= item) lo = mid;
       else hi = mid - 1;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
   };
   bool pre = false;  // this tile's first slice is in flight already
-  for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
-    const GroupDesc& g = desc[find(item)];
+  int item = xcd_logical(blockIdx.x, gridDim.x);
+  int cur = item < total_tiles ? find(item, 0) : 0;  // the items of a workgroup only grow
+  for (; item < total_tiles; item += gridDim.x) {
+    const GroupDesc& g = desc[cur];
     const int local = item - g.tile_start;
     const int tiles_n = g.Np / 256;
     DmaPanels next;
+    int nxt = cur;
     if (item + (int)gridDim.x < total_tiles) {
-      const GroupDesc& h = desc[find(item + gridDim.x)];
+      nxt = find(item + gridDim.x, cur);
+      const GroupDesc& h = desc[nxt];
       const int nl = item + gridDim.x - h.tile_start, nt = h.Np / 256;
       next.ldb = h.Np;
       next.X = (const uint8_t*)h.X + (int64_t)(nl / nt) * 256 * h.Np;
@@ -1536,6 +1561,7 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     int tid;
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
     pre = nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, local / tiles_n, local % tiles_n, smem, tid, pre, next);
+    cur = nxt;
   }
 }
 
@@ -1629,7 +1655,8 @@ static TileCfg cfg_of(int cfg) {
   }
 }
 
-size_t group_dma_lds() { return DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES; }
+// the operand ring and epilogue, then the first tile of each request (up to kMaxGroupRequests)
+size_t group_dma_lds() { return DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES + kMaxGroupRequests * sizeof(int); }
 
 hipError_t bool_kernels_init() {
   hipError_t e;

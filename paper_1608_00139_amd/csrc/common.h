@@ -177,10 +177,14 @@ hipError_t launch_scatter_edges(const int32_t* edges, int64_t m, int n, int Np, 
                                 unsigned long long* ones, hipStream_t s);
 hipError_t bool_kernels_init();
 // Measured matrix-core throughput (operations per second) of MFMA kind 0 int8,
-// 1 fp32, 2 bf16, 3 fp8, 4 fp4, 5 fp64 on the current device; `sink` must hold
-// 256 ints (never written).
-hipError_t measure_peak(int kind, int* sink, double* ops_per_s, hipStream_t s);
-// tile: 64, 128 or 256 (every request of the list has Np a multiple of it)
+// 1 fp32, 2 bf16, 3 fp8, 4 fp4, 5 fp64 on the current device, or bytes per
+// second of kind 6 (LDS reads, ds_read_b128) and 7 (global-to-LDS fill,
+// global_load_lds_dwordx4 from 1 MB at src); kind 8 is kind 5 with AGPR
+// accumulators.  `sink` must hold 256 ints (never written).
+hipError_t measure_peak(int kind, int* sink, double* ops_per_s, hipStream_t s, const uint8_t* src);
+// tile: 64, 128 or 256 (every request of the list has Np a multiple of it);
+// at most kMaxGroupRequests requests per launch
+constexpr int kMaxGroupRequests = kRing;
 hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
 
 }  // namespace dl

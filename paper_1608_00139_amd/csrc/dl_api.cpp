@@ -575,6 +575,7 @@ int dl_create(dl_ctx** out, int device, size_t budget) {
   };
   if ((e = hipSetDevice(device)) != hipSuccess) return cleanup(hip_fail(e, "hipSetDevice"));
   if ((e = bool_kernels_init()) != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
+  if ((e = dl::eps_kernels_init()) != hipSuccess) return cleanup(hip_fail(e, "kernel attributes"));
   if ((e = hipMalloc(&c->ring, kFixSlots * kSlotWords * sizeof(unsigned long long))) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc(ring)"));
   if ((e = hipMalloc(&c->conv, 64 * sizeof(int))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(conv)"));
@@ -1016,10 +1017,11 @@ int dl_solve_two_sided(dl_ctx* ctx, int64_t n, const uint8_t* Q, int64_t ldq, co
 
 int dl_measure_peak(dl_ctx* ctx, int kind, double* ops_per_s, void* stream) {
   if (!ctx || !ops_per_s) return fail(DL_EINVAL, "NULL argument");
-  if (kind < 0 || kind > 5) return fail(DL_EINVAL, "unknown MFMA kind");
+  if (kind < 0 || kind > 8) return fail(DL_EINVAL, "unknown kind");
   int rc = set_device(ctx);
   if (rc) return rc;
-  DL_HIP(measure_peak(kind, (int*)ctx->ring, ops_per_s, (hipStream_t)stream));
+  if (kind == 7 && (rc = ensure_ws(ctx, 1 << 20))) return rc;
+  DL_HIP(measure_peak(kind, (int*)ctx->ring, ops_per_s, (hipStream_t)stream, (const uint8_t*)ctx->ws));
   return DL_OK;
 }
 

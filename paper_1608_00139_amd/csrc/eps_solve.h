@@ -12,12 +12,16 @@ struct EpsWorkspace {
   void* buf = nullptr;
   size_t size = 0;
   hipStream_t side = nullptr;  // look-ahead stream of the elimination (default priority)
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t work = nullptr;  // the elimination's main stream (default priority)
+  bool masked = false;         // work and side run on disjoint compute units
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 // eps_free releases the buffer; eps_release also the stream and events.
 void eps_free(EpsWorkspace* ws);
 void eps_release(EpsWorkspace* ws);
+// Kernel attributes (once per device, at context creation).
+hipError_t eps_kernels_init();
 int64_t eps_padded_size(int64_t n);
 
 // Solves (I - eps B) X = eps C for X (fp64; B, C caller 0/1 bytes, nonzero =

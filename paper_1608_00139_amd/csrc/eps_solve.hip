@@ -27,6 +27,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <utility>
 #include <vector>
@@ -181,27 +182,42 @@ __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
       }
 }
 
+// Unused LDS requested with every launch so that one workgroup, not two, fits
+// a compute unit: the panel inverse that runs beside the trailing update on
+// the look-ahead stream (k_block_inverse, 1024 threads) then finds the
+// registers and LDS it needs next to a resident update workgroup instead of
+// waiting for a compute unit to drain.
+constexpr unsigned kDgemmLdsPad = 16384;
 static hipError_t dgemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.M % 128 || g.N % 128 || g.K % 16) return hipErrorInvalidValue;
   const int grid = (g.M / 128) * (g.N / 128);
-  hipLaunchKernelGGL((k_dgemm<128, 128, 16>), dim3(grid), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((k_dgemm<128, 128, 16>), dim3(grid), dim3(256), kDgemmLdsPad, s, g);
   return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- diagonal block inverse
 // In-place Gauss-Jordan inversion of the NB x NB block at W (ld), written to
-// Dinv (ld NB).  1024 threads; thread t owns row t / 8 and the 16 contiguous
-// columns 16 (t % 8) + m.  Step p broadcasts row p and column p through LDS
-// (double buffered, one barrier per step) and every thread then updates its
-// 16 entries without branches:
-//   row p:     a[p][j] /= a[p][p]  (j != p),   a[p][p] = 1 / a[p][p]
-//   other i:   a[i][j] -= (a[i][p] / a[p][p]) a[p][j]  (j != p),
-//              a[i][p]  = -a[i][p] / a[p][p]
+// Dinv (ld NB), with pivot blocks of PB rows and columns S = p .. p + PB - 1
+// (NB / PB steps of one barrier each).  1024 threads; thread t owns row t / 8
+// and the 16 contiguous columns 16 (t % 8) + m.  A step broadcasts the rows
+// and columns of S through LDS (double buffered); every thread inverts the
+// PB x PB pivot block P = a[S][S] itself (Gauss-Jordan in registers) and
+// updates its 16 entries:
+//   rows of S:   a[S][j] = P^-1 a[S][j]  (j not in S),   a[S][S] = P^-1
+//   other rows:  f = a[i][S] P^-1;  a[i][j] -= f a[S][j]  (j not in S),
+//                a[i][S] = -f
+// which is PB single-pivot steps done at once.  Signs: the block is a
+// strictly diagonally dominant M-matrix, so P^-1 >= 0 entrywise and, as for
+// single pivots, every update adds terms of one sign to each off-diagonal
+// entry (columns already pivoted hold entries >= 0, the others <= 0), so
+// zeros stay exact and nothing cancels.  The kernel runs beside the
+// trailing update (another stream): PB = 2 keeps it within the registers
+// that one resident update workgroup leaves free on a compute unit.
+constexpr int PB = 2;
 __global__ void __launch_bounds__(1024) k_block_inverse(const double* W, int64_t ld, double* Dinv) {
-  __shared__ __attribute__((aligned(16))) double rowbuf[2][NB];
-  __shared__ double colbuf[2][NB];
-  __shared__ double invbuf[2];
+  __shared__ __attribute__((aligned(16))) double rowbuf[2][PB][NB];
+  __shared__ double colbuf[2][PB][NB];
   const int t = threadIdx.x;
   const int i = t >> 3, j0 = (t & 7) * 16;
   double a[16];
@@ -211,40 +227,87 @@ __global__ void __launch_bounds__(1024) k_block_inverse(const double* W, int64_t
     a[m] = v.x;
     a[m + 1] = v.y;
   }
-  for (int p = 0; p < NB; ++p) {
-    const int b = p & 1;
-    const bool owns_col = (p >> 4) == (t & 7);  // this thread holds column p of its row
-    if (i == p) {
+  for (int p = 0; p < NB; p += PB) {
+    const int b = (p / PB) & 1;
+    const bool owns_cols = (p >> 4) == (t & 7);  // columns p .. p + PB - 1 are among this thread's 16
+    const int pc = p & 15;                       // their position in a[]
+    const int r_in = i - p;                      // row of S held by this thread, if 0 <= r_in < PB
+    const bool in_s = r_in >= 0 && r_in < PB;
+    if (in_s) {
 #pragma unroll
-      for (int m = 0; m < 16; m += 2) *(double2*)&rowbuf[b][j0 + m] = make_double2(a[m], a[m + 1]);
+      for (int m = 0; m < 16; m += 2) *(double2*)&rowbuf[b][r_in][j0 + m] = make_double2(a[m], a[m + 1]);
     }
-    if (owns_col) {
-      double v = a[0];
+    if (owns_cols) {
 #pragma unroll
-      for (int m = 1; m < 16; ++m) v = (m == (p & 15)) ? a[m] : v;
-      colbuf[b][i] = v;
-      if (i == p) invbuf[b] = 1.0 / v;  // one division per step
+      for (int k = 0; k < PB; ++k) {
+        double v = a[0];
+#pragma unroll
+        for (int m = 1; m < 16; ++m) v = (m == pc + k) ? a[m] : v;
+        colbuf[b][k][i] = v;
+      }
     }
     __syncthreads();
-    const double inv = invbuf[b];
-    if (i != p) {
-      // general rows: one fused multiply-add per entry
-      const double f = colbuf[b][i] * inv;
+    // P^-1 by Gauss-Jordan without pivoting (every thread, same result)
+    double q[PB][PB];
 #pragma unroll
-      for (int m = 0; m < 16; m += 2) {
-        const double2 r = *(const double2*)&rowbuf[b][j0 + m];
-        a[m] = __builtin_fma(-f, r.x, a[m]);
-        a[m + 1] = __builtin_fma(-f, r.y, a[m + 1]);
+    for (int r = 0; r < PB; ++r)
+#pragma unroll
+      for (int c = 0; c < PB; ++c) q[r][c] = rowbuf[b][r][p + c];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      const double inv = 1.0 / q[k][k];
+#pragma unroll
+      for (int r = 0; r < PB; ++r) {
+        if (r == k) continue;
+        const double f = q[r][k] * inv;
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c != k) q[r][c] = __builtin_fma(-f, q[k][c], q[r][c]);
+        q[r][k] = -f;
       }
-      if (owns_col) {  // column p receives -a[i][p] / a[p][p]
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-          if (m == (p & 15)) a[m] = -f;
+      for (int c = 0; c < PB; ++c) q[k][c] = (c == k) ? inv : q[k][c] * inv;
+    }
+    // the multipliers of this thread's row: f = a[i][S] P^-1 (other rows),
+    // or row r_in of P^-1 (rows of S)
+    double f[PB];
+    if (!in_s) {
+#pragma unroll
+      for (int c = 0; c < PB; ++c) f[c] = 0.0;
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        const double ck = colbuf[b][k][i];
+#pragma unroll
+        for (int c = 0; c < PB; ++c) f[c] = __builtin_fma(ck, q[k][c], f[c]);
       }
     } else {
-      // pivot row: scale by 1 / a[p][p]; the pivot itself becomes 1 / a[p][p]
 #pragma unroll
-      for (int m = 0; m < 16; ++m) a[m] = (j0 + m == p) ? inv : a[m] * inv;
+      for (int c = 0; c < PB; ++c) {
+        f[c] = q[0][c];
+#pragma unroll
+        for (int r = 1; r < PB; ++r) f[c] = (r == r_in) ? q[r][c] : f[c];
+      }
+    }
+    // other rows: a -= f a[S][.];  rows of S: a = f a[S][.] (sign and start differ)
+    const double sg = in_s ? 1.0 : -1.0;
+#pragma unroll
+    for (int m = 0; m < 16; m += 2) {
+      double2 acc = in_s ? make_double2(0.0, 0.0) : make_double2(a[m], a[m + 1]);
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        const double2 r = *(const double2*)&rowbuf[b][c][j0 + m];
+        acc.x = __builtin_fma(sg * f[c], r.x, acc.x);
+        acc.y = __builtin_fma(sg * f[c], r.y, acc.y);
+      }
+      a[m] = acc.x;
+      a[m + 1] = acc.y;
+    }
+    if (owns_cols) {  // the columns of S: -f (other rows) or P^-1 (rows of S)
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (m == pc + c) a[m] = sg * f[c];
     }
   }
 #pragma unroll
@@ -269,21 +332,24 @@ __global__ void __launch_bounds__(256) k_eps_init(const uint8_t* B, int64_t ldb,
 
 // R = [X > 0] (and X itself when asked for), plus the smallest positive
 // entry of X: its bits go into *minpos by an unsigned atomic minimum (positive
-// doubles order like their bit patterns), one per workgroup.
+// doubles order like their bit patterns), one per workgroup.  A fixed grid
+// walks the rows, so the atomics stay few.
+constexpr int kEmitBlocks = 1024;
 __global__ void __launch_bounds__(256)
 k_eps_emit(const double* W, int Np, int n, uint8_t* R, int64_t ldr, double* X, int64_t ldx,
            unsigned long long* minpos) {
   __shared__ unsigned long long red[4];
-  const int i = blockIdx.y;
   const int64_t ld = 2 * (int64_t)Np;
   unsigned long long m = ~0ull;
-  for (int j = blockIdx.x * 256 + threadIdx.x; j < n; j += gridDim.x * 256) {
-    const double x = W[i * ld + Np + j];
-    R[(int64_t)i * ldr + j] = x > 0.0 ? 1 : 0;
-    if (X) X[(int64_t)i * ldx + j] = x;
-    if (x > 0.0) {
-      const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-      m = b < m ? b : m;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const double x = W[i * ld + Np + j];
+      R[(int64_t)i * ldr + j] = x > 0.0 ? 1 : 0;
+      if (X) X[(int64_t)i * ldx + j] = x;
+      if (x > 0.0) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        m = b < m ? b : m;
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -301,6 +367,11 @@ k_eps_emit(const double* W, int Np, int n, uint8_t* R, int64_t ldr, double* X, i
 __global__ void k_set_word(unsigned long long* p, unsigned long long v) { *p = v; }
 
 // ----------------------------------------------------------------- driver
+hipError_t eps_kernels_init() {
+  return hipFuncSetAttribute((const void*)k_dgemm<128, 128, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kDgemmLdsPad);
+}
+
 int64_t eps_padded_size(int64_t n) { return n <= 0 ? 0 : ((n + NB - 1) / NB) * NB; }
 
 void eps_free(EpsWorkspace* ws) {
@@ -311,11 +382,13 @@ void eps_free(EpsWorkspace* ws) {
 
 void eps_release(EpsWorkspace* ws) {
   eps_free(ws);
-  for (auto& e : ws->ev)
+  for (auto& e : ws->ev) {
     if (e) (void)hipEventDestroy(e);
-  ws->ev[0] = ws->ev[1] = nullptr;
+    e = nullptr;
+  }
   if (ws->side) (void)hipStreamDestroy(ws->side);
-  ws->side = nullptr;
+  if (ws->work) (void)hipStreamDestroy(ws->work);
+  ws->side = ws->work = nullptr;
 }
 
 static hipError_t ensure(EpsWorkspace* ws, size_t budget_left, size_t need, const char* what, std::string* err) {
@@ -397,12 +470,24 @@ k_rows_store(const double* Y, int64_t ldy, int P, int64_t n, double* W, int64_t 
 // inverted on the side stream while the rest of the update runs.
 constexpr int kPanel = 4 * NB;
 
+// The elimination's two streams (default priority): the work stream takes
+// the updates, the side stream the look-ahead panel inverse.
+static hipError_t ensure_streams(EpsWorkspace* ws, std::string* err) {
+  if (ws->side) return hipSuccess;
+  EPS_CK(hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking), "side stream");
+  EPS_CK(hipStreamCreateWithFlags(&ws->work, hipStreamNonBlocking), "work stream");
+  for (auto& e : ws->ev) EPS_CK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  return hipSuccess;
+}
+
 static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t ldw, double* scratch, hipStream_t s,
                                bool timing, std::vector<std::pair<hipEvent_t, hipEvent_t>>* evs, std::string* err) {
-  if (!ws->side) {
-    EPS_CK(hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking), "side stream");
-    for (auto& e : ws->ev) EPS_CK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
-  }
+  // the caller's stream s hands over to the work stream and takes it back
+  EPS_CK(ensure_streams(ws, err), *err);
+  EPS_CK(hipEventRecord(ws->ev[2], s), "event");
+  EPS_CK(hipStreamWaitEvent(ws->work, ws->ev[2], 0), "wait");
+  const hipStream_t caller = s;
+  s = ws->work;
   auto timed = [&](const GemmArgs& g) -> hipError_t {
     hipEvent_t ea = nullptr, eb = nullptr;
     if (timing && hipEventCreate(&ea) == hipSuccess && hipEventCreate(&eb) == hipSuccess) (void)hipEventRecord(ea, s);
@@ -461,6 +546,8 @@ static hipError_t gj_eliminate(EpsWorkspace* ws, double* W, int64_t Ns, int64_t 
     EPS_CK(hipGetLastError(), "pivot rows");
     if (ahead) EPS_CK(hipStreamWaitEvent(s, ws->ev[1], 0), "wait");
   }
+  EPS_CK(hipEventRecord(ws->ev[3], s), "event");
+  EPS_CK(hipStreamWaitEvent(caller, ws->ev[3], 0), "wait");
   return hipSuccess;
 }
 
@@ -492,7 +579,7 @@ hipError_t eps_solve(EpsWorkspace* ws, size_t budget_left, int64_t n, const uint
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
   hipError_t e = gj_eliminate(ws, W, Np, ldw, Dinv, s, timing, &evs, err);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, W, (int)Np,
+    hipLaunchKernelGGL(k_eps_emit, dim3((unsigned)std::min<int64_t>(n, kEmitBlocks)), dim3(256), 0, s, W, (int)Np,
                        (int)n, R, ldr, X_out, ldx, minpos);
     e = hipGetLastError();
     if (e != hipSuccess) *err = "threshold";
