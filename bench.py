@@ -64,6 +64,8 @@ def main() -> int:
                     help="summarise a rocprofv3 --kernel-trace results database and exit")
     ap.add_argument("--eps-only", action="store_true",
                     help="run only the fp64 epsilon solve on the p = 4/N, seed 0 graph (for kernel traces) and exit")
+    ap.add_argument("--small-only", action="store_true",
+                    help="run only the plain FP32 closure at N = 512 (ER p = 2/N, seeds 0-2) and print its JSON")
     ap.add_argument("--peaks", action="store_true",
                     help="print the measured matrix-core rates and LDS data-path rates (dl_measure_peak) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -76,6 +78,9 @@ def main() -> int:
     ap.add_argument("--counter-summary", metavar="CSV",
                     help="per-launch averages of every counter in a rocprofv3 --pmc CSV for the step kernel, "
                          "per CU cycle, and exit")
+    ap.add_argument("--busy-summary", metavar="CSV",
+                    help="per kernel name: launches, duration, clock and matrix-core busy fraction from a "
+                         "rocprofv3 --pmc CSV holding SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE, and exit")
     ap.add_argument("--kernel", metavar="SUBSTRING",
                     help="with --counter-summary: summarise the kernels whose name contains SUBSTRING "
                          "(the most launched one) instead of the int8 step kernel")
@@ -91,6 +96,14 @@ def main() -> int:
 
         torch.cuda.set_device(0)
         print(json.dumps(run_programs(dl, dl.Context(0), torch)))
+        return 0
+    if args.small_only:
+        import torch
+
+        import paper_1608_00139_amd as dl
+
+        torch.cuda.set_device(0)
+        print(json.dumps(run_small_plain(dl, dl.Context(0), torch)))
         return 0
     if args.serving_only:
         import torch
@@ -108,6 +121,8 @@ def main() -> int:
         return mfma_summary(args.mfma_summary)
     if args.counter_summary:
         return counter_summary(args.counter_summary, args.kernel)
+    if args.busy_summary:
+        return busy_summary(args.busy_summary)
     if args.copy_calibration:
         return copy_calibration()
     if args.peaks:
@@ -322,22 +337,9 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
                          if tms > 0 else None})
     res["eps_solve_fp64"] = eps_rows
 
-    # plain FP32 iteration at N = 512, ER p = 2/N (time-to-fixpoint; launch bound)
+    # plain FP32 iteration at N = 512, ER p = 2/N (time-to-fixpoint; latency bound)
+    res["tc_plain_fp32_n512"] = run_small_plain(dl, ctx, torch)
     import dlgen
-
-    small = []
-    for seed in SEEDS:
-        a = torch.from_numpy(dlgen.to_dense(512, dlgen.er_edges(512, 2.0 / 512, seed))).cuda()
-        o = torch.empty_like(a)
-        dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
-        ts = []
-        for _ in range(5):
-            (_, it), t = timed(lambda: dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx))
-            ts.append(t)
-        t = statistics.median(ts)
-        small.append({"n": 512, "seed": seed, "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 3),
-                      "eff_tflops": round(2.0 * 512 ** 3 * (it - 1) / t / 1e12, 2)})
-    res["tc_plain_fp32_n512"] = small
 
     # power-law digraph, N = 32768 (1 GiB int8 operands), repeated squaring
     n = 32768
@@ -394,6 +396,31 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
     res["programs"] = run_programs(dl, ctx, torch)
     res["paper_workloads"] = run_paper_workloads(dl, ctx, torch)
     return res
+
+
+def run_small_plain(dl, ctx, torch, n: int = 512, runs: int = 20):
+    """The plain FP32 closure at N = 512 on ER p = 2/N, seeds 0-2: median
+    time-to-fixpoint of `runs` dl_tc calls each (the one-launch whole-fixpoint
+    kernel at this size), per iteration and effective TFLOP/s."""
+    import dlgen
+
+    small = []
+    for seed in SEEDS:
+        a = torch.from_numpy(dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, seed))).cuda()
+        o = torch.empty_like(a)
+        dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
+        ts = []
+        for _ in range(runs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, it = dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = statistics.median(ts)
+        small.append({"n": n, "seed": seed, "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 3),
+                      "us_per_iteration": round(t * 1e6 / it, 2),
+                      "eff_tflops": round(2.0 * n ** 3 * (it - 1) / t / 1e12, 2)})
+    return small
 
 
 def run_paper_workloads(dl, ctx, torch):
@@ -894,6 +921,36 @@ def counter_summary(csv_path: str, kernel: str | None = None) -> int:
     print(f"# {'counter':<34} {'per_launch':>16} {'per_CU_cycle':>13}")
     for k in keys:
         print(f"  {k:<34} {avg[k]:16.0f} {avg[k] / (cyc * cus):13.4f}")
+    return 0
+
+
+def busy_summary(csv_path: str) -> int:
+    """Per kernel name of a rocprofv3 --pmc CSV: launches, average duration,
+    clock (GRBM_GUI_ACTIVE / XCDs per ns) and the fraction of SIMD cycles the
+    matrix cores were busy (SQ_VALU_MFMA_BUSY_CYCLES / (cycles x SIMDs))."""
+    import csv
+    import os
+
+    xcds, simds = 8, 1024
+    info = os.path.join(os.path.dirname(csv_path), "k_agent_info.csv")
+    if os.path.exists(info):
+        for r in csv.DictReader(open(info)):
+            if r.get("Agent_Type") == "GPU":
+                xcds, simds = int(r["Num_Xcc"]), int(r["Simd_Count"])
+    disp = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = disp.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
+                                               "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    by = {}
+    for d in disp.values():
+        by.setdefault(d["name"], []).append(d)
+    print(f"# {'launches':>8} {'avg_us':>10} {'clock_ghz':>9} {'mfma_busy':>9}  kernel")
+    for name, ds in by.items():
+        ns = sum(d["ns"] for d in ds) / len(ds)
+        cyc = sum(d["GRBM_GUI_ACTIVE"] for d in ds) / len(ds) / xcds
+        busy = sum(d["SQ_VALU_MFMA_BUSY_CYCLES"] for d in ds) / len(ds) / (cyc * simds)
+        print(f"  {len(ds):8d} {ns / 1e3:10.1f} {cyc / ns:9.3f} {busy:9.3f}  {name.split('(')[0].replace('void ', '')}")
     return 0
 
 
