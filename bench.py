@@ -401,25 +401,33 @@ def run_extras(dl, ctx, graphs, outs, np, torch):
 def run_small_plain(dl, ctx, torch, n: int = 512, runs: int = 20):
     """The plain FP32 closure at N = 512 on ER p = 2/N, seeds 0-2: median
     time-to-fixpoint of `runs` dl_tc calls each (the one-launch whole-fixpoint
-    kernel at this size), per iteration and effective TFLOP/s."""
+    kernel at this size), per iteration and effective TFLOP/s, as the caller
+    sees it (host clock around the call and a device synchronisation) and on
+    the device (events recorded on the stream around the call)."""
     import dlgen
 
     small = []
+    stream = torch.cuda.current_stream()
     for seed in SEEDS:
         a = torch.from_numpy(dlgen.to_dense(n, dlgen.er_edges(n, 2.0 / n, seed))).cuda()
         o = torch.empty_like(a)
         dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
-        ts = []
+        ts, dts = [], []
         for _ in range(runs):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, it = dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx)
+            e0.record(stream)
+            _, it = dl.dl_tc(a, method=dl.DL_TC_PLAIN, prec=dl.DL_F32, out=o, ctx=ctx, stream=stream)
+            e1.record(stream)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
-        t = statistics.median(ts)
+            dts.append(e0.elapsed_time(e1) * 1e-3)
+        t, dt = statistics.median(ts), statistics.median(dts)
         small.append({"n": n, "seed": seed, "iters": it, "time_to_fixpoint_ms": round(t * 1e3, 3),
                       "us_per_iteration": round(t * 1e6 / it, 2),
-                      "eff_tflops": round(2.0 * n ** 3 * (it - 1) / t / 1e12, 2)})
+                      "eff_tflops": round(2.0 * n ** 3 * (it - 1) / t / 1e12, 2),
+                      "device_ms": round(dt * 1e3, 3), "device_us_per_iteration": round(dt * 1e6 / it, 2)})
     return small
 
 

@@ -858,25 +858,53 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
   unsigned* rowstep = p.rowstep + (int64_t)ti * stride;
   uint8_t* et = smem + 64 * ldb + kSmallPart;
 
-  // Y = rows col0 .. col0 + 31 of A + I (LDS rows 32..63), built once
+  // One pass over rows col0 .. col0 + 31 of A builds both Y = those rows
+  // of A + I (LDS rows 32..63, kept for the whole series) and S^(1) = A^T
+  // (tile element (r, c) is A[col0 + c][row0 + r], i.e. the columns
+  // row0 .. row0 + 31 of the same rows, before the identity is added).
+  // Each item is the EPC bytes of A behind one operand chunk (consecutive
+  // threads write consecutive chunks), read with one load where it is
+  // aligned and inside the n valid columns, bytewise elsewhere.
   for (int q = tid; q < 32 * kc; q += kSmallThreads) {
     const int r = q / kc, c = q % kc;
-    const int j = col0 + r, e0 = c * EPC;
-    unsigned bits = 0u;
+    const int j = col0 + r, k0 = c * EPC;
+    unsigned raw = 0u;  // bit e: A[j][k0 + e] != 0
     if (j < p.n) {
-      const uint8_t* arow = p.A + (int64_t)j * p.lda;
-      for (int e = 0; e < EPC; ++e) {
-        const int k = e0 + e;
-        if (k < p.n && (arow[k] != 0 || k == j)) bits |= 1u << e;
+      const uint8_t* src = p.A + (int64_t)j * p.lda + k0;
+      if (k0 + EPC <= p.n && ((uintptr_t)src & (EPC >= 16 ? 15 : EPC - 1)) == 0) {
+        unsigned w[EPC / 4];
+        if constexpr (EPC >= 16) {
+#pragma unroll
+          for (int h = 0; h < EPC / 16; ++h) {
+            const u32x4 v = *(const u32x4*)(src + 16 * h);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) w[4 * h + x] = v[x];
+          }
+        } else if constexpr (EPC == 8) {
+          const uint2 v = *(const uint2*)src;
+          w[0] = v.x;
+          w[1] = v.y;
+        } else {
+          w[0] = *(const unsigned*)src;
+        }
+#pragma unroll
+        for (int x = 0; x < EPC / 4; ++x)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if ((w[x] >> (8 * b)) & 0xffu) raw |= 1u << (4 * x + b);
+      } else {
+        for (int e = 0; e < EPC; ++e)
+          if (k0 + e < p.n && src[e] != 0) raw |= 1u << e;
       }
     }
-    *(u32x4*)(smem + (int64_t)(32 + r) * ldb + 16 * (c ^ ((32 + r) & mask))) = chunk_of_bits<Op::kPrec>(bits);
-  }
-  // S^(1) = A^T: tile element (r, c) is A[col0 + c][row0 + r]
-  for (int q = tid; q < 1024; q += kSmallThreads) {
-    const int r = q & 31, c = q >> 5;
-    const int gi = row0 + r, gj = col0 + c;
-    et[r * kSmallEst + c] = (gi < p.n && gj < p.n && p.A[(int64_t)gj * p.lda + gi] != 0) ? 1 : 0;
+    // S^(1): the part of this item inside columns row0 .. row0 + 31
+    if (k0 + EPC > row0 && k0 < row0 + 32)
+      for (int e = 0; e < EPC; ++e) {
+        const int k = k0 + e;
+        if (k >= row0 && k < row0 + 32) et[(k - row0) * kSmallEst + r] = (raw >> e) & 1u;
+      }
+    if (j >= k0 && j < k0 + EPC && j < p.n) raw |= 1u << (j - k0);  // the identity of A + I
+    *(u32x4*)(smem + (int64_t)(32 + r) * ldb + 16 * (c ^ ((32 + r) & mask))) = chunk_of_bits<Op::kPrec>(raw);
   }
   __syncthreads();
 
@@ -889,11 +917,13 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
       store_bool16_agent<Op::kPrec>(buffer_of(p.S[t & 1], (unsigned)(ldb * p.Np)),
                                     (int)(((int64_t)(row0 + r) * p.Np + col0 + 16 * cs) * NIB / 2), v);
       const int cnt = wave_sum(popc16(v));
-      if (lane == 0 && cnt) atomicAdd(p.ones_row + (int64_t)ti * stride + t, (unsigned long long)cnt);
       const unsigned changed = cnt != prev_cnt ? 1u : 0u;
       prev_cnt = cnt;
       wait_stores();
       if (lane == 0) atomicAdd(rowstep + t, 1u + (changed << 8));
+      // the model size after the arrival, so the arrival does not wait for
+      // it; the wait before the finishing count below covers it
+      if (lane == 0 && cnt) atomicAdd(p.ones_row + (int64_t)ti * stride + t, (unsigned long long)cnt);
     }
     ++t;
     // decide whether step t runs: the row's arrivals at step t - 1
@@ -926,12 +956,15 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
     small_tile_product<Op>(smem, ldb, kc, mask, lane, wave, et);
     __syncthreads();
   }
-  // the last iterate computed, S^(t-1), back to R = S^T, cropped
+  // the last iterate computed, S^(t-1), back to R = S^T, cropped; every
+  // store of the tile completes before the workgroup counts itself finished
   for (int q = tid; q < 1024; q += kSmallThreads) {
     const int r = q & 31, c = q >> 5;
     const int gi = row0 + r, gj = col0 + c;
     if (gi < p.n && gj < p.n) p.R[(int64_t)gj * p.ldr + gi] = et[r * kSmallEst + c];
   }
+  wait_stores();
+  __syncthreads();
   // the last workgroup to finish sums the model sizes of the whole matrix
   if (tid == 0) {
     if (tj == 0) st_agent(p.krow + ti, (unsigned)(t - 1));
@@ -940,22 +973,21 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
   }
   __syncthreads();
   if (!s_go) return;
+  // every row block's last step into LDS (one load each, all in flight
+  // together), then per step s the sum over row blocks of ones_i[min(s, k_i)]
+  // (independent loads)
+  __shared__ int s_k[kSmallMaxLdb / 32];
+  if (tid < p.tiles) s_k[tid] = (int)ld_agent(p.krow + tid);
+  __syncthreads();
   int K = 0;
-  for (int i = 0; i < p.tiles; ++i) {
-    const int k = (int)ld_agent(p.krow + i);
-    K = k > K ? k : K;
-  }
-  for (int s = tid; s <= K; s += kSmallThreads) {
+  for (int i = 0; i < p.tiles; ++i) K = s_k[i] > K ? s_k[i] : K;
+  // K <= Np + 2 < kSmallThreads: thread s sums step s
+  if (tid <= K) {
     unsigned long long sum = 0ull;
-    for (int i = 0; i < p.tiles; ++i) {
-      const int k = (int)ld_agent(p.krow + i);
-      sum += s == 0 ? 0ull : ld_agent64(p.ones_row + (int64_t)i * stride + (s < k ? s : k));
-    }
-    p.ring_out[s] = sum;
-  }
-  if (tid == 0) {
-    p.status_out[0] = (unsigned)K;
-    p.status_out[1] = 0u;
+    if (tid > 0)
+      for (int i = 0; i < p.tiles; ++i)
+        sum += ld_agent64(p.ones_row + (int64_t)i * stride + (tid < s_k[i] ? tid : s_k[i]));
+    p.ring_out[tid] = sum;
   }
   __syncthreads();
   // every other workgroup is done with the counters: zero them
@@ -966,6 +998,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
   }
   if (tid < p.tiles) st_agent(p.krow + tid, 0u);
   if (tid == 0) st_agent(p.finished, 0u);
+  // the status word last, once every store above has completed: a caller may
+  // take it as the end of the launch
+  wait_stores();
+  __syncthreads();
+  if (tid == 0) {
+    p.status_out[1] = 0u;
+    p.status_out[0] = (unsigned)K;
+  }
 }
 
 __global__ void k_fix_small_clear(FixSmallParams p) {
