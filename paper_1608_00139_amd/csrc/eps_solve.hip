@@ -42,10 +42,11 @@ constexpr int NB = 128;  // block size of the elimination
 // ----------------------------------------------------------------- fp64 MFMA GEMM
 // D = A * B (cmode 0), D = C - A * B (cmode 1) or D = C + A * B (cmode 2);
 // A: M x K, B: K x N, C/D: M x N, row-major.  128 x 128 output tiles, 4 waves
-// of 64 x 64, K slices of 16 double-buffered in LDS.  With cmode 1 or 2 the
-// accumulators start from C (for cmode 1, A is negated on its way into LDS,
-// which is exact), so C is read once at the start of the tile and D written
-// once at the end.  Row tiles at or after
+// of 64 x 64 (v_mfma_f64_16x16x4f64), K slices of 16 fetched straight into a
+// 4-slot LDS ring (global_load_lds, three slices in flight).  With cmode 1
+// or 2 the accumulators start from C (negated for cmode 1, and the result
+// negated back on the way out: both exact), so C is read once at the start of
+// the tile and D written once at the end.  Row tiles at or after
 // skip_tile are shifted down by skip_count, which leaves out the row tiles
 // skip_tile .. skip_tile + skip_count - 1 (the pivot rows of an elimination
 // step; skip_tile -1 = none).  D may alias C
@@ -70,129 +71,147 @@ __device__ inline void f64_acc_coord(int lane, int item, int& r, int& c) {
   c = lane & 15;
 }
 
-template <int BM, int BN, int BK, bool CINIT = true>
+// LDS of one slice: the A slice (128 rows x 16 doubles, 128-byte rows; the
+// 16-byte chunk c of row r at position c ^ ((r >> 1) & 7)) then the B slice
+// (16 k-rows x 128 doubles, 1 KB rows; chunk c of k-row k at c ^ 8 (k & 1)).
+// Either way the 32 lanes that one ds_read_b64 pass serves (two k values x
+// 16 rows or columns) hit 64 distinct banks.
+constexpr int kDgemmStages = 4;
+constexpr int kDgemmSliceBytes = 2 * 128 * 16 * 8;
+constexpr unsigned kDgemmLds = kDgemmStages * kDgemmSliceBytes;  // 128 KB: one update workgroup per CU
+
+// s_waitcnt with vmcnt = N and no wait on the other counters
+template <int N>
+__device__ inline void dgemm_wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
 __global__ void __launch_bounds__(256) k_dgemm(GemmArgs g) {
-  constexpr int WM = BM / 2, WN = BN / 2;   // 2 x 2 waves
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int PAD = 2;
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
-  const int tiles_m = g.M / BM;
+  const int tiles_m = g.M / 128;
   // column-major walk over tiles keeps one B column panel hot across rows
   int tm = blockIdx.x % tiles_m;
   const int tn = blockIdx.x / tiles_m;
   if (g.skip_tile >= 0 && tm >= g.skip_tile) tm += g.skip_count;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int m0 = tm * 128, n0 = tn * 128;
 
-  v4d acc[FM][FN];
-  if (CINIT && g.cmode) {
+  // Each wave issues 8 of a slice's 32 one-KB direct-to-LDS instructions:
+  // A instruction a = wave + 4 jj covers rows 8a .. 8a + 7 (lane l: row
+  // 8a + l / 8, LDS chunk l % 8), B instruction b = wave + 4 jj is k-row b
+  // (lane l: LDS chunk l).
+  const double* asrc[4];
+  const double* bsrc[4];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+  for (int jj = 0; jj < 4; ++jj) {
+    const int a = wave + 4 * jj;
+    const int row = 8 * a + (lane >> 3);
+    asrc[jj] = g.A + (int64_t)(m0 + row) * g.lda + 2 * ((lane & 7) ^ ((row >> 1) & 7));
+    bsrc[jj] = g.B + (int64_t)a * g.ldb + n0 + 2 * (lane ^ (8 * (a & 1)));
+  }
+  auto issue = [&](int kt) {
+    uint8_t* stage = lds + (kt % kDgemmStages) * kDgemmSliceBytes;
+    const int k0 = kt * 16;
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+    for (int jj = 0; jj < 4; ++jj)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(asrc[jj] + k0),
+                                       (__attribute__((address_space(3))) void*)(stage + (wave + 4 * jj) * 1024),
+                                       16, 0, 0);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(bsrc[jj] + (int64_t)k0 * g.ldb),
+                                       (__attribute__((address_space(3))) void*)(stage + 16384 + (wave + 4 * jj) * 1024),
+                                       16, 0, 0);
+  };
+
+  // fragment reads: lane (g4, r16) = (lane / 16, lane % 16) supplies
+  // A[row r16][k g4] and B[k g4][column r16] of each 16 x 16 x 4 product
+  const int g4 = lane >> 4, r16 = lane & 15;
+  auto frags = [&](const uint8_t* st, int kk, double* af, double* bf) {
+    const int k = kk + g4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + r16;
+      af[i] = *(const double*)(st + r * 128 + (((k >> 1) ^ ((r >> 1) & 7)) << 4) + ((k & 1) << 3));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = wn * 64 + j * 16 + r16;
+      bf[j] = *(const double*)(st + 16384 + k * 1024 + (((n >> 1) ^ (8 * (k & 1))) << 4) + ((n & 1) << 3));
+    }
+  };
+
+  const int nk = g.K / 16;
+#pragma unroll
+  for (int s0 = 0; s0 < kDgemmStages - 1; ++s0)
+    if (s0 < nk) issue(s0);
+
+  // the accumulators from C while the first slices are in flight
+  v4d acc[4][4];
+  const double csgn = g.cmode == 1 ? -1.0 : 1.0;
+  if (g.cmode) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           int r, c;
           f64_acc_coord(lane, v, r, c);
-          acc[i][j][v] = g.C[(int64_t)(m0 + wm * WM + i * 16 + r) * g.ldc + n0 + wn * WN + j * 16 + c];
+          acc[i][j][v] = csgn * g.C[(int64_t)(m0 + wm * 64 + i * 16 + r) * g.ldc + n0 + wn * 64 + j * 16 + c];
         }
   } else {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
   }
 
-  constexpr int ACH = BM * BK / 2;   // 16-byte chunks of the A tile
-  constexpr int BCH = BK * BN / 2;
-  constexpr int AL = ACH / 256, BL = BCH / 256;
-  static_assert(ACH % 256 == 0 && BCH % 256 == 0, "tile loads must divide evenly");
-  // with C in the accumulators, C - A B is computed as C + (-A) B
-  const double sgn = (CINIT && g.cmode == 1) ? -1.0 : 1.0;
-  double2 ra[AL], rb[BL];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < AL; ++i) {
-      const int q = tid + i * 256;
-      const int row = q / (BK / 2), kk = (q % (BK / 2)) * 2;
-      ra[i] = *(const double2*)(g.A + (int64_t)(m0 + row) * g.lda + k0 + kk);
-    }
-#pragma unroll
-    for (int i = 0; i < BL; ++i) {
-      const int q = tid + i * 256;
-      const int k = q / (BN / 2), nn = (q % (BN / 2)) * 2;
-      rb[i] = *(const double2*)(g.B + (int64_t)(k0 + k) * g.ldb + n0 + nn);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < AL; ++i) {
-      const int q = tid + i * 256;
-      const int row = q / (BK / 2), kk = (q % (BK / 2)) * 2;
-      As[buf][kk][row] = sgn * ra[i].x;
-      As[buf][kk + 1][row] = sgn * ra[i].y;
-    }
-#pragma unroll
-    for (int i = 0; i < BL; ++i) {
-      const int q = tid + i * 256;
-      const int k = q / (BN / 2), nn = (q % (BN / 2)) * 2;
-      *(double2*)&Bs[buf][k][nn] = rb[i];
-    }
-  };
-
-  const int g4 = lane >> 4, r16 = lane & 15;
-  const int nk = g.K / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+    // slice kt has landed once at most the later slices' instructions
+    // (8 per slice) are outstanding; the barrier extends that to every wave
+    // and retires every read of slot (kt - 1) % 4, refilled below
+    const int later = (kt + 2 < nk ? kt + 2 : nk - 1) - kt;
+    if (later >= 2) dgemm_wait_vmcnt<16>();
+    else if (later == 1) dgemm_wait_vmcnt<8>();
+    else dgemm_wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (kt + kDgemmStages - 1 < nk) issue(kt + kDgemmStages - 1);
+    const uint8_t* st = lds + (kt % kDgemmStages) * kDgemmSliceBytes;
+    double af[2][4], bf[2][4];
+    frags(st, 0, af[0], bf[0]);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double af[FM], bf[FN];
+    for (int q = 0; q < 4; ++q) {
+      if (q < 3) frags(st, 4 * (q + 1), af[(q + 1) & 1], bf[(q + 1) & 1]);
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[cur][kk + g4][wm * WM + i * 16 + r16];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[cur][kk + g4][wn * WN + j * 16 + r16];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[q & 1][i], bf[q & 1][j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
   }
 
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int r, c;
         f64_acc_coord(lane, v, r, c);
-        const int64_t row = m0 + wm * WM + i * 16 + r, col = n0 + wn * WN + j * 16 + c;
-        double x = acc[i][j][v];
-        if (!CINIT && g.cmode) x = g.C[row * g.ldc + col] + (g.cmode == 1 ? -x : x);
-        g.D[row * g.ldd + col] = x;
+        const int64_t row = m0 + wm * 64 + i * 16 + r, col = n0 + wn * 64 + j * 16 + c;
+        g.D[row * g.ldd + col] = csgn * acc[i][j][v];
       }
 }
 
-// Unused LDS requested with every launch so that one workgroup, not two, fits
-// a compute unit: the panel inverse that runs beside the trailing update on
-// the look-ahead stream (k_block_inverse, 1024 threads) then finds the
-// registers and LDS it needs next to a resident update workgroup instead of
-// waiting for a compute unit to drain.
-constexpr unsigned kDgemmLdsPad = 16384;
 static hipError_t dgemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.M % 128 || g.N % 128 || g.K % 16) return hipErrorInvalidValue;
   const int grid = (g.M / 128) * (g.N / 128);
-  hipLaunchKernelGGL((k_dgemm<128, 128, 16>), dim3(grid), dim3(256), kDgemmLdsPad, s, g);
+  hipLaunchKernelGGL(k_dgemm, dim3(grid), dim3(256), kDgemmLds, s, g);
   return hipGetLastError();
 }
 
@@ -368,8 +387,7 @@ __global__ void k_set_word(unsigned long long* p, unsigned long long v) { *p = v
 
 // ----------------------------------------------------------------- driver
 hipError_t eps_kernels_init() {
-  return hipFuncSetAttribute((const void*)k_dgemm<128, 128, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)kDgemmLdsPad);
+  return hipFuncSetAttribute((const void*)k_dgemm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDgemmLds);
 }
 
 int64_t eps_padded_size(int64_t n) { return n <= 0 ? 0 : ((n + NB - 1) / NB) * NB; }
