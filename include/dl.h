@@ -336,6 +336,19 @@ int dl_batch_submit(dl_batch* batch, int kind, int64_t n, const uint8_t* A, int6
 int dl_batch_submit_edges(dl_batch* batch, int kind, int64_t n, const int32_t* edges, int64_t m, int64_t tag,
                           int32_t* slot, void* stream);
 
+/* Many dl_batch_submit_edges calls in one: request i has kind kinds[i], n
+ * constants ns[i], the device edge list edges[i] of ms[i] pairs and tag
+ * tags[i] (host arrays of `count` entries; edges[i] may be NULL when
+ * ms[i] = 0).  Requests are admitted in order until one does not fit (in
+ * slots or pool memory): *admitted (host) receives how many were, slots[i]
+ * (host int32[count]) the slot of request i < *admitted.  A request that
+ * does not fit is not an error (DL_OK, *admitted < count); an invalid
+ * request is DL_EINVAL, with *admitted counting the requests before it.
+ * The edge lists follow the rules of dl_batch_submit_edges. */
+int dl_batch_submit_edges_n(dl_batch* batch, int32_t count, const int32_t* kinds, const int64_t* ns,
+                            const int32_t* const* edges, const int64_t* ms, const int64_t* tags, int32_t* slots,
+                            int32_t* admitted, void* stream);
+
 /* One round (blocks until its model sizes are read back).  *active receives
  * the number of requests still running, *finished the number that finished
  * in this round.  With one round of look-ahead, the call enqueues the next
@@ -362,6 +375,13 @@ int dl_batch_poll(dl_batch* batch, int64_t* tags, int32_t* slots, int32_t* iters
  * NULL), and free the slot and its pool memory.  A request may be fetched
  * before it is polled; dl_batch_poll then no longer reports it. */
 int dl_batch_fetch(dl_batch* batch, int32_t slot, uint8_t* R, int64_t ldr, int64_t* ones, void* stream);
+
+/* dl_batch_fetch without the models for `count` finished requests: ones[i]
+ * (host int64[count], may be NULL) receives the number of true entries of
+ * slots[i]'s model, and every slot and its pool memory is freed.  A slot
+ * that is not a finished request is DL_EINVAL; the slots before it have
+ * been freed. */
+int dl_batch_release_n(dl_batch* batch, int32_t count, const int32_t* slots, int64_t* ones);
 
 /* Tile autotuner of the grouped step (the output tile size of each request's
  * products).  For each size n of `sizes` (host int64 array of k ascending

@@ -90,6 +90,9 @@ def load() -> ctypes.CDLL:
         "dl_batch_set_tiles": ([vp, pi64, pi32, i32], ctypes.c_int),
         "dl_batch_poll": ([vp, pi64, pi32, pi32, i32, pi32], ctypes.c_int),
         "dl_batch_fetch": ([vp, i32, vp, i64, pi64, vp], ctypes.c_int),
+        "dl_batch_submit_edges_n": ([vp, i32, pi32, pi64, ctypes.POINTER(vp), pi64, pi64, pi32, pi32, vp],
+                                    ctypes.c_int),
+        "dl_batch_release_n": ([vp, i32, pi32, pi64], ctypes.c_int),
         "dl_batch_info": ([vp, pi32, pi32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "dl_solve_linear": ([vp, i64, vp, i64, vp, i64, dbl, vp, i64, vp, i64, vp], ctypes.c_int),
         "dl_solve_two_sided": ([vp, i64, vp, i64, vp, i64, vp, i64, dbl, vp, i64, vp, i64, pi32, vp],
@@ -562,6 +565,10 @@ class Batch:
         self._slots = (ctypes.c_int32 * self._cap)()
         self._iters = (ctypes.c_int32 * self._cap)()
         self._pending_edges: list = []
+        # edge lists admitted in bulk: kept referenced until the round that
+        # scatters them has completed (two dl_batch_step calls later at most)
+        self._bulk_edges: list = []
+        self._bulk_held: list = [[], []]
 
     def close(self) -> None:
         if self._h:
@@ -610,6 +617,46 @@ class Batch:
             edges.record_stream(self.stream if self.stream is not None else torch.cuda.current_stream(edges.device))
         return int(slot.value)
 
+    def dl_batch_submit_edges_n(self, kinds, ns, edges: list, tags) -> list[int]:
+        """Admit requests given as device int32 [m, 2] edge lists, in order,
+        until one does not fit; returns the slots of those admitted (a prefix
+        of the requests)."""
+        k = len(edges)
+        if not (len(kinds) == len(ns) == len(tags) == k):
+            raise ValueError("one kind, size and tag per edge list")
+        if k == 0:
+            return []
+        ptrs = (ctypes.c_void_p * k)()
+        ms = (ctypes.c_int64 * k)()
+        for i, e in enumerate(edges):
+            if not isinstance(e, torch.Tensor) or not e.is_cuda or e.dtype != torch.int32:
+                raise TypeError("edges must be device int32 tensors")
+            if e.numel() and (e.dim() != 2 or e.shape[1] != 2 or not e.is_contiguous()):
+                raise ValueError("edges must be contiguous [m, 2] tensors")
+            ms[i] = e.shape[0] if e.numel() else 0
+            ptrs[i] = e.data_ptr() if ms[i] else None
+        kk = (ctypes.c_int32 * k)(*[int(x) for x in kinds])
+        nn = (ctypes.c_int64 * k)(*[int(x) for x in ns])
+        tt = (ctypes.c_int64 * k)(*[int(x) for x in tags])
+        slots = (ctypes.c_int32 * k)()
+        got = ctypes.c_int32()
+        rc = load().dl_batch_submit_edges_n(self._h, k, kk, nn, ptrs, ms, tt, slots, ctypes.byref(got),
+                                            _stream_ptr(self.stream))
+        self._bulk_edges.extend(edges[:got.value])
+        _check(rc)
+        return [int(slots[i]) for i in range(got.value)]
+
+    def dl_batch_release_n(self, slots) -> list[int]:
+        """Free finished requests without copying their models; returns their
+        numbers of true entries."""
+        k = len(slots)
+        if k == 0:
+            return []
+        ss = (ctypes.c_int32 * k)(*[int(x) for x in slots])
+        ones = (ctypes.c_int64 * k)()
+        _check(load().dl_batch_release_n(self._h, k, ss, ones))
+        return [int(ones[i]) for i in range(k)]
+
     def tune(self, sizes: list | None = None) -> list[dict]:
         """Time the grouped step at each tile size for each request size and
         keep the fastest per size (dl_batch_tune); returns one entry per
@@ -637,6 +684,10 @@ class Batch:
             _check(load().dl_batch_step(self._h, ctypes.byref(active), ctypes.byref(fin), _stream_ptr(self.stream)))
         finally:
             self._pending_edges.clear()
+            # the round issued now scatters the bulk-admitted edges; it has
+            # completed once the next call returns
+            self._bulk_held = [self._bulk_held[1], self._bulk_edges]
+            self._bulk_edges = []
         return int(active.value), int(fin.value)
 
     def dl_batch_poll(self) -> list[tuple[int, int, int]]:

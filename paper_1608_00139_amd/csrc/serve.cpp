@@ -409,6 +409,22 @@ int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges
                });
 }
 
+int dl_batch_submit_edges_n(dl_batch* b, int32_t count, const int32_t* kinds, const int64_t* ns,
+                            const int32_t* const* edges, const int64_t* ms, const int64_t* tags, int32_t* slots,
+                            int32_t* admitted, void* stream) {
+  if (!admitted) return bfail(DL_EINVAL, "NULL admitted");
+  *admitted = 0;
+  if (count < 0 || (count > 0 && (!kinds || !ns || !edges || !ms || !tags || !slots)))
+    return bfail(DL_EINVAL, "bad request arrays");
+  for (int32_t i = 0; i < count; ++i) {
+    const int rc = dl_batch_submit_edges(b, kinds[i], ns[i], edges[i], ms[i], tags[i], slots + i, stream);
+    if (rc == DL_EAGAIN) return DL_OK;  // the first request that does not fit ends the call
+    if (rc) return rc;
+    *admitted = i + 1;
+  }
+  return DL_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -632,6 +648,15 @@ int dl_batch_fetch(dl_batch* b, int32_t slot, uint8_t* R, int64_t ldr, int64_t* 
   else
     pool_free(b, r.off, r.bytes);
   r = Req();
+  return DL_OK;
+}
+
+int dl_batch_release_n(dl_batch* b, int32_t count, const int32_t* slots, int64_t* ones) {
+  if (count < 0 || (count > 0 && !slots)) return bfail(DL_EINVAL, "bad slot array");
+  for (int32_t i = 0; i < count; ++i) {
+    const int rc = dl_batch_fetch(b, slots[i], nullptr, 0, ones ? ones + i : nullptr, nullptr);
+    if (rc) return rc;
+  }
   return DL_OK;
 }
 

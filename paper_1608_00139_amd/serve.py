@@ -57,19 +57,25 @@ class StreamStats:
 
 
 def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, keep_results: bool | set = False,
-               batch: Batch | None = None, lookahead: int = 0, tiles: list | None = None) -> tuple[StreamStats, dict]:
+               batch: Batch | None = None, lookahead: int = 0, tiles: list | None = None,
+               admit_chunk: int = 64) -> tuple[StreamStats, dict]:
     """Serve `requests` (objects with rid, kind 'tc'/'sg', n, arrival seconds).
 
     make_input(req) returns the request's relation as a uint8 device tensor
     (dense n x n) or as a device int32 [m, 2] edge list.  lookahead = 1 lets
     each round's host work overlap the next round on the device.  tiles is a
-    tile table (Batch.tune's result) for a batch this call creates.
+    tile table (Batch.tune's result) for a batch this call creates.  At most
+    admit_chunk requests are admitted between two rounds, so that a burst of
+    arrivals is admitted while the device runs the rounds of the requests
+    admitted before it (edge-list requests are admitted with one library
+    call per group).
     Returns the statistics and, if keep_results, {rid: (model tensor, iters)}
     (keep_results may be a set of rids to keep only those models).
     """
     b = batch or Batch(pool_bytes, max_active, lookahead=lookahead)
     if tiles is not None and batch is None:
         b.set_tiles(tiles)
+    bulk = hasattr(b, "dl_batch_submit_edges_n") and hasattr(b, "dl_batch_release_n")
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting: deque = deque()
     inflight = {}  # slot -> (req, admitted time)
@@ -77,33 +83,50 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
     stats = StreamStats()
     t0 = time.perf_counter()
     now = 0.0
+
+    def kind_of(req):
+        return Batch.TC if req.kind == "tc" else Batch.SG
+
+    def submit_group(group, rels):
+        """Slots of the admitted prefix of `group`."""
+        if bulk and all(r.dtype == torch.int32 for r in rels):
+            return b.dl_batch_submit_edges_n([kind_of(q) for q in group], [q.n for q in group], rels,
+                                             [q.rid for q in group])
+        slots = []
+        for q, rel in zip(group, rels):
+            if rel.dtype == torch.int32:
+                slot = b.dl_batch_submit_edges(kind_of(q), q.n, rel, q.rid)
+            else:
+                slot = b.dl_batch_submit(kind_of(q), rel, q.rid)
+            if slot is None:
+                break
+            slots.append(slot)
+        return slots
+
     while pending or waiting or inflight:
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             waiting.append(pending.popleft())
-        while waiting:
-            req = waiting[0]
-            kind = Batch.TC if req.kind == "tc" else Batch.SG
-            rel = make_input(req)
-
-            def submit():
-                if rel.dtype == torch.int32:
-                    return b.dl_batch_submit_edges(kind, req.n, rel, req.rid)
-                return b.dl_batch_submit(kind, rel, req.rid)
-
-            slot = submit()
-            if slot is None and not inflight:
+        budget = admit_chunk
+        while waiting and budget > 0:
+            group = [waiting[i] for i in range(min(budget, len(waiting)))]
+            rels = [make_input(q) for q in group]
+            slots = submit_group(group, rels)
+            if not slots and not inflight:
                 # with look-ahead, memory of fetched requests returns to the
                 # pool once the round in flight completes
                 b.dl_batch_step()
-                slot = submit()
-            if slot is None:
-                if not inflight:
-                    raise RuntimeError(f"request {req.rid} (n={req.n}) does not fit an empty pool")
+                slots = submit_group(group, rels)
+            t_adm = time.perf_counter() - t0
+            for q, slot in zip(group, slots):
+                waiting.popleft()
+                inflight[slot] = (q, t_adm)
+            budget -= len(slots)
+            if len(slots) < len(group):
+                if not slots and not inflight:
+                    raise RuntimeError(f"request {group[0].rid} (n={group[0].n}) does not fit an empty pool")
                 stats.eagain += 1
                 break
-            waiting.popleft()
-            inflight[slot] = (req, time.perf_counter() - t0)
         if not inflight:
             if pending:  # idle until the next arrival
                 while time.perf_counter() - t0 < pending[0].arrival:
@@ -112,16 +135,28 @@ def run_stream(requests, make_input, pool_bytes: int, max_active: int = 256, kee
         stats.max_active = max(stats.max_active, len(inflight))
         b.dl_batch_step()
         stats.rounds += 1
-        for tag, slot, iters in b.dl_batch_poll():
+        done = b.dl_batch_poll()
+        if not done:
+            continue
+        fin = time.perf_counter() - t0
+        keep_of = {}
+        for tag, slot, iters in done:
+            req = inflight[slot][0]
+            keep_of[slot] = (req.rid in keep_results) if isinstance(keep_results, set) else bool(keep_results)
+        drop = [slot for _, slot, _ in done if not keep_of[slot]]
+        ones_of = dict(zip(drop, b.dl_batch_release_n(drop))) if bulk else {}
+        for tag, slot, iters in done:
             req, adm = inflight.pop(slot)
-            keep = (req.rid in keep_results) if isinstance(keep_results, set) else bool(keep_results)
-            out = torch.empty((req.n, req.n), dtype=torch.uint8, device="cuda") if keep else None
-            ones = b.dl_batch_fetch(slot, out)
-            fin = time.perf_counter() - t0
-            stats.completions.append(Completion(tag, 0 if req.kind == "tc" else 1, req.n, iters, ones,
-                                                req.arrival, adm, fin))
-            if keep:
+            if keep_of[slot]:
+                out = torch.empty((req.n, req.n), dtype=torch.uint8, device="cuda")
+                ones = b.dl_batch_fetch(slot, out)
                 results[req.rid] = (out, iters)
+                t_fin = time.perf_counter() - t0
+            else:
+                ones = ones_of[slot] if bulk else b.dl_batch_fetch(slot, None)
+                t_fin = fin
+            stats.completions.append(Completion(tag, 0 if req.kind == "tc" else 1, req.n, iters, ones,
+                                                req.arrival, adm, t_fin))
     if torch.cuda.is_available():
         torch.cuda.synchronize()
     stats.wall = time.perf_counter() - t0

@@ -426,3 +426,53 @@ def test_config_serving_stream_10000(dl):
         assert np.array_equal(host(got), ref), (rid, r.kind, r.n)
         assert iters == it_ref, (rid, r.kind, r.n)
         assert by_tag[rid].ones == int(ref.sum()), (rid, r.kind, r.n)
+
+
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_bulk_admission_and_release(dl, lookahead):
+    """dl_batch_submit_edges_n admits the prefix of requests that fits (here
+    the slots run out), an invalid request stops it with an error after the
+    valid ones before it, and dl_batch_release_n reports the same model sizes
+    as dl_batch_fetch; every model equals the oracle's."""
+    import torch
+
+    reqs = dlgen.serving_stream(9, seed=21, rate=0.0, n_lo=64, n_hi=400)
+    edges = [torch.from_numpy(dlgen.request_edges(r).astype(np.int32)).cuda() for r in reqs]
+    kinds = [dl.Batch.TC if r.kind == "tc" else dl.Batch.SG for r in reqs]
+    b = dl.Batch(pool_bytes=1 << 28, max_active=6, lookahead=lookahead)
+    announce("bulk admission", lookahead)
+    slots = b.dl_batch_submit_edges_n(kinds, [r.n for r in reqs], edges, [r.rid for r in reqs])
+    assert len(slots) == 6 and len(set(slots)) == 6  # six slots
+    with pytest.raises(dl.DLError):
+        bad = torch.zeros((1, 2), dtype=torch.int32, device="cuda")
+        b.dl_batch_submit_edges_n([dl.Batch.TC], [0], [bad], [99])  # n = 0 is invalid
+    fetched, released = {}, {}
+    while len(fetched) + len(released) < 6:
+        b.dl_batch_step()
+        done = b.dl_batch_poll()
+        keep = [(tag, sl, it) for tag, sl, it in done if tag % 2 == 0]
+        drop = [(tag, sl, it) for tag, sl, it in done if tag % 2 == 1]
+        for tag, sl, it in keep:
+            r = reqs[tag]
+            out = torch.empty((r.n, r.n), dtype=torch.uint8, device="cuda")
+            b.dl_batch_fetch(sl, out)
+            fetched[tag] = (host(out), it)
+        for (tag, sl, it), ones in zip(drop, b.dl_batch_release_n([sl for _, sl, _ in drop])):
+            released[tag] = (ones, it)
+    for tag, (model, it) in fetched.items():
+        assert np.array_equal(model, _oracle(reqs[tag])), tag
+    for tag, (ones, it) in released.items():
+        assert ones == int(_oracle(reqs[tag]).sum()), tag
+    # the remaining three fit now
+    slots = b.dl_batch_submit_edges_n(kinds[6:], [r.n for r in reqs[6:]], edges[6:], [r.rid for r in reqs[6:]])
+    assert len(slots) == 3
+    left = set(range(6, 9))
+    while left:
+        b.dl_batch_step()
+        for tag, sl, it in b.dl_batch_poll():
+            r = reqs[tag]
+            out = torch.empty((r.n, r.n), dtype=torch.uint8, device="cuda")
+            b.dl_batch_fetch(sl, out)
+            assert np.array_equal(host(out), _oracle(r)), tag
+            left.discard(tag)
+    b.close()

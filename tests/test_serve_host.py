@@ -68,13 +68,41 @@ class StandInBatch:
         return 11
 
 
+class StandInBulkBatch(StandInBatch):
+    """The same, with the bulk admission and release calls (admission stops
+    at the first request that does not fit)."""
+
+    def __init__(self, slots: int, pool_bytes: int):
+        super().__init__(slots, pool_bytes)
+        self.bulk_calls = 0
+
+    def dl_batch_submit_edges_n(self, kinds, ns, edges, tags):
+        self.bulk_calls += 1
+        assert len(kinds) == len(ns) == len(edges) == len(tags)
+        out = []
+        for n, e, tag in zip(ns, edges, tags):
+            assert e.dtype == torch.int32 and e.dim() == 2 and e.shape[1] == 2
+            slot = self._admit(tag, n)
+            if slot is None:
+                break
+            out.append(slot)
+        return out
+
+    def dl_batch_release_n(self, slots):
+        return [self.dl_batch_fetch(s) for s in slots]
+
+
+BATCHES = [StandInBatch, StandInBulkBatch]
+
+
 def _edges(req):
     return torch.from_numpy(dlgen.request_edges(req)).to(torch.int32)
 
 
-def test_burst_every_request_once():
+@pytest.mark.parametrize("cls", BATCHES)
+def test_burst_every_request_once(cls):
     reqs = dlgen.serving_stream(60, seed=3, rate=0.0, n_lo=64, n_hi=300)
-    b = StandInBatch(slots=8, pool_bytes=1 << 30)
+    b = cls(slots=8, pool_bytes=1 << 30)
     stats, results = run_stream(reqs, _edges, pool_bytes=0, batch=b)
     tags = sorted(c.tag for c in stats.completions)
     assert tags == list(range(60)) and sorted(b.admitted) == tags
@@ -85,27 +113,42 @@ def test_burst_every_request_once():
         assert c.arrival <= c.admitted <= c.finished and c.iters == 7 and c.ones == 11
 
 
-def test_pool_memory_limits_admission():
+@pytest.mark.parametrize("cls", BATCHES)
+def test_pool_memory_limits_admission(cls):
     reqs = dlgen.serving_stream(30, seed=4, rate=0.0, n_lo=200, n_hi=300)
     pool = 3 * 4 * 300 * 300  # room for about three requests at a time
-    b = StandInBatch(slots=16, pool_bytes=pool)
+    b = cls(slots=16, pool_bytes=pool)
     stats, _ = run_stream(reqs, _edges, pool_bytes=0, batch=b)
     assert len(stats.completions) == 30
     assert stats.max_active <= pool // (4 * min(r.n for r in reqs) ** 2) and stats.eagain > 0
 
 
-def test_arrivals_are_respected():
+@pytest.mark.parametrize("cls", BATCHES)
+def test_arrivals_are_respected(cls):
     reqs = dlgen.serving_stream(40, seed=5, rate=4000.0, n_lo=64, n_hi=128)
     assert reqs[-1].arrival > 0.0
-    b = StandInBatch(slots=4, pool_bytes=1 << 30)
+    b = cls(slots=4, pool_bytes=1 << 30)
     stats, _ = run_stream(reqs, _edges, pool_bytes=0, batch=b)
     assert len(stats.completions) == 40
     for c in stats.completions:
         assert c.admitted >= c.arrival  # never admitted before it arrives
 
 
-def test_request_larger_than_the_pool():
+@pytest.mark.parametrize("cls", BATCHES)
+def test_request_larger_than_the_pool(cls):
     reqs = dlgen.serving_stream(3, seed=6, rate=0.0, n_lo=500, n_hi=600)
-    b = StandInBatch(slots=4, pool_bytes=4 * 100 * 100)
+    b = cls(slots=4, pool_bytes=4 * 100 * 100)
     with pytest.raises(RuntimeError, match="does not fit an empty pool"):
         run_stream(reqs, _edges, pool_bytes=0, batch=b)
+
+
+def test_burst_admitted_in_chunks():
+    """A burst larger than the admission chunk is admitted a chunk per round,
+    with one bulk call per chunk, while the earlier requests run."""
+    reqs = dlgen.serving_stream(50, seed=7, rate=0.0, n_lo=64, n_hi=100)
+    b = StandInBulkBatch(slots=64, pool_bytes=1 << 30)
+    stats, _ = run_stream(reqs, _edges, pool_bytes=0, batch=b, admit_chunk=16)
+    assert sorted(c.tag for c in stats.completions) == list(range(50))
+    assert b.bulk_calls == 4  # 16 + 16 + 16 + 2
+    first = sorted(c.admitted for c in stats.completions)
+    assert first[15] < first[16]  # the second chunk came after a round
