@@ -1177,6 +1177,21 @@ __device__ inline void wait_vmcnt() {
 // stores four 16-byte segments of out^T.  Returns this thread's ones.
 __device__ inline int ep_swz(int r) { return (r ^ (r >> 4)) & 15; }
 
+// The four 0/1 bytes of an accumulator fragment (element i of a lane ->
+// byte i): counts are non-negative, so an integer count becomes its byte by
+// min(count, 1).
+template <class Op>
+__device__ inline unsigned pack_nz4(const typename Op::Acc& a) {
+  if constexpr (__is_same(typename Op::Acc, v4i)) {
+    const unsigned b0 = min((unsigned)a[0], 1u), b1 = min((unsigned)a[1], 1u), b2 = min((unsigned)a[2], 1u),
+                   b3 = min((unsigned)a[3], 1u);
+    return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+  } else {
+    return (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
+           (Op::nz(a, 3) ? 0x1000000u : 0u);
+  }
+}
+
 // HAS_ADD: p.add is set.  Without an addend no global load is issued here,
 // so nothing in the epilogue waits on memory (a next tile's first slice
 // prefetched just before it stays in flight).
@@ -1207,41 +1222,40 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
     addv[e] = u32x4{0u, 0u, 0u, 0u};
     if constexpr (HAS_ADD) addv[e] = load_add16<Op::kPrec>(p, row0 + seg_row(e), col0 + seg_col(e));
   }
+  // Only tiles that the diagonal crosses take the identity (a uniform
+  // branch: the per-byte test costs every other tile nothing).
+  const bool diag = row0 < col0 + BN && col0 < row0 + BM;
+  const bool add_id = p.add_identity && diag, outT_id = p.outT_ident && diag;
   // one 16-byte output segment: addend, identity, count, store, LDS copy
   // (with the identity when the transposed copy is the next step's Y)
   auto emit = [&](u32x4 v, int e) {
     const int lr = seg_row(e), lc = seg_col(e);
     const int gr = row0 + lr, gc = col0 + lc;
     if constexpr (HAS_ADD) v |= addv[e];
-    if (p.add_identity) v = with_diag(v, gr, gc, p.n_valid);
+    if (add_id) v = with_diag(v, gr, gc, p.n_valid);
     cnt += popc16(v);
     store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
-    if (p.outT)
-      *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = p.outT_ident ? with_diag(v, gr, gc, p.n_valid) : v;
+    if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = outT_id ? with_diag(v, gr, gc, p.n_valid) : v;
   };
   if constexpr (K::FR == 16) {
-    const int g = lane >> 4;
 #pragma unroll
     for (int i = 0; i < K::FM; ++i) {
 #pragma unroll
       for (int q = 0; q < K::FN / 4; ++q) {
+        // P[t]: the four 0/1 bytes this lane holds of column tile 4 q + t
         unsigned P[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const auto& a = acc[i][4 * q + t];
-          P[t] = (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
-                 (Op::nz(a, 3) ? 0x1000000u : 0u);
-        }
-        u32x4 v = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = g ^ r;  // offer P[g ^ r]; receive lane (g ^ r)'s P[g] into dword g ^ r
-          const unsigned offer = k == 0 ? P[0] : (k == 1 ? P[1] : (k == 2 ? P[2] : P[3]));
-          const unsigned got = r == 0 ? offer : (unsigned)__shfl_xor((int)offer, 16 * r, 64);
-#pragma unroll
-          for (int d = 0; d < 4; ++d) v[d] = d == k ? got : v[d];
-        }
-        emit(v, i * (K::FN / 4) + q);
+        for (int t = 0; t < 4; ++t) P[t] = pack_nz4<Op>(acc[i][4 * q + t]);
+        // 4 x 4 dword transpose over the lane rows g = lane / 16 (lane g
+        // then holds the 16 bytes of column tile 4 q + g): swap the odd
+        // 16-lane rows of P[0] / P[2] with the even rows of P[1] / P[3],
+        // then rows 2-3 of P[0] / P[1] with rows 0-1 of P[2] / P[3]
+        // (v_permlane16_swap / v_permlane32_swap, no LDS round trip)
+        const auto s01 = __builtin_amdgcn_permlane16_swap(P[0], P[1], false, false);
+        const auto s23 = __builtin_amdgcn_permlane16_swap(P[2], P[3], false, false);
+        const auto s02 = __builtin_amdgcn_permlane32_swap(s01[0], s23[0], false, false);
+        const auto s13 = __builtin_amdgcn_permlane32_swap(s01[1], s23[1], false, false);
+        emit(u32x4{s02[0], s13[0], s02[1], s13[1]}, i * (K::FN / 4) + q);
       }
     }
   } else {
