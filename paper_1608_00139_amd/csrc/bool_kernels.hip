@@ -1165,7 +1165,7 @@ __device__ inline void wait_vmcnt() {
 // (i, j) is C[row WM wm + 16 i + c][col WN wn + 16 j + 4 g + v], so a lane
 // holds four consecutive bytes of one output row.  Four lanes (g = 0..3,
 // same c) hold a row's 64 bytes over the column tiles 4q .. 4q + 3; a 4 x 4
-// dword transpose across them (shuffles on lane ^ 16 r) leaves lane g with
+// dword transpose across them (permlane swaps of 16-lane rows) leaves lane g with
 // the 16 bytes of tile 4q + g, which are OR-ed with the addend and stored
 // straight to global memory (16 rows x 64 contiguous bytes per instruction).
 // 32 x 32 tiles need only one exchange of two dwords between lanes l and
