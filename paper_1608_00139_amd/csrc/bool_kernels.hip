@@ -1352,9 +1352,17 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
     const int c = (lane % K::KC) ^ rsw<K::KC>(r);
     return ((r < BM) ? (Xb + (int64_t)r * lb) : (Yb + (int64_t)(r - BM) * lb)) + c * 16;
   };
-  const uint8_t* src[K::DMA_PER_WAVE];
-#pragma unroll
-  for (int j = 0; j < K::DMA_PER_WAVE; ++j) src[j] = lane_src(Xg, Yg, ldb, j);
+  // Instruction j of this wave reads rows r0 + j NWAVES ROWS_PER_DMA of the
+  // X panel then the Y panel at the same chunk c (rsw repeats every 32
+  // rows): one lane offset and a uniform base per instruction, so the
+  // addresses take one register instead of one pointer per instruction.
+  static_assert((K::NWAVES * K::ROWS_PER_DMA) % 32 == 0, "the row swizzle must repeat across instructions");
+  const int r0 = wave * K::ROWS_PER_DMA + lane / K::KC;
+  const unsigned lane_off = (unsigned)(r0 * ldb + 16 * ((lane % K::KC) ^ rsw<K::KC>(r0)));
+  auto base_of = [&](const uint8_t* Xb, const uint8_t* Yb, int64_t lb, int j) {
+    const int jr = j * K::NWAVES * K::ROWS_PER_DMA;  // uniform
+    return jr < BM ? Xb + (int64_t)jr * lb : Yb + (int64_t)(jr - BM) * lb;
+  };
   // the next tile's slice 0 goes to slot 0 while this tile's last slice
   // (slot 1: nk even) is multiplied and its epilogue uses slot 1
   constexpr bool CAN_PREFETCH = K::SWAPPED && NSTAGE == 2 && (size_t)BM * BN <= K::STAGE_BYTES;
@@ -1364,9 +1372,18 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
 #pragma unroll
     for (int j = 0; j < K::DMA_PER_WAVE; ++j) {
       uint8_t* dst = stage + (wave + j * K::NWAVES) * 1024;  // wave-uniform
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[j] + (int64_t)kt * KB),
-                                       (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(base_of(Xg, Yg, ldb, j) + (int64_t)kt * KB + lane_off),
+          (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
+  };
+  // the next tile's slice 0 into slot 0
+  auto issue_next0 = [&]() {
+#pragma unroll
+    for (int j = 0; j < K::DMA_PER_WAVE; ++j)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)lane_src(next.X, next.Y, next.ldb, j),
+                                       (__attribute__((address_space(3))) void*)(smem + (wave + j * K::NWAVES) * 1024),
+                                       16, 0, 0);
   };
 
   typename Op::Acc acc[K::FM][K::FN];
@@ -1418,6 +1435,51 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
     }
   };
 
+  // Two slots of two MFMA k-steps: the barrier that makes slice kt + 1
+  // visible is taken in the middle of slice kt's products -- after the
+  // first k-step -- and the second k-step's products (their fragments read
+  // before it) are issued after it, just before the waves fetch slice
+  // kt + 1's fragments.  The matrix cores then have queued work while all
+  // 16 waves read LDS at once, instead of idling behind every barrier
+  // (barrier after half of the second k-step, after three quarters of it,
+  // or in the middle of the first: 0.3 - 4% slower at N = 8192).
+  constexpr bool SPLIT = NSTAGE == 2 && K::KSTEPS == 2 && Op::kPrec != P_FP4;  // fp4 would spill registers
+  auto products = [&](const FragA& a, const FragB& b, int j0, int j1) {
+#pragma unroll
+    for (int i = 0; i < K::FM; ++i)
+#pragma unroll
+      for (int j = j0; j < j1; ++j) {
+        if constexpr (K::SWAPPED)
+          acc[i][j] = Op::mma(b[j], a[i], acc[i][j]);  // tile of C^T
+        else
+          acc[i][j] = Op::mma(a[i], b[j], acc[i][j]);
+      }
+  };
+  if constexpr (SPLIT) {
+    // prologue: slice 0 (already in flight when the previous tile fetched it)
+    if (!pre) issue(0);
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (1 < nk) issue(1);
+    for (int kt = 0; kt < nk; ++kt) {
+      const uint8_t* xs = smem + (kt & 1) * K::STAGE_BYTES;
+      FragA fa0, fa1;
+      FragB fb0, fb1;
+      load_frags(xs, xs + BM * KB, 0, fa0, fb0);
+      load_frags(xs, xs + BM * KB, 1, fa1, fb1);
+      products(fa0, fb0, 0, K::FN);
+      if (kt + 1 < nk) {
+        // slice kt + 1, issued one barrier ago, is this wave's only load in
+        // flight; the barrier extends its arrival to every wave and, with
+        // every LDS read of this wave retired first, frees slot kt % 2
+        wait_vmcnt<0>();
+        lds_barrier();
+        if (kt + 2 < nk) issue(kt + 2);
+        else if (prefetch) issue_next0();  // kt + 2 == nk: the next tile's slice 0, slot 0 (nk even)
+      }
+      products(fa1, fb1, 0, K::FN);
+    }
+  } else {
   // prologue: NSTAGE - 1 slices in flight (slice 0 may be in flight already)
 #pragma unroll
   for (int s0 = 0; s0 < NSTAGE - 1; ++s0)
@@ -1430,15 +1492,9 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
     else wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
     if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
-    if (prefetch && kt == nk - 1) {
-#pragma unroll
-      for (int j = 0; j < K::DMA_PER_WAVE; ++j)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)lane_src(next.X, next.Y,
-                                                                                               next.ldb, j),
-                                         (__attribute__((address_space(3))) void*)(smem + (wave + j * K::NWAVES) * 1024),
-                                         16, 0, 0);
-    }
+    if (prefetch && kt == nk - 1) issue_next0();
     compute(kt % NSTAGE);
+  }
   }
   if (prefetch) {
     __builtin_amdgcn_s_barrier();  // every wave is done reading slot 1; the next slice 0 stays in flight
