@@ -573,10 +573,14 @@ size_t small_lds_bytes(int64_t ldb) { return (size_t)64 * ldb + kSmallPart + 32 
 // groups 1..3 handing their partial sums to group 0 through LDS, which
 // writes the 0/1 result into the epilogue tile et (32 rows of kSmallEst
 // bytes).  Called by all kSmallThreads threads; ends before the barrier
-// that publishes et.
-template <class Op>
+// that publishes et.  With XBYTES (fp32 only) the 32 X rows are 0/1 bytes
+// instead, xrow bytes per row from the start of the LDS image with the
+// 16-byte chunk c of row r at c ^ (r & 15), and each lane turns the four
+// bytes behind its operand chunk into four floats.
+template <class Op, bool XBYTES = false>
 __device__ inline void small_tile_product(uint8_t* smem, int64_t ldb, int kc, int mask, int lane, int wave,
-                                          uint8_t* et) {
+                                          uint8_t* et, int xrow = 0) {
+  static_assert(!XBYTES || Op::kPrec == P_F32, "byte-valued X rows feed the fp32 product only");
   constexpr int KSTEP_CHUNKS = (64 / Op::FR) * Op::CPL;
   const int kg = wave >> 2, wq = wave & 3;  // K group, block of the tile
   const int wm = wq >> 1, wn = wq & 1;
@@ -591,7 +595,15 @@ __device__ inline void small_tile_product(uint8_t* smem, int64_t ldb, int kc, in
 #pragma unroll
     for (int c = 0; c < Op::CPL; ++c) {
       const int ch = ks * KSTEP_CHUNKS + g * Op::CPL + c;
-      a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
+      if constexpr (XBYTES) {
+        // fp32 chunk ch = 4 ks + g holds k = 16 ks + 4 g .. + 3: dword g of
+        // byte chunk ks of the row
+        const unsigned w = *(const unsigned*)(smem + ra * xrow + 16 * (ks ^ (ra & 15)) + 4 * g);
+        const v4f f = {(float)(w & 0xffu), (float)((w >> 8) & 0xffu), (float)((w >> 16) & 0xffu), (float)(w >> 24)};
+        a[c] = __builtin_bit_cast(u32x4, f);
+      } else {
+        a[c] = *(const u32x4*)(xa + 16 * (ch ^ (ra & mask)));
+      }
       b[c] = *(const u32x4*)(yb + 16 * (ch ^ (rb & mask)));
     }
     acc = Op::mma(a, b, acc);
@@ -844,6 +856,10 @@ template <class Op>
 __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   __shared__ int s_go;  // 1 compute the step, 0 stop, -1 abort
+  // fp32: the iterates are kept as 0/1 bytes (Np bytes per row) and widened
+  // to floats as the product reads them, so that a step publishes and
+  // fetches a quarter of the bytes
+  constexpr bool XB = Op::kPrec == P_F32;
   constexpr int NIB = elem_nibbles(Op::kPrec);
   constexpr int EPC = 32 / NIB;  // operand elements per 16-byte chunk
   const unsigned G = gridDim.x;
@@ -914,8 +930,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
     if (wave == 0) {
       const int r = lane >> 1, cs = lane & 1;
       const u32x4 v = *(const u32x4*)(et + r * kSmallEst + 16 * cs);
-      store_bool16_agent<Op::kPrec>(buffer_of(p.S[t & 1], (unsigned)(ldb * p.Np)),
-                                    (int)(((int64_t)(row0 + r) * p.Np + col0 + 16 * cs) * NIB / 2), v);
+      if constexpr (XB)
+        st_agent_x4(buffer_of(p.S[t & 1], (unsigned)(p.Np * p.Np)), (row0 + r) * p.Np + col0 + 16 * cs, v);
+      else
+        store_bool16_agent<Op::kPrec>(buffer_of(p.S[t & 1], (unsigned)(ldb * p.Np)),
+                                      (int)(((int64_t)(row0 + r) * p.Np + col0 + 16 * cs) * NIB / 2), v);
       const int cnt = wave_sum(popc16(v));
       const unsigned changed = cnt != prev_cnt ? 1u : 0u;
       prev_cnt = cnt;
@@ -944,16 +963,18 @@ __global__ void __launch_bounds__(kSmallThreads) k_fix_small(FixSmallParams p) {
     if (go < 0) return;
     if (go == 0) break;
     // X = rows row0 .. row0 + 31 of S^(t-1) into LDS rows 0..31
-    const uint8_t* Xg = (const uint8_t*)p.S[(t - 1) & 1] + (int64_t)row0 * ldb;
-    for (int i = wave; i < kc / 2; i += kSmallThreads / 64) {
+    const int xrow = XB ? p.Np : (int)ldb;  // bytes per X row (global and LDS)
+    const int xc = xrow / 16, xmask = XB ? 15 : mask;
+    const uint8_t* Xg = (const uint8_t*)p.S[(t - 1) & 1] + (int64_t)row0 * xrow;
+    for (int i = wave; i < xc / 2; i += kSmallThreads / 64) {
       const int q = 64 * i + lane;
-      const int r = q / kc, pos = q % kc;
-      const int c = pos ^ (r & mask);
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Xg + (int64_t)r * ldb + 16 * c),
+      const int r = q / xc, pos = q % xc;
+      const int c = pos ^ (r & xmask);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(Xg + (int64_t)r * xrow + 16 * c),
                                        (__attribute__((address_space(3))) void*)(smem + 1024 * i), 16, 0, kCpolSc1);
     }
     __syncthreads();  // vmcnt(0): the panel is in LDS
-    small_tile_product<Op>(smem, ldb, kc, mask, lane, wave, et);
+    small_tile_product<Op, XB>(smem, ldb, kc, mask, lane, wave, et, xrow);
     __syncthreads();
   }
   // the last iterate computed, S^(t-1), back to R = S^T, cropped; every

@@ -103,7 +103,7 @@ struct FixSmallParams {
   int64_t lda;
   uint8_t* R;
   int64_t ldr;
-  void* S[2];                    // iterates in operand precision, Np x Np (S^(t) in S[t & 1])
+  void* S[2];                    // iterates, Np x Np (S^(t) in S[t & 1]): fp32 as 0/1 bytes, others in operand precision
   // counters: zero when the launch starts, and left zero by a launch that
   // ends normally (the last workgroup clears them); see fix_small_words
   unsigned long long* ones_row;  // [tiles][Np + 3] model size of each row block per step
