@@ -86,6 +86,14 @@ def main() -> int:
                          "(the most launched one) instead of the int8 step kernel")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving workload (--serve-requests of them) and print its JSON")
+    ap.add_argument("--phase-gaps", type=float, default=0.0, metavar="SECONDS",
+                    help="idle time around each timed serving run, so that a kernel trace splits into "
+                         "one segment per run (see --trace-busy)")
+    ap.add_argument("--trace-busy", metavar="DB",
+                    help="split a rocprofv3 --kernel-trace database at device idle gaps of at least "
+                         "--gap-ms and print each segment's span, the time some kernel ran, and its "
+                         "largest kernels, then exit")
+    ap.add_argument("--gap-ms", type=float, default=100.0)
     ap.add_argument("--programs-only", action="store_true",
                     help="run only the layered program workloads (both methods) and print their JSON")
     args = ap.parse_args()
@@ -111,8 +119,10 @@ def main() -> int:
         import paper_1608_00139_amd as dl
 
         torch.cuda.set_device(0)
-        print(json.dumps(run_serving(dl, torch, args.serve_requests)))
+        print(json.dumps(run_serving(dl, torch, args.serve_requests, gaps=args.phase_gaps)))
         return 0
+    if args.trace_busy:
+        return trace_busy(args.trace_busy, args.gap_ms)
     if args.trace_summary:
         return trace_summary(args.trace_summary)
     if args.pmc_summary:
@@ -554,7 +564,7 @@ def graphs_dev_release(graphs):
     return []
 
 
-def run_serving(dl, torch, count: int, seed: int = 0):
+def run_serving(dl, torch, count: int, seed: int = 0, gaps: float = 0.0):
     """Serving stream: 70% closure / 30% same generation, n log-uniform in
     [64, 2048], ER p = 3/n or random forests.  A closed-loop burst of
     min(count, 2000) requests (all arriving at t = 0) measures the saturated
@@ -563,7 +573,10 @@ def run_serving(dl, torch, count: int, seed: int = 0):
     up to 3000 more at 0.5x and at 0.95x).  Latency = completion -
     arrival.  Relations are generated as edge lists before the run, kept on
     the device, and built into the request's buffers by the library's
-    edge-list admission (dl_batch_submit_edges)."""
+    edge-list admission (dl_batch_submit_edges).  gaps > 0 leaves the device
+    idle for that many seconds around each timed run (for kernel traces)."""
+    import time
+
     import numpy as np
 
     import dlgen
@@ -598,13 +611,24 @@ def run_serving(dl, torch, count: int, seed: int = 0):
     mk = prepare(burst)
     warm = dlgen.serving_stream(64, seed + 1, rate=0.0)
     run_stream(warm, prepare(warm), pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
-    sb, _ = run_stream(burst, mk, pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+
+    def timed_run(reqs, make):
+        if gaps > 0:
+            torch.cuda.synchronize()
+            time.sleep(gaps)
+        r = run_stream(reqs, make, pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+        if gaps > 0:
+            torch.cuda.synchronize()
+            time.sleep(gaps)
+        return r
+
+    sb, _ = timed_run(burst, mk)
     sat = sb.summary()
     rate = 0.8 * sat["req_per_s"]
     stream = dlgen.serving_stream(count, seed, rate=rate)
     log(f"serving: Poisson stream of {count} at {rate:.0f} req/s")
     mk = prepare(stream)
-    st, _ = run_stream(stream, mk, pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+    st, _ = timed_run(stream, mk)
     ops = 0.0
     for c in st.completions:
         per_step = 2.0 if c.kind == 1 else 1.0
@@ -619,7 +643,7 @@ def run_serving(dl, torch, count: int, seed: int = 0):
         else:
             sw = dlgen.serving_stream(min(count, 3000), seed + 2 + k, rate=frac * sat["req_per_s"])
             log(f"serving: Poisson stream of {len(sw)} at {frac}x saturation")
-            sx, _ = run_stream(sw, prepare(sw), pool_bytes=pool, max_active=512, lookahead=1, tiles=tiles)
+            sx, _ = timed_run(sw, prepare(sw))
             s_ = sx.summary()
         sweep.append({"offered_frac": frac, "offered_rate": round(frac * sat["req_per_s"], 1),
                       "requests": s_["requests"], "req_per_s": s_["req_per_s"],
@@ -959,6 +983,45 @@ def busy_summary(csv_path: str) -> int:
         cyc = sum(d["GRBM_GUI_ACTIVE"] for d in ds) / len(ds) / xcds
         busy = sum(d["SQ_VALU_MFMA_BUSY_CYCLES"] for d in ds) / len(ds) / (cyc * simds)
         print(f"  {len(ds):8d} {ns / 1e3:10.1f} {cyc / ns:9.3f} {busy:9.3f}  {name.split('(')[0].replace('void ', '')}")
+    return 0
+
+
+def trace_busy(db_path: str, gap_ms: float) -> int:
+    """Device occupancy of a rocprofv3 kernel trace, per segment: the trace is
+    cut wherever no kernel runs for gap_ms or more; for each segment, its span
+    (first start to last end), the time at least one kernel was running (the
+    union of the kernel intervals) and the kernels with the most time."""
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    rows = sorted(con.execute("select start, end, name from kernels").fetchall())
+    if not rows:
+        print("no kernels in the trace")
+        return 1
+    segs, cur, cur_end = [], [], None
+    for r in rows:
+        if cur and r[0] - cur_end >= gap_ms * 1e6:
+            segs.append(cur)
+            cur = []
+        cur.append(r)
+        cur_end = r[1] if not cur_end or len(cur) == 1 else max(cur_end, r[1])
+    segs.append(cur)
+    print(f"# segments of {db_path} split at device idle gaps >= {gap_ms:g} ms")
+    print(f"# {'seg':>3} {'kernels':>8} {'span_ms':>9} {'busy_ms':>9} {'busy':>6}  largest kernels (ms)")
+    for i, sg in enumerate(segs):
+        t0, t1 = sg[0][0], max(e for _, e, _ in sg)
+        busy, reach = 0, t0
+        for s, e, _ in sg:
+            if e > reach:
+                busy += e - max(s, reach)
+                reach = e
+        per = {}
+        for s, e, n in sg:
+            k = n.split("(")[0].replace("void ", "")
+            per[k] = per.get(k, 0) + (e - s)
+        top = sorted(per.items(), key=lambda x: -x[1])[:4]
+        print(f"  {i:3d} {len(sg):8d} {(t1 - t0) / 1e6:9.2f} {busy / 1e6:9.2f} {busy / (t1 - t0):6.3f}  "
+              + ", ".join(f"{k} {v / 1e6:.2f}" for k, v in top))
     return 0
 
 
