@@ -1200,13 +1200,23 @@ __device__ inline int ep_swz(int r) { return (r ^ (r >> 4)) & 15; }
 
 // The four 0/1 bytes of an accumulator fragment (element i of a lane ->
 // byte i): counts are non-negative, so an integer count becomes its byte by
-// min(count, 1).
+// min(count, 1), which v_min_u32 with a byte destination select writes
+// straight into byte i (SDWA, the other bytes kept): four instructions per
+// fragment, where the compiler makes a compare, a select and an OR of each.
 template <class Op>
 __device__ inline unsigned pack_nz4(const typename Op::Acc& a) {
   if constexpr (__is_same(typename Op::Acc, v4i)) {
-    const unsigned b0 = min((unsigned)a[0], 1u), b1 = min((unsigned)a[1], 1u), b2 = min((unsigned)a[2], 1u),
-                   b3 = min((unsigned)a[3], 1u);
-    return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+    const unsigned one = 1u;
+    unsigned r;
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:BYTE_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+        : "=v"(r) : "v"(a[0]), "v"(one));
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+        : "+v"(r) : "v"(a[1]), "v"(one));
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:BYTE_2 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+        : "+v"(r) : "v"(a[2]), "v"(one));
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+        : "+v"(r) : "v"(a[3]), "v"(one));
+    return r;
   } else {
     return (Op::nz(a, 0) ? 1u : 0u) | (Op::nz(a, 1) ? 0x100u : 0u) | (Op::nz(a, 2) ? 0x10000u : 0u) |
            (Op::nz(a, 3) ? 0x1000000u : 0u);
@@ -1247,18 +1257,22 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
   // branch: the per-byte test costs every other tile nothing).
   const bool diag = row0 < col0 + BN && col0 < row0 + BM;
   const bool add_id = p.add_identity && diag, outT_id = p.outT_ident && diag;
-  // one 16-byte output segment: addend, identity, count, store, LDS copy
-  // (with the identity when the transposed copy is the next step's Y)
-  auto emit = [&](u32x4 v, int e) {
+  // one 16-byte output segment at dst: addend, identity, count, store, LDS
+  // copy (with the identity when the transposed copy is the next step's Y)
+  auto emit = [&](u32x4 v, int e, uint8_t* dst) {
     const int lr = seg_row(e), lc = seg_col(e);
     const int gr = row0 + lr, gc = col0 + lc;
     if constexpr (HAS_ADD) v |= addv[e];
     if (add_id) v = with_diag(v, gr, gc, p.n_valid);
     cnt += popc16(v);
-    store_bool16<Op::kPrec>(outb + ((int64_t)gr * p.ld + gc) * K::NIB / 2, v);
+    store_bool16<Op::kPrec>(dst, v);
     if (p.outT) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = outT_id ? with_diag(v, gr, gc, p.n_valid) : v;
   };
   if constexpr (K::FR == 16) {
+    // segment (i, q) lies 16 i rows and 64 q columns from segment (0, 0):
+    // one 64-bit product per tile, then uniform offsets
+    uint8_t* const seg00 = outb + ((int64_t)(row0 + seg_row(0)) * p.ld + col0 + seg_col(0)) * K::NIB / 2;
+    const int64_t rstep = (int64_t)16 * p.ld * K::NIB / 2;
 #pragma unroll
     for (int i = 0; i < K::FM; ++i) {
 #pragma unroll
@@ -1276,7 +1290,7 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
         const auto s23 = __builtin_amdgcn_permlane16_swap(P[2], P[3], false, false);
         const auto s02 = __builtin_amdgcn_permlane32_swap(s01[0], s23[0], false, false);
         const auto s13 = __builtin_amdgcn_permlane32_swap(s01[1], s23[1], false, false);
-        emit(u32x4{s02[0], s13[0], s02[1], s13[1]}, i * (K::FN / 4) + q);
+        emit(u32x4{s02[0], s13[0], s02[1], s13[1]}, i * (K::FN / 4) + q, seg00 + i * rstep + q * 64 * K::NIB / 2);
       }
     }
   } else {
@@ -1297,7 +1311,8 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
         const unsigned r0 = (unsigned)__shfl_xor((int)(h ? D[0] : D[2]), 32, 64);
         const unsigned r1 = (unsigned)__shfl_xor((int)(h ? D[1] : D[3]), 32, 64);
         const u32x4 v = h ? u32x4{r0, D[2], r1, D[3]} : u32x4{D[0], r0, D[1], r1};
-        emit(v, i * K::FN + j);
+        const int e = i * K::FN + j;
+        emit(v, e, outb + ((int64_t)(row0 + seg_row(e)) * p.ld + col0 + seg_col(e)) * K::NIB / 2);
       }
     }
   }
@@ -1314,18 +1329,21 @@ __device__ inline int dma_epilogue_swapped(const NTParams& p, const typename Op:
         const int lr = 16 * rb + k;
         d[k] = *(const unsigned*)(et + lr * BN + 16 * ((cb >> 2) ^ ep_swz(lr)) + 4 * x);
       }
+      // row 4 cb + qq of out^T, columns 16 rb .. 16 rb + 15 of the tile
+      uint8_t* const trow = outt + ((int64_t)(col0 + 4 * cb) * p.ld + row0 + 16 * rb) * K::NIB / 2;
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        // byte qq of d[k] is element (row 16 rb + k, column 4 cb + qq)
-        const unsigned sel = (unsigned)qq | ((unsigned)(4 + qq) << 8);
+        // byte qq of d[k] is element (row 16 rb + k, column 4 cb + qq); the
+        // selectors put it in byte k % 4 of dword k / 4 and zero the rest
+        // (selector byte 0x0c gives 0x00)
+        const unsigned sel_lo = (unsigned)qq | ((unsigned)(4 + qq) << 8) | 0x0c0c0000u;
+        const unsigned sel_hi = 0x0c0cu | ((unsigned)qq << 16) | ((unsigned)(4 + qq) << 24);
         u32x4 t;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const unsigned lo = __builtin_amdgcn_perm(d[4 * m + 1], d[4 * m], sel) & 0xffffu;
-          const unsigned hi = __builtin_amdgcn_perm(d[4 * m + 3], d[4 * m + 2], sel);
-          t[m] = lo | (hi << 16);
-        }
-        store_bool16<Op::kPrec>(outt + ((int64_t)(col0 + 4 * cb + qq) * p.ld + row0 + 16 * rb) * K::NIB / 2, t);
+        for (int m = 0; m < 4; ++m)
+          t[m] = __builtin_amdgcn_perm(d[4 * m + 1], d[4 * m], sel_lo) |
+                 __builtin_amdgcn_perm(d[4 * m + 3], d[4 * m + 2], sel_hi);
+        store_bool16<Op::kPrec>(trow + (int64_t)qq * p.ld * K::NIB / 2, t);
       }
     }
   }
