@@ -18,20 +18,22 @@
 // Layered programs still pass an addend (their running sums).
 // min1 on the non-negative integer counts is the test "!= 0" (Sec. 2, 3).
 //
-// Operands hold exactly 0 or 1 in the chosen precision (int8, fp32, bf16 or
-// fp8 e4m3), so every product is exact: int32 accumulation, or fp32
-// accumulation of counts below 2^24.
+// Operands hold exactly 0 or 1 in the chosen precision (int8, fp32, bf16,
+// fp8 e4m3 or fp4 e2m1), so every product is exact: int32 accumulation, or
+// fp32 accumulation of counts below 2^24.
 //
-// Kernel structure: one workgroup computes a BM x BN output tile, staging
-// BK-byte slices of its X and Y row panels through LDS with double
-// buffering.  LDS holds each slice as 16-byte chunks ordered
+// Kernel structure (k_nt_step): one workgroup computes a BM x BN output
+// tile, staging BK-byte slices of its X and Y row panels through LDS with
+// double buffering.  LDS holds each slice as 16-byte chunks ordered
 // [chunk][row][16 B], so the 16 lanes that read one MFMA operand chunk read
 // 256 contiguous bytes (no bank conflicts).  The epilogue stages the 0/1
 // tile through LDS, ORs the addend with 16-byte loads, stores coalesced rows
 // (and, for squaring, the transposed tile), and counts the ones of the tile
-// with a wave reduction and a single atomic per workgroup.  A launch first
-// checks the device-side convergence state and returns at once if the
-// fixpoint was already reached, so chunks of steps can be enqueued ahead.
+// with a wave reduction and a single atomic per workgroup.  The large-tile
+// kernel (k_nt_dma, below) fetches its slices straight into LDS and keeps
+// the tile in registers until the stores.  A launch first checks the
+// device-side convergence state and returns at once if the fixpoint was
+// already reached, so chunks of steps can be enqueued ahead.
 #include "common.h"
 
 namespace dl {
