@@ -206,15 +206,12 @@ __device__ inline unsigned elem_nz(const uint8_t* p, int64_t idx) {
   else return p[idx] != 0 ? 1u : 0u;
 }
 
-// The 16 addend flags of row gr, columns gc .. gc + 15 (gc a multiple of 16)
-// as 0/1 bytes: from an int8 0/1 addend, or (p.add_op) from an addend in the
-// operand precision PREC, any nonzero element being true.
+// The 16 consecutive elements of precision PREC at base (aligned to 16
+// elements) as 0/1 bytes, any nonzero element being true.
 template <int PREC>
-__device__ inline u32x4 load_add16(const NTParams& p, int gr, int gc) {
-  if (PREC == P_I8 || !p.add_op) return *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
-  const uint8_t* base = (const uint8_t*)p.add + ((int64_t)gr * p.ld + gc) * elem_nibbles(PREC) / 2;
+__device__ inline u32x4 bool16_of(const uint8_t* base) {
   u32x4 v = {0u, 0u, 0u, 0u};
-  if constexpr (PREC == P_FP8) {
+  if constexpr (PREC == P_FP8 || PREC == P_I8) {
     u32x4 x = *(const u32x4*)base;  // fold each byte's bits into its bit 0
     x |= x >> 4;
     x |= x >> 2;
@@ -247,6 +244,15 @@ __device__ inline u32x4 load_add16(const NTParams& p, int gr, int gc) {
     }
   }
   return v;
+}
+
+// The 16 addend flags of row gr, columns gc .. gc + 15 (gc a multiple of 16)
+// as 0/1 bytes: from an int8 0/1 addend, or (p.add_op) from an addend in the
+// operand precision PREC, any nonzero element being true.
+template <int PREC>
+__device__ inline u32x4 load_add16(const NTParams& p, int gr, int gc) {
+  if (PREC == P_I8 || !p.add_op) return *(const u32x4*)(p.add + (int64_t)gr * p.Np + gc);
+  return bool16_of<PREC>((const uint8_t*)p.add + ((int64_t)gr * p.ld + gc) * elem_nibbles(PREC) / 2);
 }
 
 __device__ inline int popc16(u32x4 v) {
@@ -2058,12 +2064,8 @@ k_emit(const uint8_t* __restrict__ S, int Np, int transpose, int n, uint8_t* R, 
     const int gi = bi * 64 + r, gj0 = bj * 64 + c0;
     if (gi < n) {
       uint8_t* dst = R + (int64_t)gi * ldr + gj0;
-      if ((PREC == P_I8 || PREC == P_FP8) && gj0 + 16 <= n && (((uintptr_t)dst) & 15) == 0) {
-        u32x4 x = *(const u32x4*)(S + (int64_t)gi * Np + gj0);
-        x |= x >> 4;
-        x |= x >> 2;
-        x |= x >> 1;
-        *(u32x4*)dst = x & 0x01010101u;
+      if (gj0 + 16 <= n && (((uintptr_t)dst) & 15) == 0) {
+        *(u32x4*)dst = bool16_of<PREC>(S + ((int64_t)gi * Np + gj0) * elem_nibbles(PREC) / 2);
       } else {
 #pragma unroll
         for (int t = 0; t < 16; ++t)
