@@ -750,26 +750,35 @@ __device__ inline void block_count(int (&c)[K], unsigned long long* out) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_count_positive(const double* X, int Np, unsigned long long* out) {
-  const int i = blockIdx.y;
+// Element-wise passes over a whole Np x Np matrix (Np even) walk it as
+// pairs of doubles on a fixed grid, so that each workgroup adds its counts
+// with one atomic per counter (one workgroup per 256 entries left ~10^5
+// atomics on the same two words, which serialised the pass).
+constexpr int kElemGrid = 2048;
+
+__global__ void __launch_bounds__(256) k_count_positive(const double* X, int64_t count, unsigned long long* out) {
   int c[1] = {0};
-  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) c[0] += X[(int64_t)i * Np + j] > 0.0;
+  const double2* X2 = (const double2*)X;
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < count / 2; q += (int64_t)gridDim.x * 256) {
+    const double2 x = X2[q];
+    c[0] += (x.x > 0.0) + (x.y > 0.0);
+  }
   block_count<1>(c, out);
 }
 
 // X += I (the doubling's increment) in place; counts the positive entries of
 // the new X into out[0] and the entries whose value changed into out[1].
 __global__ void __launch_bounds__(256)
-k_stein_accumulate(double* X, const double* I, int Np, unsigned long long* out) {
-  const int i = blockIdx.y;
+k_stein_accumulate(double* X, const double* I, int64_t count, unsigned long long* out) {
   int c[2] = {0, 0};
-  for (int j = blockIdx.x * 256 + threadIdx.x; j < Np; j += gridDim.x * 256) {
-    const int64_t o = (int64_t)i * Np + j;
-    const double x = X[o];
-    const double y = x + I[o];
-    c[0] += y > 0.0;
-    c[1] += y != x;
-    X[o] = y;
+  double2* X2 = (double2*)X;
+  const double2* I2 = (const double2*)I;
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < count / 2; q += (int64_t)gridDim.x * 256) {
+    const double2 x = X2[q], d = I2[q];
+    const double2 y = {x.x + d.x, x.y + d.y};
+    c[0] += (y.x > 0.0) + (y.y > 0.0);
+    c[1] += (y.x != x.x) + (y.y != x.y);
+    X2[q] = y;
   }
   block_count<2>(c, out);
 }
@@ -791,10 +800,9 @@ static hipError_t stein_doubling(int64_t Np, double* X, double* B, double* C, do
                                  bool c_is_bt, bool want_values, int max_doublings, hipStream_t s,
                                  unsigned long long* d_counter, unsigned long long* h_counter, int64_t* positives,
                                  int32_t* doublings, bool* done_out, std::string* err) {
-  const dim3 rows((unsigned)((Np + 255) / 256), (unsigned)Np);
   const dim3 tgrid((unsigned)(Np / 32), (unsigned)(Np / 32));
   EPS_CK(hipMemsetAsync(d_counter, 0, sizeof(unsigned long long), s), "counter clear");
-  hipLaunchKernelGGL(k_count_positive, rows, dim3(256), 0, s, (const double*)X, (int)Np, d_counter);
+  hipLaunchKernelGGL(k_count_positive, dim3(kElemGrid), dim3(256), 0, s, (const double*)X, (int64_t)Np * Np, d_counter);
   EPS_CK(hipGetLastError(), "count");
   EPS_CK(hipMemcpyAsync(h_counter, d_counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "readback");
   EPS_CK(hipStreamSynchronize(s), "sync");
@@ -815,7 +823,8 @@ static hipError_t stein_doubling(int64_t Np, double* X, double* B, double* C, do
     GemmArgs g3{T, Np, C, Np, nullptr, 0, B, Np, (int)Np, (int)Np, (int)Np, 0, -1};
     EPS_CK(dgemm(g3, s), "T C");
     EPS_CK(hipMemsetAsync(d_counter, 0, 2 * sizeof(unsigned long long), s), "counter clear");
-    hipLaunchKernelGGL(k_stein_accumulate, rows, dim3(256), 0, s, X, (const double*)B, (int)Np, d_counter);
+    hipLaunchKernelGGL(k_stein_accumulate, dim3(kElemGrid), dim3(256), 0, s, X, (const double*)B, (int64_t)Np * Np,
+                       d_counter);
     EPS_CK(hipGetLastError(), "accumulate");
     std::swap(B, Bn);
     if (c_is_bt) {
