@@ -2132,20 +2132,46 @@ hipError_t launch_ring_set(unsigned long long* ones, int slot, unsigned long lon
   return hipGetLastError();
 }
 
-// Largest row sum of the 0/1 relation (||A||_inf, Sec. 2): one workgroup per row.
+// Largest row sum of the 0/1 relation (||A||_inf, Sec. 2): one wave per row
+// on a grid of at most 1024 workgroups, 16 bytes per lane where the row is
+// 16-byte aligned, one atomic per workgroup (a workgroup per row with byte
+// loads and an atomic each took 116 us at N = 8192).
+constexpr int kRowMaxGrid = 1024;
+
 __global__ void __launch_bounds__(256) k_row_max(const uint8_t* A, int64_t lda, int n, int* out_max) {
-  const int row = blockIdx.x;
-  int s = 0;
-  for (int j = threadIdx.x; j < n; j += 256) s += A[(int64_t)row * lda + j] != 0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int best = 0;
+  for (int row = blockIdx.x * 4 + wave; row < n; row += gridDim.x * 4) {
+    const uint8_t* r = A + (int64_t)row * lda;
+    int s = 0, j0 = 0;
+    if (((uintptr_t)r & 15) == 0) {
+      const int nv = n / 16;
+      for (int v = lane; v < nv; v += 64) {
+        u32x4 x = *(const u32x4*)(r + 16 * v);
+        x |= x >> 4;  // each byte's bits folded into its bit 0
+        x |= x >> 2;
+        x |= x >> 1;
+        s += popc16(x & 0x01010101u);
+      }
+      j0 = 16 * nv;
+    }
+    for (int j = j0 + lane; j < n; j += 64) s += r[j] != 0;
+    s = wave_sum(s);
+    best = s > best ? s : best;
+  }
   __shared__ int red[4];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  if (lane == 0) red[wave] = best;
   __syncthreads();
-  if (threadIdx.x == 0) atomicMax(out_max, red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const int m = max(max(red[0], red[1]), max(red[2], red[3]));
+    if (m) atomicMax(out_max, m);
+  }
 }
 
 hipError_t launch_row_max(const uint8_t* A, int64_t lda, int n, int* out_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_max, dim3(n), dim3(256), 0, s, A, lda, n, out_max);
+  const int grid = (n + 3) / 4 < kRowMaxGrid ? (n + 3) / 4 : kRowMaxGrid;
+  if (grid < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_row_max, dim3(grid), dim3(256), 0, s, A, lda, n, out_max);
   return hipGetLastError();
 }
 
