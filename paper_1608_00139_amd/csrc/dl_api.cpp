@@ -291,7 +291,9 @@ class Fix {
   // Chunk sizes: squaring needs 2 + log2(D) steps (at most 18 for n <=
   // 65536): a first chunk of 6 covers D <= 16, then 4, 8, ...; launches
   // after the fixpoint return at once but still cost a few microseconds
-  // each.  The plain and same-generation series start at 4 and double.
+  // each.  The plain series starts at 4 and doubles; the same-generation
+  // series (two launches a step, each ~3 us when it returns at once) starts
+  // at 4 and grows by half, so that fewer steps run past its fixpoint.
   int chunk() {
     if (chunk_ == 0) chunk_ = mode_ == M_SQUARE ? 6 : 4;
     const int cnt = (int)std::min<int64_t>(chunk_, (int64_t)max_steps_ - s0_ + 1);
@@ -333,7 +335,7 @@ class Fix {
     }
     const int64_t upto = s0_ + cnt - 1;
     s0_ += cnt;
-    chunk_ = (mode_ == M_SQUARE && s0_ == 8) ? 4 : std::min(chunk_ * 2, 256);
+    chunk_ = (mode_ == M_SQUARE && s0_ == 8) ? 4 : std::min(mode_ == M_SG ? chunk_ + chunk_ / 2 : chunk_ * 2, 256);
     return readback(upto);
   }
 
