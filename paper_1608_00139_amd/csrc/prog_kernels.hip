@@ -142,36 +142,47 @@ __device__ inline int find_req(int nreq, long long x, F start) {
 
 // Clear every request's region in 16-byte units; units inside the identity
 // block get the diagonal bytes (i, i) for i < n; the thread that clears a
-// request's first unit zeroes its counter.
+// request's first unit zeroes its counter.  The requests' first units are
+// read into LDS once, so each unit's request is found by a search in LDS
+// (not by a chain of dependent global loads), and the unit's row in the
+// identity block by a 32-bit division (np^2 < 2^32).
 __global__ void __launch_bounds__(256) k_admit_clear(const AdmitDesc* __restrict__ d, int nreq, long long total) {
+  extern __shared__ long long s_first[];  // nreq entries
+  for (int i = threadIdx.x; i < nreq; i += 256) s_first[i] = d[i].clear_start;
+  __syncthreads();
   for (long long u = (long long)blockIdx.x * 256 + threadIdx.x; u < total; u += (long long)gridDim.x * 256) {
-    const int q = find_req(nreq, u, [&](int i) { return d[i].clear_start; });
-    const long long local = u - d[q].clear_start;
+    const int q = find_req(nreq, u, [&](int i) { return s_first[i]; });
+    const long long local = u - s_first[q];
+    const AdmitDesc& a = d[q];
     u32x4 v = {0u, 0u, 0u, 0u};
-    if (d[q].ident_off >= 0) {
-      const long long o = local * 16 - d[q].ident_off;
-      const long long np = d[q].Np;
-      if (o >= 0 && o < np * np) {
-        const long long i = o / np, j0 = o % np;
-        if (i < d[q].n && i >= j0 && i < j0 + 16) {
+    const long long ident = a.ident_off;
+    if (ident >= 0) {
+      const long long o = local * 16 - ident;
+      const unsigned np = (unsigned)a.Np;
+      if (o >= 0 && o < (long long)np * np) {
+        const unsigned i = (unsigned)o / np, j0 = (unsigned)o - i * np;
+        if ((int)i < a.n && i >= j0 && i < j0 + 16) {
           const int t = (int)(i - j0);
           v[t >> 2] |= 1u << (8 * (t & 3));
         }
       }
     }
-    *(u32x4*)(d[q].base + local * 16) = v;
-    if (local == 0 && d[q].ones) *d[q].ones = 0ull;
+    *(u32x4*)(a.base + local * 16) = v;
+    if (local == 0 && a.ones) *a.ones = 0ull;
   }
 }
 
 // Scatter every request's edges (as k_scatter_edges).  A wave whose lanes all
 // hold edges of one request adds its distinct-edge count with one atomic.
 __global__ void __launch_bounds__(256) k_admit_scatter(const AdmitDesc* __restrict__ d, int nreq, long long total) {
+  extern __shared__ long long s_first[];  // nreq entries: each request's first edge
+  for (int i = threadIdx.x; i < nreq; i += 256) s_first[i] = d[i].edge_start;
+  __syncthreads();
   for (long long e0 = (long long)blockIdx.x * 256; e0 < total; e0 += (long long)gridDim.x * 256) {
     const long long e = e0 + threadIdx.x;
     int q = -1, c = 0;
     if (e < total) {
-      q = find_req(nreq, e, [&](int i) { return d[i].edge_start; });
+      q = find_req(nreq, e, [&](int i) { return s_first[i]; });
       const AdmitDesc& a = d[q];
       const long long k = e - a.edge_start;
       const int i = a.edges[2 * k], j = a.edges[2 * k + 1];
@@ -198,17 +209,18 @@ __global__ void __launch_bounds__(256) k_admit_scatter(const AdmitDesc* __restri
 
 hipError_t launch_admit(const AdmitDesc* d, int nreq, long long total_units, long long total_edges, hipStream_t s) {
   if (nreq <= 0) return hipSuccess;
+  if (nreq > kRing) return hipErrorInvalidValue;  // the LDS copy of the requests' starts (32 KB at most)
   if (total_units > 0) {
     const long long blocks = (total_units + 255) / 256;
-    hipLaunchKernelGGL(k_admit_clear, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, d, nreq,
-                       total_units);
+    hipLaunchKernelGGL(k_admit_clear, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256),
+                       (size_t)nreq * sizeof(long long), s, d, nreq, total_units);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (total_edges > 0) {
     const long long blocks = (total_edges + 255) / 256;
-    hipLaunchKernelGGL(k_admit_scatter, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256), 0, s, d, nreq,
-                       total_edges);
+    hipLaunchKernelGGL(k_admit_scatter, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(256),
+                       (size_t)nreq * sizeof(long long), s, d, nreq, total_edges);
     return hipGetLastError();
   }
   return hipSuccess;
