@@ -1379,18 +1379,31 @@ struct DmaPanels {
 // `pre` for the next tile, whose slice 0 is then already in flight.
 // tid is threadIdx.x (a persistent caller passes it through an opaque move
 // each tile, so that nothing derived from it is kept live across tiles).
-template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE>
+// SK: the stream-K part of a symmetric product (k_nt_dma_sk): only the K
+// slices sk->kb .. sk->ke - 1 of the tile, finished by dma_epilogue_sk.
+struct SkTile {
+  int t;       // upper-triangle tile index
+  int kb, ke;  // K slices of this part
+  int my, nc;  // this workgroup's contributor index, contributors of the tile
+};
+template <class K, class Op>
+__device__ int dma_epilogue_sk(const NTParams& p, const SkParams& q, const typename Op::Acc (&acc)[K::FM][K::FN],
+                               uint8_t* et, int row0, int col0, int wm, int wn, int lane, int tid, const SkTile& sk,
+                               bool diag_tile);
+template <int BM, int BN, int WM, int WN, int KB, class Op, int NSTAGE, bool SK = false>
 __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, uint8_t* smem, int tid,
-                                            bool pre = false, DmaPanels next = DmaPanels()) {
+                                            bool pre = false, DmaPanels next = DmaPanels(),
+                                            const SkTile* sk = nullptr, const SkParams* skq = nullptr) {
   typedef DmaKernel<BM, BN, WM, WN, KB, Op, NSTAGE> K;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / K::WAVES_N, wn = wave % K::WAVES_N;
   const int row0 = tm * BM, col0 = tn * BN;
   const int64_t ldb = p.ld * K::NIB / 2;
-  const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb;
-  const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb;
-  const int nk = (int)(ldb / KB);
+  const int kb = SK ? sk->kb : 0;
+  const uint8_t* Xg = (const uint8_t*)p.X + (int64_t)row0 * ldb + (int64_t)kb * KB;
+  const uint8_t* Yg = (const uint8_t*)p.Y + (int64_t)col0 * ldb + (int64_t)kb * KB;
+  const int nk = SK ? sk->ke - kb : (int)(ldb / KB);
 
   // per-lane source address of DMA instruction j of this wave in panels
   // (Xb, Yb) of row pitch lb
@@ -1551,7 +1564,9 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
   }
 
   int cnt = 0;
-  if constexpr (K::SWAPPED) {
+  if constexpr (SK) {
+    cnt = dma_epilogue_sk<K, Op>(p, *skq, acc, smem, row0, col0, wm, wn, lane, tid, *sk, tm == tn);
+  } else if constexpr (K::SWAPPED) {
     uint8_t* et = prefetch ? smem + K::STAGE_BYTES : smem;
     cnt = p.add ? dma_epilogue_swapped<K, Op, true>(p, acc, et, row0, col0, wm, wn, lane, tid)
                 : dma_epilogue_swapped<K, Op, false>(p, acc, et, row0, col0, wm, wn, lane, tid);
@@ -1660,6 +1675,168 @@ k_nt_dma(NTParams p) {
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
     pre = nt_dma_tile<BM, BN, WM, WN, KB, Op, NSTAGE>(p, tm, tn, smem, tid, pre, next);
   }
+}
+
+// Epilogue of a stream-K part (k_nt_dma_sk).  The 0/1 segments are packed as
+// in dma_epilogue_swapped.  A tile with several contributors: every one
+// stores its segments in its scratch slot with write-through stores, waits
+// for them, and counts itself in tile_cnt[t]; the last to arrive ORs in the
+// other slots (device-scope loads), clears the counter and finishes the tile:
+// identity on the diagonal tile, count, stores of the tile and (off the
+// diagonal) of its mirror image.  Returns the ones it adds to the model
+// size (an off-diagonal tile counts for its mirror too).
+template <class K, class Op>
+__device__ int dma_epilogue_sk(const NTParams& p, const SkParams& q, const typename Op::Acc (&acc)[K::FM][K::FN],
+                               uint8_t* et, int row0, int col0, int wm, int wn, int lane, int tid, const SkTile& sk,
+                               bool diag_tile) {
+  static_assert(K::FR == 16 && Op::NI == 4 && __is_same(typename Op::Acc, v4i), "int8 16 x 16 fragments");
+  constexpr int BM = K::WAVES_M * K::FM * K::FR, BN = K::WAVES_N * K::FN * K::FR;
+  static_assert(BM == 256 && BN == 256, "65536-byte slots");
+  constexpr int NSEG = K::FM * (K::FN / 4);
+  auto seg_row = [&](int e) { return wm * (K::FM * 16) + 16 * (e / (K::FN / 4)) + (lane & 15); };
+  auto seg_col = [&](int e) { return wn * (K::FN * 16) + 16 * (4 * (e % (K::FN / 4)) + (lane >> 4)); };
+  u32x4 vs[NSEG];
+#pragma unroll
+  for (int i = 0; i < K::FM; ++i) {
+#pragma unroll
+    for (int qq = 0; qq < K::FN / 4; ++qq) {
+      unsigned P[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) P[t] = pack_nz4<Op>(acc[i][4 * qq + t]);
+      const auto s01 = __builtin_amdgcn_permlane16_swap(P[0], P[1], false, false);
+      const auto s23 = __builtin_amdgcn_permlane16_swap(P[2], P[3], false, false);
+      const auto s02 = __builtin_amdgcn_permlane32_swap(s01[0], s23[0], false, false);
+      const auto s13 = __builtin_amdgcn_permlane32_swap(s01[1], s23[1], false, false);
+      vs[i * (K::FN / 4) + qq] = u32x4{s02[0], s13[0], s02[1], s13[1]};
+    }
+  }
+  if (sk.nc > 1) {
+    constexpr unsigned kSlot = BM * BN;
+    __shared__ int s_last;
+    const __amdgpu_buffer_rsrc_t mine = buffer_of(q.scratch + ((size_t)sk.t * q.maxc + sk.my) * kSlot, kSlot);
+#pragma unroll
+    for (int e = 0; e < NSEG; ++e) st_agent_x4(mine, seg_row(e) * BN + seg_col(e), vs[e]);
+    wait_stores();
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned before =
+          __hip_atomic_fetch_add(q.tile_cnt + sk.t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = before == (unsigned)(sk.nc - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return 0;
+    for (int k = 0; k < sk.nc; ++k) {
+      if (k == sk.my) continue;
+      const __amdgpu_buffer_rsrc_t other = buffer_of(q.scratch + ((size_t)sk.t * q.maxc + k) * kSlot, kSlot);
+#pragma unroll
+      for (int e = 0; e < NSEG; ++e)
+        vs[e] |= __builtin_amdgcn_raw_buffer_load_b128(other, seg_row(e) * BN + seg_col(e), 0, kCpolSc1);
+    }
+    if (tid == 0) st_agent(q.tile_cnt + sk.t, 0u);
+  }
+  uint8_t* outb = (uint8_t*)p.out;
+  const bool add_id = p.add_identity && diag_tile;
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < NSEG; ++e) {
+    const int lr = seg_row(e), lc = seg_col(e);
+    u32x4 v = vs[e];
+    if (add_id) v = with_diag(v, row0 + lr, col0 + lc, p.n_valid);
+    cnt += popc16(v);
+    *(u32x4*)(outb + (int64_t)(row0 + lr) * p.ld + col0 + lc) = v;
+    if (!diag_tile) *(u32x4*)(et + lr * BN + 16 * ((lc >> 4) ^ ep_swz(lr))) = v;
+  }
+  if (!diag_tile) {
+    // the mirror image: element (row0 + r, col0 + c) also at (col0 + c, row0 + r)
+    lds_barrier();
+    constexpr int RB = BM / 16, CB = BN / 4;
+    for (int blk = tid; blk < RB * CB; blk += K::NT) {
+      const int x = blk & 3, rb = (blk >> 2) % RB, w = (blk >> 2) / RB;
+      const int cb = 4 * w + x;
+      unsigned d[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int lr = 16 * rb + k;
+        d[k] = *(const unsigned*)(et + lr * BN + 16 * ((cb >> 2) ^ ep_swz(lr)) + 4 * x);
+      }
+      uint8_t* const trow = outb + (int64_t)(col0 + 4 * cb) * p.ld + row0 + 16 * rb;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const unsigned sel_lo = (unsigned)qq | ((unsigned)(4 + qq) << 8) | 0x0c0c0000u;
+        const unsigned sel_hi = 0x0c0cu | ((unsigned)qq << 16) | ((unsigned)(4 + qq) << 24);
+        u32x4 t;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          t[m] = __builtin_amdgcn_perm(d[4 * m + 1], d[4 * m], sel_lo) |
+                 __builtin_amdgcn_perm(d[4 * m + 3], d[4 * m + 2], sel_hi);
+        *(u32x4*)(trow + (int64_t)qq * p.ld) = t;
+      }
+    }
+  }
+  return diag_tile ? cnt : 2 * cnt;
+}
+
+// Stream-K product of a symmetric result (see SkParams): workgroup g takes the
+// K slices [g share, (g + 1) share) of the upper-triangle tiles laid end to
+// end (each tile nk = Np / 128 slices, tiles in row-major order), in XCD-
+// contiguous runs.  No workgroup waits for another.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
+k_nt_dma_sk(NTParams p, SkParams q) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (step_is_done(p)) return;
+  const int nk = (int)(p.ld / 128);
+  const long long U = (long long)q.tiles * nk;
+  const int g = xcd_logical(blockIdx.x, gridDim.x);
+  const long long u1 = min(U, (long long)(g + 1) * q.share);
+  for (long long u = (long long)g * q.share; u < u1;) {
+    SkTile sk;
+    sk.t = (int)(u / nk);
+    const long long t0 = (long long)sk.t * nk;
+    sk.kb = (int)(u - t0);
+    sk.ke = (int)min((long long)nk, u1 - t0);
+    const int first = (int)(t0 / q.share), last = (int)((t0 + nk - 1) / q.share);
+    sk.my = g - first;
+    sk.nc = last - first + 1;
+    int tm = 0, rem = sk.t;  // the t-th tile (tm, tn), tm <= tn, row by row
+    while (rem >= q.side - tm) {
+      rem -= q.side - tm;
+      ++tm;
+    }
+    __syncthreads();  // the previous part's epilogue is done with LDS
+    int tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2, true>(p, tm, tm + rem, smem, tid, false, DmaPanels(), &sk, &q);
+    u = t0 + sk.ke;
+  }
+}
+
+bool sk_supported(int prec, int cfg_id, int64_t Np) { return prec == P_I8 && cfg_id == 0 && Np >= 256 && Np % 256 == 0; }
+
+void sk_plan(int64_t Np, SkParams& q) {
+  const int nk = (int)(Np / 128);
+  q.side = (int)(Np / 256);
+  q.tiles = q.side * (q.side + 1) / 2;
+  const long long U = (long long)q.tiles * nk;
+  // an even deal over the compute units, but no part under 8 slices (or a
+  // whole tile) where there is little work
+  const long long even = (U + g_cus - 1) / g_cus;
+  const long long floor_share = nk < 8 ? nk : 8;
+  q.share = (int)(even > floor_share ? even : floor_share);
+  // a tile's nk slices meet at most (nk - 1) / share + 2 parts
+  q.maxc = (nk - 1) / q.share + 2;
+}
+
+size_t sk_scratch_bytes(const SkParams& q) {
+  return (size_t)q.tiles * q.maxc * 65536 + ((size_t)q.tiles * sizeof(unsigned) + 255) / 256 * 256;
+}
+
+hipError_t launch_nt_sym_sk(const NTParams& p, const SkParams& q, hipStream_t s) {
+  typedef DmaKernel<256, 256, 64, 64, 128, OpI8, 2> K;
+  if (p.ld % 256 || p.ld / 256 != q.side || q.share < 1 || !q.scratch || !q.tile_cnt) return hipErrorInvalidValue;
+  const long long U = (long long)q.tiles * (p.ld / 128);
+  const int grid = (int)((U + q.share - 1) / q.share);
+  hipLaunchKernelGGL(k_nt_dma_sk, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, p, q);
+  return hipGetLastError();
 }
 
 // Grouped serving step with the direct-to-LDS 256 x 256 tiles (requests with
@@ -1823,6 +2000,9 @@ hipError_t bool_kernels_init() {
   g_cus = cus >= 8 ? cus / 8 * 8 : 8;
   if ((e = hipFuncSetAttribute((const void*)k_group_dma, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)group_dma_lds())) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_nt_dma_sk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES)) != hipSuccess)
     return e;
   if ((e = init_op<OpI8>()) != hipSuccess) return e;
   if ((e = init_op<OpF32>()) != hipSuccess) return e;

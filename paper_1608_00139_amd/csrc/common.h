@@ -144,6 +144,32 @@ struct TileCfg {
 };
 
 hipError_t launch_nt_step(int prec, int cfg_id, const NTParams& p, hipStream_t s);
+
+// Stream-K split of a product whose result is symmetric (the same-generation
+// S' = [I + T P^T]): only the tiles tm <= tn of the 256 x 256 int8 tiling are
+// computed, their tiles x (Np / 128) K slices dealt to the workgroups in runs
+// of `share` slices, so that every compute unit gets the same number of
+// slices.  A tile split over several workgroups is finished by the last of
+// them to arrive: each stores its partial 0/1 tile in scratch slot
+// (t * maxc + contributor) with write-through stores and counts itself in
+// tile_cnt[t]; the last ORs the others' partials (device-scope loads), adds
+// the identity, counts, writes the tile and its mirror image and clears
+// tile_cnt[t] for the next launch.  tile_cnt starts at zero.
+struct SkParams {
+  uint8_t* scratch;    // tiles * maxc slots of 65536 bytes
+  unsigned* tile_cnt;  // [tiles] arrivals, zero between launches
+  int side;            // tiles per side, Np / 256
+  int tiles;           // side (side + 1) / 2
+  int share;           // K slices per workgroup
+  int maxc;            // slots per tile (contributors at most)
+};
+// Whether the split applies (int8 operands, the direct-to-LDS configuration,
+// Np a multiple of 256), the plan for Np, and the scratch it needs (slots,
+// then the counters).
+bool sk_supported(int prec, int cfg_id, int64_t Np);
+void sk_plan(int64_t Np, SkParams& q);
+size_t sk_scratch_bytes(const SkParams& q);
+hipError_t launch_nt_sym_sk(const NTParams& p, const SkParams& q, hipStream_t s);
 TileCfg nt_config(int prec, int cfg_id);
 int choose_nt_config(int prec, int64_t n);
 int nt_config_count(int prec);  // cfg ids are 0 .. count - 1

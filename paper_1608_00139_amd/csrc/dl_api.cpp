@@ -228,6 +228,15 @@ class Fix {
       DL_HIP(launch_ingest(prec_, A_, lda_, (int)n_, (int)Np_, nullptr, nullptr, Yop_, nullptr, 0, nullptr, s_));
       DL_HIP(launch_identity(prec_, S_[1], (int)Np_, (int)n_, s_));
       DL_HIP(launch_ring_set(sl_.ring, 1, (unsigned long long)n_, s_));
+      // S' is symmetric: its product runs on the upper-triangle tiles only,
+      // split stream-K over the compute units (scratch after the operands)
+      if (sk_supported(prec_, cfg_, Np_)) {
+        sk_plan(Np_, skq_);
+        skq_.scratch = sl_.ws + 4 * matT;
+        skq_.tile_cnt = (unsigned*)(skq_.scratch + (size_t)skq_.tiles * skq_.maxc * 65536);
+        DL_HIP(hipMemsetAsync(skq_.tile_cnt, 0, (size_t)skq_.tiles * sizeof(unsigned), s_));
+        use_sk_ = true;
+      }
     }
     // When the caller's R has exactly the layout of an int8 iterate (no
     // padding, row stride Np, not transposed), it serves as iterate buffer
@@ -330,7 +339,10 @@ class Fix {
         tm_.end(ev);
         p.X = Tmp_; p.Y = Yop_; p.add_identity = 1;
         p.out = S_[cur]; p.outT = nullptr; p.count = 1; p.check = 0;
-        DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
+        if (use_sk_)
+          DL_HIP(launch_nt_sym_sk(p, skq_, s_));
+        else
+          DL_HIP(launch_nt_step(prec_, cfg_, p, s_));
       }
     }
     const int64_t upto = s0_ + cnt - 1;
@@ -388,6 +400,8 @@ class Fix {
   int chunk_ = 0;
   bool done_ = false;
   bool r_is_s0_ = false;  // the caller's R is iterate buffer S[0]
+  bool use_sk_ = false;   // same generation: S' by the stream-K symmetric product
+  SkParams skq_{};
 };
 
 // The plain series at small Np as one cooperative launch (k_fix_small): the
@@ -486,7 +500,12 @@ int run_fixpoints(dl_ctx* c, int mode, int count, int64_t n, const uint8_t* cons
     return DL_OK;
   }
   const int64_t Np = padded_size_for(prec, n);
-  const size_t need = fix_ws_bytes(prec, Np);
+  size_t need = fix_ws_bytes(prec, Np);
+  if (mode == M_SG && sk_supported(prec, pick_config(c, prec, Np), Np)) {
+    SkParams q{};
+    sk_plan(Np, q);
+    need += sk_scratch_bytes(q);  // the stream-K scratch of S' (Fix::start)
+  }
   // the plain series takes the whole-fixpoint kernel where it applies unless
   // the caller set another configuration for this size (an entry recorded
   // by dl_tune names the fastest product kernel, which this path does not use)

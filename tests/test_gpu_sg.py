@@ -77,3 +77,42 @@ def test_config_forest_n4096(dl):
         assert np.array_equal(got, got.T)
     p = dlgen.to_dense(n, dlgen.forest_edges(n, 0))
     _check(dl, p, "fp4", "cfg4096 fp4")
+
+
+@pytest.mark.parametrize("n", [100, 600, 1024, 1280, 2000])
+def test_symmetric_stream_k_product(dl, n):
+    """S' = [I + T P^T] is symmetric: with int8 operands and the direct-to-LDS
+    configuration only its upper-triangle tiles are computed, their K slices
+    dealt evenly over the workgroups (stream-K), a tile split over several
+    workgroups finished by the last of them to arrive, and the lower tiles
+    written as mirror images.  At n = 1280 and 2000 tiles are split over two
+    or three workgroups; n = 100 and 600 are padded.  Forests and random
+    relations with self-loops, whole model and iteration count."""
+    for kind, p in (("forest", dlgen.to_dense(n, dlgen.forest_edges(n, 5))),
+                    ("er", dlgen.to_dense(n, dlgen.er_edges(n, 1.2 / n, 6, self_loops=True)))):
+        ctx = dl.Context(0)
+        ctx.set_tuning("i8", n, 0)
+        announce("sg stream-k", kind, n)
+        s, iters = dl.dl_sg(dev(p), prec="i8", ctx=ctx)
+        ref, _, it_ref, _ = oracle.sg_seminaive(p)
+        mism = int((host(s) != ref).sum())
+        ctx.close()
+        assert mism == 0 and iters == it_ref, (kind, n, mism, iters, it_ref)
+
+
+def test_symmetric_stream_k_per_step(dl):
+    """Every iterate of the stream-K same-generation series at n = 1280 (tiles
+    split over workgroups; the partial-tile counters must be back at zero after
+    each product) equals the oracle's, with the model sizes."""
+    n = 1280
+    p = dlgen.to_dense(n, dlgen.er_edges(n, 1.0 / n, 8, self_loops=True))
+    _, ones_ref, iters_ref, _ = oracle.sg_seminaive(p)
+    ctx = dl.Context(0)
+    ctx.set_tuning("i8", n, 0)
+    for k in range(0, iters_ref + 2):
+        announce("sg stream-k steps", k)
+        res = dl.dl_sg_steps(dev(p), k, prec="i8", ctx=ctx)
+        assert np.array_equal(host(res.R), oracle.sg_seminaive(p, maxsteps=k)[0]), k
+        assert res.steps == min(k, iters_ref)
+        assert res.ones == list(ones_ref[: res.steps + 1])
+    ctx.close()
