@@ -79,7 +79,7 @@ def test_config_forest_n4096(dl):
     _check(dl, p, "fp4", "cfg4096 fp4")
 
 
-@pytest.mark.parametrize("n", [100, 600, 1024, 1280, 2000])
+@pytest.mark.parametrize("n", [100, 600, 1024, 1280, 2000, 3000])
 def test_symmetric_stream_k_product(dl, n):
     """S' = [I + T P^T] is symmetric: with int8 operands and the direct-to-LDS
     configuration only its upper-triangle tiles are computed, their K slices
@@ -116,3 +116,12 @@ def test_symmetric_stream_k_per_step(dl):
         assert res.steps == min(k, iters_ref)
         assert res.ones == list(ones_ref[: res.steps + 1])
     ctx.close()
+
+
+def test_symmetric_stream_k_n8192(dl):
+    """The stream-K S' product at N = 8192 (528 upper-triangle tiles, 132 K
+    slices per workgroup, tiles split over two workgroups), a random forest,
+    by the size rule's configuration."""
+    n = 8192
+    p = dlgen.to_dense(n, dlgen.forest_edges(n, 2))
+    _check(dl, p, "i8", "stream-k n8192")
