@@ -143,9 +143,9 @@ int dl_tc_noalloc(int64_t n, const uint8_t* A, int64_t lda, uint8_t* R, int64_t 
  * S' = min1(I + T P^T); thresholding the intermediate keeps the zero
  * pattern of P S P^T.  prec: any dl_prec.  S' is symmetric: with int8 on the
  * large tiles (n rounded up to 256 at least 4096 by the size rule, or tile
- * configuration 0) only
- * its upper-triangle tiles are computed and then mirrored, and the context's
- * workspace also holds that product's partial tiles (27 MB at n = 4096). */
+ * configuration 0) only its upper-triangle tiles are computed and then
+ * mirrored, and the context's workspace also holds that product's partial
+ * tiles (27 MB at n = 4096). */
 int dl_sg(dl_ctx* ctx, int64_t n, const uint8_t* P, int64_t ldp, uint8_t* S, int64_t lds,
           int prec, int32_t* iters, void* stream);
 
