@@ -235,6 +235,10 @@ static hipError_t dgemm(const GemmArgs& g, hipStream_t s) {
 // that one resident update workgroup leaves free on a compute unit.
 constexpr int PB = 2;
 __global__ void __launch_bounds__(1024) k_block_inverse(const double* W, int64_t ld, double* Dinv) {
+  // the next panel's inverse shares its compute unit with a trailing-update
+  // workgroup and is the longer chain in the late panels: its waves issue
+  // first (0.2-0.3 ms per N = 8192 solve)
+  __builtin_amdgcn_s_setprio(3);
   __shared__ __attribute__((aligned(16))) double rowbuf[2][PB][NB];
   __shared__ double colbuf[2][PB][NB];
   const int t = threadIdx.x;
