@@ -1637,10 +1637,11 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
 #pragma unroll
       for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
       // a global (not flat) atomic: a flat one would first wait for the
-      // prefetched slice, whose LDS writes it might alias
+      // prefetched slice, whose LDS writes it might alias; count 2: the tile
+      // stands for its mirror image too
       if (t)
-        __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)(p.ones + (p.step % kRing)), t,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)(p.ones + (p.step % kRing)),
+                               t * (unsigned long long)p.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   return prefetch;
@@ -1860,22 +1861,38 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     }
     return __builtin_amdgcn_readfirstlane(lo);
   };
+  // tile (tm, tn) of a request's local index: row-major over all tiles, or
+  // over the tiles tm <= tn of a symmetric product
+  auto coords = [](int local, int nt, int sym, int& tm, int& tn) {
+    if (!sym) {
+      tm = local / nt;
+      tn = local % nt;
+      return;
+    }
+    tm = 0;
+    while (local >= nt - tm) {
+      local -= nt - tm;
+      ++tm;
+    }
+    tn = tm + local;
+  };
   bool pre = false;  // this tile's first slice is in flight already
   int item = xcd_logical(blockIdx.x, gridDim.x);
   int cur = item < total_tiles ? find(item, 0) : 0;  // the items of a workgroup only grow
   for (; item < total_tiles; item += gridDim.x) {
     const GroupDesc& g = desc[cur];
-    const int local = item - g.tile_start;
-    const int tiles_n = g.Np / 256;
+    int tm, tn;
+    coords(item - g.tile_start, g.Np / 256, g.sym, tm, tn);
     DmaPanels next;
     int nxt = cur;
     if (item + (int)gridDim.x < total_tiles) {
       nxt = find(item + gridDim.x, cur);
       const GroupDesc& h = desc[nxt];
-      const int nl = item + gridDim.x - h.tile_start, nt = h.Np / 256;
+      int tm2, tn2;
+      coords(item + gridDim.x - h.tile_start, h.Np / 256, h.sym, tm2, tn2);
       next.ldb = h.Np;
-      next.X = (const uint8_t*)h.X + (int64_t)(nl / nt) * 256 * h.Np;
-      next.Y = (const uint8_t*)h.Y + (int64_t)(nl % nt) * 256 * h.Np;
+      next.X = (const uint8_t*)h.X + (int64_t)tm2 * 256 * h.Np;
+      next.Y = (const uint8_t*)h.Y + (int64_t)tn2 * 256 * h.Np;
     }
     NTParams p{};
     p.X = g.X;
@@ -1890,11 +1907,16 @@ k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.outT = g.outT;
     p.ones = g.cnt;
     p.count = g.cnt != nullptr;
+    if (g.sym && tm != tn) {  // the mirror image goes to out as well (it holds no identity)
+      p.outT = g.out;
+      p.outT_ident = 0;
+      p.count *= 2;
+    }
     p.step = 0;
     __syncthreads();  // the previous tile's epilogue is done with LDS
     int tid;
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
-    pre = nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, local / tiles_n, local % tiles_n, smem, tid, pre, next);
+    pre = nt_dma_tile<256, 256, 64, 64, 128, OpI8, 2>(p, tm, tn, smem, tid, pre, next);
     cur = nxt;
   }
 }

@@ -72,6 +72,9 @@ struct GroupDesc {
   int add_identity;
   int outT_ident;  // outT = out^T + I (see NTParams)
   int tile_start;  // first work-list index of this request
+  int sym;         // the result is symmetric (same generation's S'): only the
+                   // tiles tm <= tn are listed, each off-diagonal one also
+                   // written mirrored into out and counted twice
 };
 
 // One request of a grouped admission (serving): clear its buffers, write the

@@ -507,10 +507,13 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
       g.add_identity = 1;
       g.out = r.b[1 + cur];
       g.cnt = cnt + i;
+      // S' is symmetric: on the 256 tiles only tm <= tn, mirrored
+      g.sym = li == 2 ? 1 : 0;
       r.icomp = t;
       r.iphase = 0;
     }
-    tiles[li] += (int)((r.Np / r.tile) * (r.Np / r.tile));
+    const int tside = (int)(r.Np / r.tile);
+    tiles[li] += g.sym ? tside * (tside + 1) / 2 : tside * tside;
     rd.items.push_back(it);
     ++fill[li];
   }
