@@ -539,7 +539,8 @@ __device__ __forceinline__ void nt_tile(const NTParams& p, int row0, int col0,
       unsigned long long t = 0;
 #pragma unroll
       for (int w = 0; w < K::NWAVES; ++w) t += (unsigned long long)red[w];
-      if (t) atomicAdd(cnt_dst, t);
+      // count 2: a tile of a symmetric product stands for its mirror image too
+      if (t) atomicAdd(cnt_dst, p.count > 1 ? t * (unsigned long long)p.count : t);
     }
   }
 }
@@ -1084,9 +1085,20 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
       else hi = mid - 1;
     }
     const GroupDesc& g = desc[lo];
-    const int local = item - g.tile_start;
+    int local = item - g.tile_start;
     const int tiles_n = g.Np / T;
-    const int tm = local / tiles_n, tn = local % tiles_n;
+    int tm, tn;
+    if (!g.sym) {
+      tm = local / tiles_n;
+      tn = local % tiles_n;
+    } else {  // the tiles tm <= tn, row by row
+      tm = 0;
+      while (local >= tiles_n - tm) {
+        local -= tiles_n - tm;
+        ++tm;
+      }
+      tn = tm + local;
+    }
     NTParams p{};
     p.X = g.X;
     p.Y = g.Y;
@@ -1098,6 +1110,11 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
     p.n_valid = g.n_valid;
     p.out = g.out;
     p.outT = g.outT;
+    if (g.sym && tm != tn) {  // the mirror image goes to out as well (it holds no identity)
+      p.outT = g.out;
+      p.outT_ident = 0;
+      p.count = 2;
+    }
     __syncthreads();  // the previous tile's epilogue is done with LDS
     int tid;  // re-derived per tile: nothing computed from it stays live across tiles
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));

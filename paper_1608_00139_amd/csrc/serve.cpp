@@ -507,8 +507,8 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
       g.add_identity = 1;
       g.out = r.b[1 + cur];
       g.cnt = cnt + i;
-      // S' is symmetric: on the 256 tiles only tm <= tn, mirrored
-      g.sym = li == 2 ? 1 : 0;
+      // S' is symmetric: only the tiles tm <= tn, mirrored
+      g.sym = 1;
       r.icomp = t;
       r.iphase = 0;
     }
