@@ -1533,11 +1533,23 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
       }
   };
   if constexpr (SPLIT) {
-    // prologue: slice 0 (already in flight when the previous tile fetched it)
-    if (!pre) issue(0);
-    wait_vmcnt<0>();
+    // prologue: slice 0 (already in flight when the previous tile fetched
+    // it).  A prefetched slice 0 means slot 1 is free already -- the
+    // caller's barrier retired the previous epilogue's LDS use -- so slice 1
+    // goes out before the wait, and its fetch overlaps the drain of the
+    // previous tile's stores (which the wait for slice 0 includes): 3%
+    // faster at N = 8192, four tiles per workgroup
+    if (!pre) {
+      issue(0);
+      wait_vmcnt<0>();
+    } else if (1 < nk) {
+      issue(1);
+      wait_vmcnt<K::DMA_PER_WAVE>();
+    } else {
+      wait_vmcnt<0>();
+    }
     __builtin_amdgcn_s_barrier();
-    if (1 < nk) issue(1);
+    if (!pre && 1 < nk) issue(1);
     for (int kt = 0; kt < nk; ++kt) {
       const uint8_t* xs = smem + (kt & 1) * K::STAGE_BYTES;
       FragA fa0, fa1;
@@ -1557,18 +1569,23 @@ __device__ __forceinline__ bool nt_dma_tile(const NTParams& p, int tm, int tn, u
       products(fa1, fb1, 0, K::FN);
     }
   } else {
-  // prologue: NSTAGE - 1 slices in flight (slice 0 may be in flight already)
+  // prologue: NSTAGE - 1 slices in flight (slice 0 may be in flight already;
+  // then, with two slots, slot 1 is free and slice 1 goes out at once, as in
+  // the split loop)
 #pragma unroll
   for (int s0 = 0; s0 < NSTAGE - 1; ++s0)
     if (s0 < nk && !(pre && s0 == 0)) issue(s0);
+  const bool early1 = NSTAGE == 2 && pre && 1 < nk;
+  if (early1) issue(1);
   for (int kt = 0; kt < nk; ++kt) {
     // this wave's DMA for slice kt has landed once at most the later
     // slices' instructions are outstanding; the barrier extends that to
     // every wave, and also retires all reads of the slot refilled below
-    if (kt + NSTAGE - 2 < nk) wait_vmcnt<(NSTAGE - 2) * K::DMA_PER_WAVE>();
+    if (kt == 0 && early1) wait_vmcnt<K::DMA_PER_WAVE>();
+    else if (kt + NSTAGE - 2 < nk) wait_vmcnt<(NSTAGE - 2) * K::DMA_PER_WAVE>();
     else wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (kt + NSTAGE - 1 < nk) issue(kt + NSTAGE - 1);
+    if (kt + NSTAGE - 1 < nk && !(kt == 0 && early1)) issue(kt + NSTAGE - 1);
     if (prefetch && kt == nk - 1) issue_next0();
     compute(kt % NSTAGE);
   }
