@@ -1073,10 +1073,13 @@ static hipError_t launch_fix_small_op(FixSmallParams p, hipStream_t s) {
 // tiles of one request, which read the same operand panels, share an L2.
 // T x T tiles, four waves of (T/2) x (T/2): 64 for small requests, 128 for
 // the others (four times the work per tile, twice the operand reuse).
+// dyn_total: the live tile count after k_group_upload skipped the products of
+// finished requests (their descriptors then hold no tiles), or null.
 template <int T>
 __global__ void __launch_bounds__(256)
-k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
+k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles, const int* __restrict__ dyn_total) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (dyn_total) total_tiles = min(total_tiles, *dyn_total);
   for (int item = xcd_logical(blockIdx.x, gridDim.x); item < total_tiles; item += gridDim.x) {
     int lo = 0, hi = nreq - 1;  // last request whose first tile is <= item
     while (lo < hi) {
@@ -1122,20 +1125,24 @@ k_group_step(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
   }
 }
 
-__global__ void k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles);
+__global__ void k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles,
+                            const int* __restrict__ dyn_total);
 size_t group_dma_lds();
 
-hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s) {
+hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s,
+                             const int* dyn_total) {
   if (nreq <= 0 || total_tiles <= 0) return hipSuccess;
   if (nreq > kMaxGroupRequests) return hipErrorInvalidValue;
   if (tile == 64) {
     typedef NTKernel<64, 64, 32, 32, 64, OpI8, 2, 1> K;
-    hipLaunchKernelGGL(k_group_step<64>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+    hipLaunchKernelGGL(k_group_step<64>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles,
+                       dyn_total);
   } else if (tile == 128) {
     typedef NTKernel<128, 128, 64, 64, 64, OpI8, 2, 1> K;
-    hipLaunchKernelGGL(k_group_step<128>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles);
+    hipLaunchKernelGGL(k_group_step<128>, dim3(grid), dim3(K::NT), K::LDS_BYTES, s, desc, nreq, total_tiles,
+                       dyn_total);
   } else if (tile == 256) {
-    hipLaunchKernelGGL(k_group_dma, dim3(grid), dim3(1024), group_dma_lds(), s, desc, nreq, total_tiles);
+    hipLaunchKernelGGL(k_group_dma, dim3(grid), dim3(1024), group_dma_lds(), s, desc, nreq, total_tiles, dyn_total);
   } else {
     return hipErrorInvalidValue;
   }
@@ -1879,8 +1886,9 @@ hipError_t launch_nt_sym_sk(const NTParams& p, const SkParams& q, hipStream_t s)
 // lists as k_group_step does, fetching each next tile's first K slice while
 // it finishes the current one.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(1, 4)))
-k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles) {
+k_group_dma(const GroupDesc* __restrict__ desc, int nreq, int total_tiles, const int* __restrict__ dyn_total) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  if (dyn_total) total_tiles = min(total_tiles, *dyn_total);  // see k_group_step
   // every request's first tile, in LDS: the search for a tile's request
   // takes LDS reads instead of a chain of dependent global loads
   int* first = (int*)(smem + DmaKernel<256, 256, 64, 64, 128, OpI8, 2>::LDS_BYTES);

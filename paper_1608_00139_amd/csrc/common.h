@@ -75,6 +75,19 @@ struct GroupDesc {
   int sym;         // the result is symmetric (same generation's S'): only the
                    // tiles tm <= tn are listed, each off-diagonal one also
                    // written mirrored into out and counted twice
+  // Skip test of a product issued before the previous round's model sizes
+  // were read back: the request finished in that round exactly when its
+  // cumulative counter *chk equals chk_val, and then this product gets no
+  // tiles (see k_group_upload).  chk null: never skipped.
+  const unsigned long long* chk;
+  unsigned long long chk_val;
+};
+
+// The tile lists of one serving round, in descriptor order: segment k holds
+// descriptors [begin[k], begin[k + 1]) of tile size tile[k] (begin[3] = all).
+struct GroupLists {
+  int begin[4];
+  int tile[3];
 };
 
 // One request of a grouped admission (serving): clear its buffers, write the
@@ -214,6 +227,14 @@ hipError_t measure_peak(int kind, int* sink, double* ops_per_s, hipStream_t s, c
 // tile: 64, 128 or 256 (every request of the list has Np a multiple of it);
 // at most kMaxGroupRequests requests per launch
 constexpr int kMaxGroupRequests = kRing;
-hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s);
+// dyn_total (device int, may be null): the live tile count written by
+// k_group_upload; total_tiles is then the bound the grid was sized for.
+hipError_t launch_group_step(int tile, const GroupDesc* desc, int nreq, int total_tiles, int grid, hipStream_t s,
+                             const int* dyn_total = nullptr);
+// Copy a round's descriptors from src (a device mapping of host memory) to
+// dst and renumber the tiles of each segment over the products that are not
+// skipped (GroupDesc::chk); totals[k] receives segment k's live tile count.
+hipError_t launch_group_upload(const GroupDesc* src, GroupDesc* dst, const GroupLists& lists, int* totals,
+                               hipStream_t s);
 
 }  // namespace dl

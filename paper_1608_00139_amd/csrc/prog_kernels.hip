@@ -243,6 +243,95 @@ hipError_t launch_publish(const unsigned long long* src, unsigned long long* dst
   return hipGetLastError();
 }
 
+// A serving round's descriptor upload (in place of a k_publish of them),
+// compacting its tile lists: a product issued before the previous round's
+// model sizes were read back, of a request that finished in that round
+// (*chk == chk_val), gets no tiles, and the other products' tiles are
+// renumbered without gaps, so that the persistent launches deal only live
+// tiles and stay balanced.  A descriptor without tiles keeps its place: its
+// tile_start equals the next one's, and the grouped kernels' search (the last
+// request whose first tile is <= the item) passes over it.  One workgroup;
+// thread q handles descriptors [q c, q c + c), c = ceil(all / 1024) <= 4.
+constexpr int kUploadThreads = 1024;
+constexpr int kUploadPerThread = (kMaxGroupRequests + kUploadThreads - 1) / kUploadThreads;
+
+__global__ void __launch_bounds__(kUploadThreads)
+k_group_upload(const GroupDesc* __restrict__ src, GroupDesc* __restrict__ dst, GroupLists L, int* __restrict__ totals) {
+  __shared__ int s_wave[kUploadThreads / 64];
+  __shared__ int s_base[4];
+  const int nall = L.begin[3];
+  const int q = threadIdx.x, lane = q & 63, w = q >> 6;
+  const int c = (nall + kUploadThreads - 1) / kUploadThreads;
+  const int i0 = min(q * c, nall), i1 = min(i0 + c, nall);
+  auto segment = [&](int i) { return i < L.begin[1] ? 0 : (i < L.begin[2] ? 1 : 2); };
+  int live[kUploadPerThread];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < kUploadPerThread; ++j) {
+    const int i = i0 + j;
+    live[j] = 0;
+    if (i < i1) {
+      const GroupDesc g = src[i];
+      const int side = g.Np / L.tile[segment(i)];
+      const int tiles = g.sym ? side * (side + 1) / 2 : side * side;
+      live[j] = (g.chk != nullptr && *g.chk == g.chk_val) ? 0 : tiles;
+      dst[i] = g;  // tile_start is rewritten below (same thread, same address: in order)
+      sum += live[j];
+    }
+  }
+  // exclusive prefix of the per-thread sums: a scan in each wave, then the
+  // totals of the waves before
+  int incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) s_wave[w] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int x = 0; x < kUploadThreads / 64; ++x) {
+    const int v = s_wave[x];
+    before += x < w ? v : 0;
+    total += v;
+  }
+  const int excl = before + incl - sum;
+  // the prefix at each segment's first descriptor, from the thread holding it
+  for (int k = 0; k < 4; ++k) {
+    const int first = L.begin[k];
+    if (first >= nall) {
+      if (q == 0) s_base[k] = total;
+    } else if (first >= i0 && first < i1) {
+      int v = excl;
+#pragma unroll
+      for (int j = 0; j < kUploadPerThread; ++j) v += (i0 + j < first) ? live[j] : 0;
+      s_base[k] = v;
+    }
+  }
+  __syncthreads();
+  int run = excl;
+#pragma unroll
+  for (int j = 0; j < kUploadPerThread; ++j) {
+    const int i = i0 + j;
+    if (i < i1) {
+      dst[i].tile_start = run - s_base[segment(i)];
+      run += live[j];
+    }
+  }
+  if (q < 3) totals[q] = s_base[q + 1] - s_base[q];
+}
+
+hipError_t launch_group_upload(const GroupDesc* src, GroupDesc* dst, const GroupLists& L, int* totals, hipStream_t s) {
+  const int nall = L.begin[3];
+  if (nall <= 0) return hipSuccess;
+  if (nall > kMaxGroupRequests || L.begin[0] != 0 || L.begin[1] < 0 || L.begin[1] > L.begin[2] ||
+      L.begin[2] > L.begin[3] || !src || !dst || !totals)
+    return hipErrorInvalidValue;
+  for (int k = 0; k < 3; ++k)
+    if (L.tile[k] != 64 && L.tile[k] != 128 && L.tile[k] != 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_group_upload, dim3(1), dim3(kUploadThreads), 0, s, src, dst, L, totals);
+  return hipGetLastError();
+}
+
 // M[i][j] = a pseudo-random bit (density 1/2) for i, j < n, 0 in the padding
 // up to Np; bits from the "lowbias32" integer hash (C. Wellons) of the
 // element index mixed with the seed.

@@ -21,8 +21,11 @@
 // enqueues the next round before it waits for the one already on the device,
 // so the host's bookkeeping between rounds overlaps the device's products.
 // The next round is built before the current one's model sizes are known: a
-// request that finishes in round k has its round k + 1 product computed and
-// ignored (it writes only the buffer that does not hold the model).  Each
+// request that may finish in round k still gets a round k + 1 product, with a
+// test the device evaluates once round k is done (its counter against the
+// value that means "model size repeated"); k_group_upload then gives that
+// product no tiles, so finished requests cost the round nothing (their
+// product would write only the buffer that does not hold the model).  Each
 // round has its own counter, descriptor and read-back set (two sets
 // alternate); a round's entries carry the request's admission number, so a
 // slot fetched and reused meanwhile is not confused with its previous
@@ -121,6 +124,7 @@ struct dl_batch {
   GroupDesc* h_desc = nullptr;  // pinned host descriptors, same layout (coherent, device-mapped:
                                 // a kernel moves them, see move_words)
   GroupDesc* h_desc_dev = nullptr;  // device mapping of h_desc
+  int* d_tot = nullptr;             // per set: live tiles of the three lists (k_group_upload)
   unsigned long long* d_cnt = nullptr;  // per set: round counters [max], then admission counters [max]
   unsigned long long* h_cnt = nullptr;  // pinned copy, same layout (coherent, device-mapped)
   unsigned long long* h_cnt_dev = nullptr;  // device mapping of h_cnt
@@ -241,6 +245,8 @@ int dl_batch_create(dl_ctx* ctx, int device, size_t pool_bytes, int max_active, 
   b->free_list[0] = pool_bytes;
   if ((e = hipMalloc(&b->d_desc, sizeof(GroupDesc) * 2 * max_active)) != hipSuccess)
     return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
+  if ((e = hipMalloc(&b->d_tot, sizeof(int) * 8)) != hipSuccess)
+    return fail_destroy(bfail(DL_ENOMEM, "descriptor allocation failed"));
   // host buffers the device reads or writes directly (k_publish moves them;
   // runtime copies left a gap of ~10 us before each in the kernel trace)
   constexpr unsigned kMapped = hipHostMallocMapped | hipHostMallocCoherent;
@@ -280,6 +286,7 @@ int dl_batch_destroy(dl_batch* b) {
   (void)hipDeviceSynchronize();
   if (b->pool) (void)hipFree(b->pool);
   if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_tot) (void)hipFree(b->d_tot);
   if (b->h_desc) (void)hipHostFree(b->h_desc);
   if (b->d_cnt) (void)hipFree(b->d_cnt);
   if (b->h_cnt) (void)hipHostFree(b->h_cnt);
@@ -461,6 +468,14 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
   // the set's descriptors); the counter of a request's product is
   // d_cnt[set][slot]
   unsigned long long* cnt = b->d_cnt + (size_t)set * 2 * M;
+  // With the previous round still in flight, a request's product there may
+  // turn out to be its last: its counter in that round's set then equals the
+  // value read after that set's previous round plus the model size the host
+  // already holds for the iterate before.  The device tests this before this
+  // round's products (k_group_upload).
+  const bool ahead = b->lookahead && b->inflight.live && b->inflight.seq == b->rounds_issued - 1;
+  const unsigned long long* pcnt = b->d_cnt + (size_t)(set ^ 1) * 2 * M;
+  const unsigned long long* plast = b->last.data() + (size_t)(set ^ 1) * M;
   GroupDesc* hset = b->h_desc + (size_t)set * M;
   GroupDesc* dset = b->d_desc + (size_t)set * M;
   int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};
@@ -485,6 +500,12 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
     RoundItem it{i, r.gen, r.kind, r.iphase, r.icomp + 1, r.admit_count};
     r.admit_count = false;
     const int64_t t = r.icomp + 1;  // iterate this product belongs to
+    // the previous round made iterate t - 1 (closure, or same generation's
+    // S' before a T product) and the host knows the size of iterate t - 2
+    if (ahead && (r.kind == 0 || r.iphase == 0) && t >= 3 && (int64_t)r.ones.size() > t - 2) {
+      g.chk = pcnt + i;
+      g.chk_val = plast[i] + (unsigned long long)r.ones[(size_t)(t - 2)];
+    }
     if (r.kind == 0) {
       const int prev = (int)((t - 1) & 1), cur = (int)(t & 1);
       g.X = r.b[2 * prev];
@@ -518,11 +539,15 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
     ++fill[li];
   }
   if (rd.items.empty()) return DL_OK;
-  BHIP(move_words(b->h_desc_dev + (size_t)set * M, dset, sizeof(GroupDesc) * rd.items.size(), s));
+  // descriptor segments in array order: the 256-, 128- and 64-tile lists
+  GroupLists gl{{0, na[2], na[2] + na[1], na[2] + na[1] + na[0]}, {256, 128, 64}};
+  int* tot = b->d_tot + 4 * set;
+  BHIP(launch_group_upload(b->h_desc_dev + (size_t)set * M, dset, gl, tot, s));
   for (int li = kLists - 1; li >= 0; --li) {  // the largest tiles first
     if (!na[li]) continue;
     const int grid = li == 2 ? b->cus : b->grid;  // the 256 tiles take a whole CU each
-    BHIP(launch_group_step(64 << li, dset + first[li], na[li], tiles[li], std::min(grid, tiles[li]), s));
+    BHIP(launch_group_step(64 << li, dset + first[li], na[li], tiles[li], std::min(grid, tiles[li]), s,
+                           tot + (2 - li)));
   }
   // round and admission counters of the set in one read-back
   BHIP(move_words(cnt, b->h_cnt_dev + (size_t)set * 2 * M, sizeof(unsigned long long) * 2 * M, s));
