@@ -363,9 +363,10 @@ int dl_batch_step(dl_batch* batch, int32_t* active, int32_t* finished, void* str
 
 /* Rounds of look-ahead of dl_batch_step: 0 (the default: each call runs and
  * reads back one round) or 1 (each call enqueues one round and reads back
- * the previous one; a request that finishes in a round has its next product
- * computed and discarded, and pool memory freed by dl_batch_fetch returns to
- * the pool after the round in flight completes).  Setting 0 while a round is
+ * the previous one; a request that finishes in a round still has its next
+ * product enqueued, which the device skips once it sees from that round's
+ * counters that the request finished, and pool memory freed by dl_batch_fetch
+ * returns to the pool after the round in flight completes).  Setting 0 while a round is
  * in flight is DL_EINVAL: call dl_batch_step until *active is 0 first. */
 int dl_batch_set_lookahead(dl_batch* batch, int32_t rounds);
 
