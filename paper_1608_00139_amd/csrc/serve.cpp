@@ -396,13 +396,16 @@ int dl_batch_submit_edges(dl_batch* b, int kind, int64_t n, const int32_t* edges
   return admit(b, kind, n, tag, slot_out, nullptr, true,
                [&](int64_t nn, int64_t Np, int8_t* base, int8_t* M, int8_t* MT, unsigned long long* ones) -> int {
                  const long long mb = (long long)Np * Np;
-                 // the request's buffers are contiguous from base: closure
-                 // clears R0, R0T, R1 and R1T = I (before the edges' A^T);
-                 // same generation P, S0 and S1 = I
+                 // the request's buffers are contiguous from base (closure:
+                 // R0, R0T, R1, R1T; same generation: P, S0, S1, T).  Closure
+                 // clears R1 and R1T = I (before the edges' A^T), the first
+                 // iterate: the first product writes every byte of R0 and R0T.
+                 // Same generation clears P, S0 and S1 = I (S0, which its
+                 // first S' product writes whole, lies between the other two).
                  AdmitDesc a{};
-                 a.base = base;
-                 a.clear_units = (kind == 0 ? 4 : 3) * mb / 16;
-                 a.ident_off = kind == 0 ? 3 * mb : 2 * mb;
+                 a.base = kind == 0 ? base + 2 * mb : base;
+                 a.clear_units = (kind == 0 ? 2 : 3) * mb / 16;
+                 a.ident_off = kind == 0 ? mb : 2 * mb;
                  a.M = M;
                  a.M2 = nullptr;
                  a.MT = MT;
