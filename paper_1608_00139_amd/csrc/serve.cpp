@@ -146,6 +146,7 @@ struct dl_batch {
   int grid = 1024;  // persistent workgroups of the 64 and 128 tile launches
   int cus = 256;
   std::vector<int> finished;  // slots finished and not yet polled
+  std::vector<int> order;     // issue_round's scratch: active slots, largest first
 };
 
 namespace {
@@ -482,17 +483,24 @@ int issue_round(dl_batch* b, hipStream_t s, Round& rd) {
   GroupDesc* hset = b->h_desc + (size_t)set * M;
   GroupDesc* dset = b->d_desc + (size_t)set * M;
   int na[kLists] = {0, 0, 0}, tiles[kLists] = {0, 0, 0};
+  // the largest requests first: a tile's time grows with Np (its K loop),
+  // and the persistent workgroups take the list in passes, so the short
+  // tiles of small requests fill the last pass (largest-first scheduling)
+  std::vector<int>& order = b->order;
+  order.clear();
   for (int i = 0; i < M; ++i) {
     const Req& r = b->req[i];
-    if (r.used && !r.done) ++na[list_of(r.tile)];
+    if (!r.used || r.done) continue;
+    ++na[list_of(r.tile)];
+    order.push_back(i);
   }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->req[x].Np > b->req[y].Np; });
   int first[kLists], fill[kLists] = {0, 0, 0};
   first[2] = 0;
   first[1] = na[2];
   first[0] = na[2] + na[1];
-  for (int i = 0; i < M; ++i) {
+  for (const int i : order) {
     Req& r = b->req[i];
-    if (!r.used || r.done) continue;
     const int li = list_of(r.tile);
     GroupDesc& g = hset[first[li] + fill[li]];
     std::memset(&g, 0, sizeof g);
