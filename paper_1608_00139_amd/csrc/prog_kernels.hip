@@ -1,9 +1,10 @@
 // prog_kernels.hip -- elementwise kernels on int8 0/1 matrices (Np x Np,
 // row-major, zero padded): disjunction of relations, complement for negated
 // atoms (Sec. 8), transposed copies for converse atoms, the column-sum norm,
-// the edge-list scatter that admits serving requests, the fixpoint driver's
-// read-back into pinned host memory, and the pseudo-random relation the tile
-// autotuner times its candidates on.
+// the edge-list scatter that admits serving requests, the serving rounds'
+// descriptor upload (which drops the products of finished requests), the
+// fixpoint driver's read-back into pinned host memory, and the pseudo-random
+// relation the tile autotuner times its candidates on.
 #include "common.h"
 
 namespace dl {
